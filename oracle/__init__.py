@@ -1,0 +1,231 @@
+"""FP64 CPU oracle for A-term IDG gridding/degridding -- TEST INFRASTRUCTURE.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product library never does, and the
+two share no code: this wrapper drives ``oracle.cpp`` (plain C++17, double
+precision, OpenMP over subgrids or directions) through ctypes on numpy arrays.
+
+Pins (tests/test_oracle_*.py) tie every function here to something other than
+itself: lattice identities against the brute-force direct DFT, a Dirichlet
+closed form, numpy FFTs and scipy's Bessel function for special cases, and the
+adjoint identity between gridding and degridding.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "oracle.cpp")
+LIB = os.path.join(HERE, "liboracle.so")
+
+SUBGRID_DTYPE = np.dtype([
+    ("bl", "<i4"), ("st1", "<i4"), ("st2", "<i4"), ("t0", "<i4"), ("nt", "<i4"),
+    ("c0", "<i4"), ("nc", "<i4"), ("U0", "<i4"), ("V0", "<i4"), ("wlayer", "<i4"),
+    ("aint", "<i4"), ("reserved", "<i4"), ("w0", "<f8"), ("vis_offset", "<i8")])
+assert SUBGRID_DTYPE.itemsize == 64
+
+CHECK_CODES = {
+    0: "ok", 1: "bad baseline/stations", 2: "sub-table outside table", 3: "A-term interval",
+    4: "window off grid", 5: "uv beyond (L-K)/2", 6: "w beyond layer", 7: "visibility twice",
+    8: "placeable visibility missing", 9: "inconsistent layer w0", 10: "vis_offset",
+}
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.cpp into liboracle.so (g++, -O2, OpenMP)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["g++", "-std=c++17", "-O2", "-fopenmp", "-fPIC", "-shared",
+                               "-Wall", "-Wextra", "-o", tmp, SRC])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build(force=True)
+        _lib = ctypes.CDLL(LIB)
+        _lib.oracle_partition.restype = ctypes.c_int64
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c128(a):
+    return np.ascontiguousarray(a, dtype=np.complex128)
+
+
+def _geo(wl):
+    return [ctypes.c_int(wl.grid_size), ctypes.c_int(wl.subgrid_size),
+            ctypes.c_int(wl.kernel_support), ctypes.c_double(wl.pixel_scale)]
+
+
+def _obs(wl):
+    return [ctypes.c_int(wl.n_stations), ctypes.c_int(wl.n_baselines), ctypes.c_int(wl.n_times),
+            ctypes.c_int(wl.n_chans), ctypes.c_int(wl.aterm_interval)]
+
+
+def _arrs(wl):
+    bl = np.ascontiguousarray(wl.baselines, np.int32)
+    uvw = np.ascontiguousarray(wl.uvw, np.float64)
+    f = np.ascontiguousarray(wl.freqs, np.float64)
+    return bl, uvw, f
+
+
+def taper(L: int, K: int, beta: float = 0.0) -> np.ndarray:
+    T = np.zeros((L, L))
+    lib().oracle_taper(ctypes.c_int(L), ctypes.c_int(K), ctypes.c_double(beta), _p(T))
+    return T
+
+
+def partition(wl, w_step: float) -> np.ndarray:
+    bl, uvw, f = _arrs(wl)
+    cap = max(1024, wl.n_vis)
+    out = np.zeros(cap, SUBGRID_DTYPE)
+    n = lib().oracle_partition(*_geo(wl), *_obs(wl), _p(bl), _p(uvw), _p(f),
+                               ctypes.c_double(w_step), _p(out), ctypes.c_int64(cap))
+    assert n >= 0
+    return out[:n].copy()
+
+
+def check_partition(wl, table: np.ndarray, w_step: float) -> tuple[int, int]:
+    bl, uvw, f = _arrs(wl)
+    table = np.ascontiguousarray(table, SUBGRID_DTYPE)
+    bad = ctypes.c_int64(0)
+    code = lib().oracle_check_partition(*_geo(wl), *_obs(wl), _p(bl), _p(uvw), _p(f),
+                                        ctypes.c_double(w_step), _p(table),
+                                        ctypes.c_int64(table.shape[0]), ctypes.byref(bad))
+    return int(code), int(bad.value)
+
+
+def n_layers(table: np.ndarray) -> int:
+    return int(table["wlayer"].max()) + 1 if table.shape[0] else 1
+
+
+def layer_w(table: np.ndarray) -> np.ndarray:
+    W = n_layers(table)
+    w = np.zeros(W)
+    for j in range(W):
+        sel = table["wlayer"] == j
+        if sel.any():
+            w[j] = table["w0"][sel][0]
+    return w
+
+
+def grid_subgrid(wl, vis: np.ndarray, sg, stage: int, beta: float = 0.0) -> np.ndarray:
+    bl, uvw, f = _arrs(wl)
+    A = _c128(wl.aterms)
+    vis = _c128(vis)
+    sgr = np.ascontiguousarray(np.asarray(sg, SUBGRID_DTYPE).reshape(1))
+    L = wl.subgrid_size
+    out = np.zeros((4, L, L), np.complex128)
+    lib().oracle_grid_subgrid(*_geo(wl), ctypes.c_double(beta), *_obs(wl),
+                              ctypes.c_int(A.shape[0]), _p(bl), _p(uvw), _p(f), _p(A), _p(vis),
+                              _p(sgr), ctypes.c_int(stage), _p(out))
+    return out
+
+
+def grid(wl, vis: np.ndarray, table: np.ndarray, W: int | None = None, beta: float = 0.0,
+         nthreads: int = 0, out: np.ndarray | None = None) -> np.ndarray:
+    bl, uvw, f = _arrs(wl)
+    A = _c128(wl.aterms)
+    vis = _c128(vis)
+    table = np.ascontiguousarray(table, SUBGRID_DTYPE)
+    W = n_layers(table) if W is None else W
+    N = wl.grid_size
+    G = np.zeros((W, 4, N, N), np.complex128) if out is None else out
+    rc = lib().oracle_grid(*_geo(wl), ctypes.c_double(beta), *_obs(wl), ctypes.c_int(A.shape[0]),
+                           _p(bl), _p(uvw), _p(f), _p(A), _p(vis), _p(table),
+                           ctypes.c_int64(table.shape[0]), ctypes.c_int(W), _p(G),
+                           ctypes.c_int(nthreads))
+    assert rc == 0
+    return G
+
+
+def degrid(wl, G: np.ndarray, table: np.ndarray, beta: float = 0.0, nthreads: int = 0) -> np.ndarray:
+    bl, uvw, f = _arrs(wl)
+    A = _c128(wl.aterms)
+    G = _c128(G)
+    table = np.ascontiguousarray(table, SUBGRID_DTYPE)
+    V = np.zeros((wl.n_baselines, wl.n_times, wl.n_chans, 4), np.complex128)
+    rc = lib().oracle_degrid(*_geo(wl), ctypes.c_double(beta), *_obs(wl), ctypes.c_int(A.shape[0]),
+                             _p(bl), _p(uvw), _p(f), _p(A), _p(G), _p(table),
+                             ctypes.c_int64(table.shape[0]), ctypes.c_int(G.shape[0]), _p(V),
+                             ctypes.c_int(nthreads))
+    assert rc == 0
+    return V
+
+
+def direct_image(wl, vis: np.ndarray, l, m, xs=None, ys=None, mask=None, nthreads: int = 0) -> np.ndarray:
+    bl, uvw, f = _arrs(wl)
+    A = _c128(wl.aterms)
+    vis = _c128(vis)
+    l = np.ascontiguousarray(l, np.float64)
+    m = np.ascontiguousarray(m, np.float64)
+    n = l.shape[0]
+    xs = -np.ones(n, np.int32) if xs is None else np.ascontiguousarray(xs, np.int32)
+    ys = -np.ones(n, np.int32) if ys is None else np.ascontiguousarray(ys, np.int32)
+    mk = None if mask is None else np.ascontiguousarray(mask, np.uint8)
+    out = np.zeros((n, 4), np.complex128)
+    lib().oracle_direct_image(ctypes.c_int(wl.grid_size), ctypes.c_int(wl.subgrid_size),
+                              ctypes.c_double(wl.pixel_scale), *_obs(wl), ctypes.c_int(A.shape[0]),
+                              _p(bl), _p(uvw), _p(f), _p(A), _p(vis),
+                              None if mk is None else _p(mk), ctypes.c_int(n), _p(l), _p(m),
+                              _p(xs), _p(ys), _p(out), ctypes.c_int(nthreads))
+    return out
+
+
+def direct_predict(wl, l, m, B, xs=None, ys=None, nthreads: int = 0) -> np.ndarray:
+    bl, uvw, f = _arrs(wl)
+    A = _c128(wl.aterms)
+    l = np.ascontiguousarray(l, np.float64)
+    m = np.ascontiguousarray(m, np.float64)
+    n = l.shape[0]
+    xs = -np.ones(n, np.int32) if xs is None else np.ascontiguousarray(xs, np.int32)
+    ys = -np.ones(n, np.int32) if ys is None else np.ascontiguousarray(ys, np.int32)
+    B = _c128(B)
+    V = np.zeros((wl.n_baselines, wl.n_times, wl.n_chans, 4), np.complex128)
+    lib().oracle_direct_predict(ctypes.c_int(wl.grid_size), ctypes.c_int(wl.subgrid_size),
+                                ctypes.c_double(wl.pixel_scale), *_obs(wl),
+                                ctypes.c_int(A.shape[0]), _p(bl), _p(uvw), _p(f), _p(A),
+                                ctypes.c_int(n), _p(l), _p(m), _p(xs), _p(ys), _p(B), _p(V),
+                                ctypes.c_int(nthreads))
+    return V
+
+
+def layer_image_at(G_layer: np.ndarray, du: float, l, m, nthreads: int = 0) -> np.ndarray:
+    G = _c128(G_layer)
+    N = G.shape[-1]
+    l = np.ascontiguousarray(l, np.float64)
+    m = np.ascontiguousarray(m, np.float64)
+    out = np.zeros((l.shape[0], 4), np.complex128)
+    lib().oracle_layer_image_at(_p(G), ctypes.c_int(N), ctypes.c_double(du), ctypes.c_int(l.shape[0]),
+                                _p(l), _p(m), _p(out), ctypes.c_int(nthreads))
+    return out
+
+
+def coverage_mask(wl, table: np.ndarray) -> np.ndarray:
+    """1 for visibilities that belong to a subgrid of the table, else 0."""
+    mask = np.zeros((wl.n_baselines, wl.n_times, wl.n_chans), np.uint8)
+    for s in table:
+        mask[s["bl"], s["t0"]:s["t0"] + s["nt"], s["c0"]:s["c0"] + s["nc"]] = 1
+    return mask
+
+
+def lattice_dirs(wl, xs, ys):
+    """Direction cosines of subgrid-lattice pixels (xs, ys)."""
+    L = wl.subgrid_size
+    step = wl.fov / L
+    xs = np.asarray(xs, np.int32)
+    ys = np.asarray(ys, np.int32)
+    return (xs - L // 2) * step, (ys - L // 2) * step

@@ -1,0 +1,402 @@
+"""Pins of the FP64 oracle against facts fixed outside it.
+
+Each test ties an oracle function to the mathematics or a library routine, not to
+the oracle's own formulas:
+  * the Kaiser-Bessel taper against scipy's modified Bessel function;
+  * the centred subgrid DFT against numpy's FFT;
+  * gridding of one visibility against the Dirichlet-kernel closed form;
+  * direct imaging of on-cell visibilities against numpy's inverse FFT;
+  * IDG gridding against the direct A-term imaging equation at the subgrid
+    lattice directions, where the two agree exactly (Sec. 4.3: the method
+    interpolates between lattice samples and is exact at them);
+  * IDG degridding of lattice point sources against direct prediction (Eq. 1);
+  * the adjoint identity between gridding and degridding;
+  * Jones factorisation, linearity, permutation invariance, Hermitian symmetry
+    of the measurement equation (Sec. 2.4 footnote) and partition validity.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.special
+
+import synth
+
+C = 299792458.0
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+def inner(a, b):
+    return complex(np.vdot(np.ravel(a), np.ravel(b)))
+
+
+# ------------------------------------------------------------------ taper
+
+
+@pytest.mark.parametrize("L,K", [(32, 8), (64, 16), (96, 24), (16, 0)])
+def test_taper_matches_scipy_bessel(orc, L, K):
+    T = orc.taper(L, K)
+    beta = math.pi * K / 4.0
+    assert T[L // 2, L // 2] == pytest.approx(1.0, abs=1e-15)
+    # edge pixel x = 0: f = -1/2 so the Bessel argument is 0
+    assert T[L // 2, 0] == pytest.approx(1.0 / scipy.special.i0(beta), rel=1e-13)
+    assert T[0, 0] == pytest.approx(1.0 / scipy.special.i0(beta) ** 2, rel=1e-13)
+    # an interior point through scipy's i0
+    x, y = L // 4, 3 * L // 4 - 1
+    fx, fy = (x - L // 2) / L, (y - L // 2) / L
+    ref = (scipy.special.i0(beta * math.sqrt(1 - 4 * fx * fx)) *
+           scipy.special.i0(beta * math.sqrt(1 - 4 * fy * fy)) / scipy.special.i0(beta) ** 2)
+    assert T[y, x] == pytest.approx(ref, rel=1e-13)
+    assert np.allclose(T, T.T)
+
+
+def test_taper_main_lobe_width(orc):
+    """Fourier transform of the 1-D taper: its main lobe spans about +-K/4 cells."""
+    L, K = 96, 24
+    t = orc.taper(L, K)[L // 2]
+    over = 64
+    spec = np.abs(np.fft.fftshift(np.fft.fft(np.fft.ifftshift(np.pad(t, (L * over - L) // 2)))))
+    spec /= spec.max()
+    centre = spec.shape[0] // 2
+    first_min = centre + int(np.argmax(np.diff(spec[centre:]) > 0))
+    assert abs((first_min - centre) / over - K / 4) < 1.0
+
+
+# ------------------------------------------------------------------ single-visibility workloads
+
+
+def one_vis_workload(L=32, N=256, K=0, du_off=(3.0, -5.0), w=0.0, dl=None, f=150e6, n_st=2):
+    """One baseline, one time, one channel, at a chosen cell offset from grid centre + 10."""
+    dl = dl if dl is not None else math.radians(15.0) / N
+    fov = N * dl
+    du = 1.0 / fov
+    lam = C / f
+    gu = N // 2 + 10 + du_off[0]
+    gv = N // 2 - 7 + du_off[1]
+    uvw = np.array([[[(gu - N // 2) * du * lam, (gv - N // 2) * du * lam, w * lam]]])
+    A = np.zeros((1, n_st, L, L, 4), np.complex128)
+    A[..., 0] = A[..., 3] = 1.0
+    wl = synth.Workload("one", n_st, np.array([[0, 1]], np.int32), uvw, np.array([f]), N, L, K, dl,
+                        1, A)
+    return wl, gu, gv
+
+
+def single_table(orc, wl, U0, V0, w0=0.0):
+    t = np.zeros(1, orc.SUBGRID_DTYPE)
+    t[0] = (0, int(wl.baselines[0, 0]), int(wl.baselines[0, 1]), 0, 1, 0, 1, U0, V0, 0, 0, 0, w0, 0)
+    return t
+
+
+@pytest.mark.parametrize("frac", [(0.0, 0.0), (0.37, -0.21), (0.5, 0.25)])
+def test_gridding_one_visibility_is_dirichlet(orc, frac):
+    """T = 1 (K = 0), A = I, w_k = w0: the uv subgrid is the product of two
+    Dirichlet kernels D(z) = exp(-i pi z/L) sin(pi z)/sin(pi z/L), z = delta - (a - L/2)."""
+    L, N = 32, 256
+    wl, gu, gv = one_vis_workload(L=L, N=N, du_off=(3.0 + frac[0], -5.0 + frac[1]))
+    U0, V0 = N // 2 + 10, N // 2 - 7
+    V = np.zeros((1, 1, 1, 4), np.complex128)
+    V[..., 0] = 1.0
+    V[..., 3] = 2.0 - 1.0j
+    out = orc.grid_subgrid(wl, V, single_table(orc, wl, U0, V0)[0], stage=3)
+    du, dv = gu - U0, gv - V0
+
+    def D(z):
+        z = np.asarray(z, float)
+        with np.errstate(invalid="ignore", divide="ignore"):
+            val = np.exp(-1j * np.pi * z / L) * np.sin(np.pi * z) / np.sin(np.pi * z / L)
+        near = np.abs(np.sin(np.pi * z / L)) < 1e-12
+        return np.where(near, L * np.exp(-1j * np.pi * z / L) * np.cos(np.pi * z) /
+                        np.cos(np.pi * z / L), val)
+
+    a = np.arange(L) - L // 2
+    ref = D(dv - a)[:, None] * D(du - a)[None, :]
+    assert rel(out[0], ref) < 1e-12
+    assert rel(out[3], (2.0 - 1.0j) * ref) < 1e-12
+    assert np.abs(out[1]).max() == 0 and np.abs(out[2]).max() == 0
+    if frac == (0.0, 0.0):
+        assert abs(out[0][L // 2 - 5, L // 2 + 3] - L * L) < 1e-9
+
+
+def test_centred_subgrid_dft_matches_numpy_fft(orc):
+    wl = synth.config_tiny(11)
+    V = synth.random_vis((wl.n_baselines, wl.n_times, wl.n_chans), np.random.default_rng(1))
+    t = orc.partition(wl, 0.0)
+    for sg in t[:3]:
+        img = orc.grid_subgrid(wl, V, sg, stage=2)
+        uv = orc.grid_subgrid(wl, V, sg, stage=3)
+        ref = np.fft.fftshift(np.fft.fft2(np.fft.ifftshift(img, axes=(1, 2)), axes=(1, 2)), axes=(1, 2))
+        assert rel(uv, ref) < 1e-12
+
+
+# ------------------------------------------------------------------ direct imaging vs numpy FFT
+
+
+def test_direct_image_of_on_cell_visibilities_is_inverse_fft(orc):
+    """w = 0, A = I, every u_k on a grid cell: the direct image at image-pixel
+    centres is N^2 times the centred inverse FFT of the gridded visibilities."""
+    rng = np.random.default_rng(5)
+    N, L = 64, 16
+    dl = math.radians(20.0) / N
+    fov = N * dl
+    du = 1.0 / fov
+    f = 150e6
+    lam = C / f
+    nbl, nt = 12, 3
+    cells = rng.integers(-20, 21, (nbl, nt, 2))
+    uvw = np.zeros((nbl, nt, 3))
+    uvw[..., :2] = cells * du * lam
+    A = np.zeros((1, 8, L, L, 4), np.complex128)
+    A[..., 0] = A[..., 3] = 1.0
+    bl = np.array([[i % 7, i % 7 + 1] for i in range(nbl)], np.int32)
+    wl = synth.Workload("cells", 8, bl, uvw, np.array([f]), N, L, 0, dl, nt, A)
+    V = synth.random_vis((nbl, nt, 1), rng)
+    G = np.zeros((4, N, N), np.complex128)
+    for b in range(nbl):
+        for t in range(nt):
+            G[:, cells[b, t, 1] + N // 2, cells[b, t, 0] + N // 2] += V[b, t, 0]
+    img_fft = np.fft.fftshift(np.fft.ifft2(np.fft.ifftshift(G, axes=(1, 2)), axes=(1, 2)),
+                              axes=(1, 2)) * N * N
+    X = rng.integers(0, N, 40)
+    Y = rng.integers(0, N, 40)
+    l = (X - N // 2) * dl
+    m = (Y - N // 2) * dl
+    # exclude directions where n1 matters: w = 0 makes the w-term vanish anyway
+    img = orc.direct_image(wl, V, l, m)
+    ref = img_fft[:, Y, X].T
+    assert rel(img, ref) < 1e-12
+    lay = orc.layer_image_at(G, du, l, m)
+    assert rel(lay, ref) < 1e-12
+
+
+def test_direct_predict_phase_centre_and_adjoint(orc):
+    wl = synth.config_tiny(7)
+    L = wl.subgrid_size
+    rng = np.random.default_rng(2)
+    B = synth.random_vis((3,), rng)
+    xs = np.array([L // 2, 5, L - 3], np.int32)
+    ys = np.array([L // 2, 9, 4], np.int32)
+    l, m = orc.lattice_dirs(wl, xs, ys)
+    # a source at the phase centre has zero phase: V_k = A_p B A_q^H
+    V0 = orc.direct_predict(wl, l[:1], m[:1], B[:1], xs[:1], ys[:1])
+    for b in range(wl.n_baselines):
+        p, q = wl.baselines[b]
+        for t in range(wl.n_times):
+            i = t // wl.aterm_interval
+            Ap = wl.aterms[i, p, L // 2, L // 2].reshape(2, 2)
+            Aq = wl.aterms[i, q, L // 2, L // 2].reshape(2, 2)
+            ref = (Ap @ B[0].reshape(2, 2) @ Aq.conj().T).ravel()
+            assert np.allclose(V0[b, t], ref[None, :], rtol=1e-13, atol=1e-13)
+    # prediction and imaging are adjoint: <predict(B), V> = <B, image(V)>
+    Vr = synth.random_vis((wl.n_baselines, wl.n_times, wl.n_chans), rng)
+    P = orc.direct_predict(wl, l, m, B, xs, ys)
+    I = orc.direct_image(wl, Vr, l, m, xs, ys)
+    lhs, rhs = inner(P, Vr), inner(B, I)
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+def test_measurement_equation_hermitian_symmetry(orc):
+    """V(-u,-v,-w) = V(u,v,w)^H for Hermitian brightness and A = I (Sec. 2.4 footnote)."""
+    wl = synth.config_tiny(8)
+    wl.aterms[...] = 0
+    wl.aterms[..., 0] = wl.aterms[..., 3] = 1
+    src = synth.point_sources(5, wl.fov, 0.5, 5.0, np.random.default_rng(3))
+    V = orc.direct_predict(wl, src["l"], src["m"], src["B"])
+    wl2 = synth.Workload(**{**wl.__dict__, "uvw": -wl.uvw})
+    V2 = orc.direct_predict(wl2, src["l"], src["m"], src["B"])
+    VH = V.reshape(V.shape[:-1] + (2, 2)).conj().swapaxes(-1, -2).reshape(V.shape)
+    assert rel(V2, VH) < 1e-13
+
+
+# ------------------------------------------------------------------ lattice identities (P1, P2)
+
+
+def lattice_all(L):
+    ys, xs = np.mgrid[0:L, 0:L]
+    return xs.ravel().astype(np.int32), ys.ravel().astype(np.int32)
+
+
+def n1(l, m):
+    r2 = l * l + m * m
+    return -r2 / (1 + np.sqrt(1 - r2))
+
+
+CASES = [dict(seed=21), dict(seed=22, w_step=15.0), dict(seed=23, w_step=6.0, L=16, K=4, N=64),
+         dict(seed=24, n_t=7, aterm_interval=2, w_step=25.0)]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_gridding_exact_at_lattice_directions(orc, case):
+    """sum_j I_j(l_s, m_s) e^{2 pi i w0_j n1_s} = L^2 T(x_s, y_s) * direct_image(l_s, m_s)."""
+    case = dict(case)
+    w_step = case.pop("w_step", 0.0)
+    wl = synth.config_tiny(**case)
+    L = wl.subgrid_size
+    rng = np.random.default_rng(case["seed"])
+    V = synth.random_vis((wl.n_baselines, wl.n_times, wl.n_chans), rng)
+    table = orc.partition(wl, w_step)
+    assert orc.check_partition(wl, table, w_step) == (0, -1)
+    if w_step > 0:
+        assert orc.n_layers(table) >= 2
+    G = orc.grid(wl, V, table)
+    w0 = orc.layer_w(table)
+    xs, ys = lattice_all(L)
+    sel = rng.choice(xs.shape[0], 120, replace=False)
+    xs, ys = xs[sel], ys[sel]
+    l, m = orc.lattice_dirs(wl, xs, ys)
+    lhs = sum(orc.layer_image_at(G[j], 1.0 / wl.fov, l, m) * np.exp(2j * np.pi * w0[j] * n1(l, m))[:, None]
+              for j in range(G.shape[0]))
+    mask = orc.coverage_mask(wl, table)
+    T = orc.taper(L, wl.kernel_support)
+    rhs = L * L * T[ys, xs][:, None] * orc.direct_image(wl, V, l, m, xs, ys, mask=mask)
+    assert rel(lhs, rhs) < 1e-11
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_degridding_exact_for_lattice_sources(orc, case):
+    """G_j = sum_s B_s e^{-2 pi i [(g-N/2) du . (l_s, m_s) + w0_j n1_s]} / (L^2 T_s)
+    degrids to the direct prediction (Eq. 1) of those sources."""
+    case = dict(case)
+    w_step = case.pop("w_step", 0.0)
+    wl = synth.config_tiny(**case)
+    L, N = wl.subgrid_size, wl.grid_size
+    rng = np.random.default_rng(case["seed"] + 100)
+    src = synth.point_sources(4, wl.fov, 0.5, 5.0, rng, L=L, on_lattice=True)
+    table = orc.partition(wl, w_step)
+    w0 = orc.layer_w(table)
+    T = orc.taper(L, wl.kernel_support)
+    du = 1.0 / wl.fov
+    g = np.arange(N) - N // 2
+    G = np.zeros((len(w0), 4, N, N), np.complex128)
+    for s in range(4):
+        ramp = np.exp(-2j * np.pi * (g[None, :] * du * src["l"][s] + g[:, None] * du * src["m"][s]))
+        Ts = T[src["ys"][s], src["xs"][s]]
+        for j in range(len(w0)):
+            ph = np.exp(-2j * np.pi * w0[j] * n1(src["l"][s], src["m"][s]))
+            G[j] += (src["B"][s][:, None, None] / (L * L * Ts)) * (ramp * ph)[None]
+    V = orc.degrid(wl, G, table)
+    Vd = orc.direct_predict(wl, src["l"], src["m"], src["B"], src["xs"], src["ys"])
+    mask = orc.coverage_mask(wl, table).astype(bool)
+    assert mask.sum() > 0.8 * mask.size
+    assert rel(V[mask], Vd[mask]) < 1e-11
+    assert np.abs(V[~mask]).max(initial=0.0) == 0.0
+
+
+# ------------------------------------------------------------------ adjoint, linearity, Jones
+
+
+@pytest.mark.parametrize("seed,w_step", [(31, 0.0), (32, 10.0)])
+def test_adjoint_identity(orc, seed, w_step):
+    wl = synth.config_tiny(seed)
+    rng = np.random.default_rng(seed)
+    table = orc.partition(wl, w_step)
+    W = orc.n_layers(table)
+    V = synth.random_vis((wl.n_baselines, wl.n_times, wl.n_chans), rng)
+    G = synth.random_grid(W, wl.grid_size, rng)
+    lhs = inner(orc.grid(wl, V, table), G)
+    rhs = inner(V, orc.degrid(wl, G, table))
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+def test_linearity_and_order_invariance(orc):
+    wl = synth.config_tiny(41)
+    rng = np.random.default_rng(41)
+    table = orc.partition(wl, 0.0)
+    V1 = synth.random_vis((wl.n_baselines, wl.n_times, wl.n_chans), rng)
+    V2 = synth.random_vis((wl.n_baselines, wl.n_times, wl.n_chans), rng)
+    a, b = 0.3 - 1.2j, 2.0 + 0.5j
+    G12 = orc.grid(wl, a * V1 + b * V2, table)
+    assert rel(G12, a * orc.grid(wl, V1, table) + b * orc.grid(wl, V2, table)) < 1e-13
+    perm = rng.permutation(table.shape[0])
+    assert rel(orc.grid(wl, V1, table[perm]), orc.grid(wl, V1, table)) < 1e-13
+
+
+def test_direction_independent_jones_factor_out(orc):
+    """With A constant over the field, grid(V; A) = A_p^H grid(V; I) A_q cell by cell."""
+    wl = synth.config_tiny(51, n_st=2, n_t=3, aterm_interval=3)
+    rng = np.random.default_rng(51)
+    Ap = rng.standard_normal(4) + 1j * rng.standard_normal(4)
+    Aq = rng.standard_normal(4) + 1j * rng.standard_normal(4)
+    L = wl.subgrid_size
+    wl.aterms = np.zeros((1, 2, L, L, 4), np.complex128)
+    wl.aterms[0, 0] = Ap
+    wl.aterms[0, 1] = Aq
+    table = orc.partition(wl, 0.0)
+    V = synth.random_vis((1, wl.n_times, wl.n_chans), rng)
+    GA = orc.grid(wl, V, table)
+    wl.aterms[...] = 0
+    wl.aterms[..., 0] = wl.aterms[..., 3] = 1
+    GI = orc.grid(wl, V, table)
+    M = GI[0].transpose(1, 2, 0).reshape(wl.grid_size, wl.grid_size, 2, 2)
+    ref = Ap.reshape(2, 2).conj().T @ M @ Aq.reshape(2, 2)
+    assert rel(GA[0], ref.reshape(wl.grid_size, wl.grid_size, 4).transpose(2, 0, 1)) < 1e-13
+
+
+def test_phase_only_jones_adjoint_equals_inverse(orc):
+    """For A = e^{i phi} I the adjoint mode A^H equals the paper's A^{-1} (Eq. withw)."""
+    wl = synth.config_tiny(52, complex_jones=False)
+    A = wl.aterms.reshape(wl.aterms.shape[:-1] + (2, 2))
+    Ainv = np.linalg.inv(A)
+    AH = A.conj().swapaxes(-1, -2)
+    assert np.allclose(Ainv, AH, atol=1e-13)
+
+
+# ------------------------------------------------------------------ partition validity (P7)
+
+
+@pytest.mark.parametrize("seed,w_step", [(61, 0.0), (62, 12.0), (63, 5.0)])
+def test_oracle_partition_is_valid(orc, seed, w_step):
+    wl = synth.config_tiny(seed, n_st=7, n_t=9, n_c=8)
+    t = orc.partition(wl, w_step)
+    assert orc.check_partition(wl, t, w_step) == (0, -1)
+
+
+def test_checker_rejects_planted_mistakes(orc):
+    wl = synth.config_tiny(64, n_st=6, n_t=6, n_c=6)
+    good = orc.partition(wl, 10.0)
+    assert orc.check_partition(wl, good, 10.0)[0] == 0
+    multi = np.nonzero((good["nt"] > 1) | (good["nc"] > 1))[0]
+    assert multi.size
+
+    def bad(mut):
+        t = good.copy()
+        mut(t)
+        return orc.check_partition(wl, t, 10.0)[0]
+
+    def setf(field, fn):
+        def mut(t):
+            t[field][0] = fn(t[0])
+        return mut
+
+    assert bad(setf("st2", lambda r: r["st1"])) == 1
+    assert bad(setf("nc", lambda r: wl.n_chans + 1)) == 2
+    assert bad(setf("aint", lambda r: 5)) == 3
+    assert bad(setf("U0", lambda r: 3)) == 4
+    assert bad(setf("U0", lambda r: r["U0"] + wl.subgrid_size // 2)) == 5
+    assert bad(setf("w0", lambda r: r["w0"] + 3.0)) == 6
+    i = int(multi[0])
+
+    def shrink(t):
+        if t[i]["nc"] > 1:
+            t[i]["nc"] -= 1
+        else:
+            t[i]["nt"] -= 1
+    assert bad(shrink) == 8
+    assert bad(setf("vis_offset", lambda r: r["vis_offset"] + 1)) == 10
+    dup = np.concatenate([good, good[:1]])
+    assert orc.check_partition(wl, dup, 10.0)[0] == 7
+
+
+def test_excluded_visibilities_are_outside(orc):
+    """Visibilities within K/2 cells of the grid edge cannot be placed; the
+    partition leaves exactly those out and degridding returns zero for them."""
+    wl = synth.config_tiny(71, N=64, diameter_m=600.0)
+    t = orc.partition(wl, 0.0)
+    assert orc.check_partition(wl, t, 0.0)[0] == 0
+    mask = orc.coverage_mask(wl, t)
+    assert 0 < mask.sum() < mask.size
+    G = synth.random_grid(1, wl.grid_size, np.random.default_rng(1))
+    V = orc.degrid(wl, G, t)
+    assert np.abs(V[mask == 0]).max() == 0.0
