@@ -1,0 +1,184 @@
+/*
+ * aidg.h -- C ABI of the MI355X (gfx950) A-term image-domain gridding library.
+ *
+ * The library implements the hot path of image-domain gridding (IDG) with
+ * direction-, time- and baseline-dependent 2x2 Jones A-terms (Hodgson 2025,
+ * "That pesky A-term", arXiv:2502.17789, Sec. 2 and Sec. 3):
+ *
+ *   gridding   (Sec. 2.5, imaging steps 1-2):  for every subgrid p
+ *       S(x,y)  = sum_k V_k exp(+2 pi i phi_k(x,y))            (Sec. 2.4, Eq. withw)
+ *       S'(x,y) = T(x,y) A_p(x,y)^H S(x,y) A_q(x,y)            (Sec. 3.3, deferred A-term)
+ *       G_w[window of p] += centred forward DFT of S'          (Sec. 2.3, Eq. shiftback)
+ *   degridding (Sec. 2.5, prediction step 3), the exact adjoint:
+ *       S  = centred inverse DFT of G_w[window of p]           (splitter + inverse FFT)
+ *       S' = T A_p S A_q^H
+ *       V_k = sum_{x,y} S'(x,y) exp(-2 pi i phi_k(x,y))        (Eq. degridder)
+ *   phi_k(x,y) = (u_k - u0) l_x + (v_k - v0) m_y + (w_k - w0) (n - 1)   [turns]
+ *
+ * Geometry and conventions:
+ *   grid cell (gu, gv), 0 <= gu, gv < N, sits at u = (gu - N/2) du, du = 1/(N dl).
+ *   subgrid centre (U0, V0) is an integer cell; its window covers cells
+ *   U0 - L/2 .. U0 + L/2 - 1 (same for v) and must lie on the grid.
+ *   subgrid image pixel (x, y) sits at l = (x - L/2) N dl / L.
+ *   Visibility k = (baseline b = (p, q), timestep t, channel c):
+ *   u_k = uvw_m[b][t][0] f_c / c (metres to wavelengths), likewise v, w.
+ *   Polarisations are the 2x2 row-major Jones layout [[XX, XY], [YX, YY]];
+ *   V_pq = A_p B A_q^H.  Gridding applies A^H (the adjoint of degridding); for
+ *   unitary A (phase screens) this equals the paper's A^-1 of Eq. withw.
+ *   The taper is the separable Kaiser-Bessel window of Sec. 4.2,
+ *   T(x,y) = t(x) t(y), t(x) = I0(beta sqrt(1 - (2 (x - L/2)/L)^2)) / I0(beta).
+ *   Subgrid DFTs are unnormalised; all image-domain scaling is left to the caller.
+ *
+ * Array layouts (all C order; "c64" = interleaved float re/im, "c128" = double):
+ *   baselines  host   int32  [nbl][2]                  stations (p, q) of each baseline
+ *   uvw_m      host   double [nbl][nt][3]              metres
+ *   freqs_hz   host   double [nc]                      strictly increasing
+ *   aterms     device c64|c128 [n_int][n_st][L][L][4]  n_int = ceil(nt / aterm_interval),
+ *                                                      pixel [y][x], Jones row-major
+ *   vis        device c64|c128 [nbl][nt][nc][4]
+ *   grid       device c64|c128 [W][4][N][N]            W w-layers, u (gu) fastest
+ * c64 with precision AIDG_FP32, c128 with AIDG_FP64.
+ *
+ * Ownership: host arrays are read during the call that receives them and may be
+ * freed afterwards.  Device buffers passed to aidg_grid / aidg_degrid belong to
+ * the caller and must stay alive until the work queued on the given HIP stream
+ * has completed.  A plan owns its own device copies of the A-terms and its
+ * metadata, taper and workspace; aidg_plan_destroy frees them.
+ *
+ * Errors: every call returns an aidg_status; nothing throws across the ABI.
+ * aidg_last_error() returns a thread-local message describing the last non-OK
+ * status.  aidg_grid / aidg_degrid never allocate memory and never synchronise
+ * the host; they queue kernels on the given stream.  A plan must not be used by
+ * two host threads at once (AIDG_E_BUSY).
+ */
+#ifndef AIDG_H
+#define AIDG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define AIDG_ABI_VERSION 1
+
+typedef enum {
+  AIDG_OK = 0,
+  AIDG_E_INVALID = 1,     /* bad argument or geometry */
+  AIDG_E_NOMEM = 2,       /* host or device allocation failed */
+  AIDG_E_DEVICE = 3,      /* a HIP call failed */
+  AIDG_E_UNSUPPORTED = 4, /* valid request the GPU path does not implement (e.g. L) */
+  AIDG_E_RANGE = 5,       /* strict_range set and a visibility cannot be placed */
+  AIDG_E_BUSY = 6         /* plan already in use by another thread */
+} aidg_status;
+
+enum { AIDG_FP32 = 0, AIDG_FP64 = 1 };
+
+/* Imaging geometry and numerics of a plan. */
+typedef struct {
+  int32_t grid_size;       /* N: even, >= subgrid_size */
+  int32_t subgrid_size;    /* L: 32, 64 or 96 */
+  int32_t kernel_support;  /* K: even, 0 <= K < L; cells reserved for taper/w/A spread, both sides */
+  int32_t aterm_interval;  /* timesteps per A-term interval (Sec. 3.3), >= 1 */
+  double pixel_scale;      /* dl: image pixel size in direction cosines; FOV = N dl, FOV/sqrt(2) < 1 */
+  double w_step;           /* w-layer spacing in wavelengths (Sec. 2.4): > 0 explicit,
+                              0 automatic (2 w_max with w_max = K / (4 FOV rho),
+                              rho = max |grad n| over the lattice; one layer when K = 0),
+                              < 0 a single layer at w0 = 0 */
+  double taper_beta;       /* Kaiser-Bessel beta; 0 selects pi K / 4 */
+  int32_t precision;       /* AIDG_FP32 (FP32 phasors/accumulation, FP64 phase origins) or AIDG_FP64 */
+  int32_t reseed_channels; /* FP32 phasor recurrence re-seeded from FP64 every R channels; 0 = 32 */
+  int32_t strict_range;    /* 0: unplaceable visibilities are excluded (grid ignores them,
+                              degrid writes 0); 1: plan creation fails with AIDG_E_RANGE */
+  int32_t max_subgrid_vis; /* cap on visibilities per subgrid, 0 = 1024; larger caller
+                              sub-tables are split in time */
+  int64_t workspace_bytes; /* subgrid stack budget on the device; 0 = 2 GiB */
+} aidg_geometry;
+
+/* One subgrid: the rectangular sub-table [t0, t0+nt) x [c0, c0+nc) of one
+ * baseline's visibility table (Sec. 3.1), its integer centre cell, its w-layer
+ * and its A-term interval.  64 bytes. */
+typedef struct {
+  int32_t bl, st1, st2;   /* baseline index and its stations (p, q) */
+  int32_t t0, nt, c0, nc; /* sub-table */
+  int32_t U0, V0;         /* centre cell */
+  int32_t wlayer;         /* index into the plan's w-layers, 0 .. W-1 */
+  int32_t aint;           /* A-term interval = t0 / aterm_interval */
+  int32_t reserved;       /* 0 */
+  double w0;              /* w of the layer, wavelengths */
+  int64_t vis_offset;     /* flat index of visibility (bl, t0, c0) */
+} aidg_subgrid;
+
+typedef struct {
+  int64_t n_subgrids;      /* after splitting at max_subgrid_vis */
+  int64_t n_vis;           /* nbl * nt * nc */
+  int64_t n_excluded;      /* visibilities in no subgrid */
+  int32_t n_wlayers;       /* W */
+  int32_t subgrid_size;    /* L */
+  double w_step;           /* layer spacing used (0 for a single layer) */
+  int64_t device_bytes;    /* everything the plan holds on the device */
+  int64_t workspace_bytes; /* subgrid stack */
+  int64_t grid_bytes;      /* size of one grid for this plan, W * 4 * N * N * complex */
+  int64_t vis_bytes;       /* size of one visibility array */
+  int64_t n_batches;       /* kernel batches per aidg_grid / aidg_degrid call */
+  int64_t max_subgrid_vis; /* largest sub-table */
+} aidg_plan_info;
+
+typedef struct aidg_plan aidg_plan;
+
+/* Partition only (host, no device use): the library's sub-table partitioner of
+ * Sec. 3.1.  Each baseline's rows of one A-term interval are split at their first
+ * timestep into channel runs whose uv span comfortably fits (3/4 of L - K), and
+ * each run is then extended in time while every visibility stays within
+ * (L - K)/2 cells of an integer centre, in one w-layer, and under max_subgrid_vis.
+ * Writes up to cap records to out (may be NULL with cap 0), the count to *n_out
+ * and the layer spacing used to *w_step_out.  AIDG_E_INVALID if cap is too small
+ * (*n_out still receives the count). */
+aidg_status aidg_partition(const aidg_geometry* geo, int32_t n_stations, int32_t n_baselines,
+                           int32_t n_times, int32_t n_chans, const int32_t* baselines,
+                           const double* uvw_m, const double* freqs_hz, aidg_subgrid* out,
+                           int64_t cap, int64_t* n_out, double* w_step_out);
+
+/* Build a plan: validate the geometry, partition (or take the caller's table),
+ * upload metadata, taper and a copy of the A-terms on hip_stream, and allocate
+ * the workspace.  table/n_table: optional caller partition (NULL/0 to use the
+ * library's own); it must cover each visibility at most once and keep every
+ * window on the grid, and its wlayer indices must map to one w0 each.  The
+ * call synchronises hip_stream before returning. */
+aidg_status aidg_plan_create(const aidg_geometry* geo, int32_t n_stations, int32_t n_baselines,
+                             int32_t n_times, int32_t n_chans, const int32_t* baselines,
+                             const double* uvw_m, const double* freqs_hz, const void* aterms,
+                             const aidg_subgrid* table, int64_t n_table, void* hip_stream,
+                             aidg_plan** out);
+
+aidg_status aidg_plan_info_get(const aidg_plan* plan, aidg_plan_info* info);
+
+/* Copy the plan's subgrid table (after splitting) to host memory; cap records at most. */
+aidg_status aidg_plan_subgrids(const aidg_plan* plan, aidg_subgrid* out, int64_t cap);
+
+/* Copy the w of each layer (cap entries at most) to host memory. */
+aidg_status aidg_plan_wlayers(const aidg_plan* plan, double* w0, int32_t cap);
+
+/* Replace the plan's A-terms (device buffer, same layout and precision). */
+aidg_status aidg_plan_set_aterms(aidg_plan* plan, const void* aterms, void* hip_stream);
+
+/* Gridding: ACCUMULATE the plan's visibilities into grid (both device). */
+aidg_status aidg_grid(aidg_plan* plan, const void* vis, void* grid, void* hip_stream);
+
+/* Degridding: OVERWRITE vis_out with the prediction from grid (both device);
+ * visibilities that belong to no subgrid are set to zero. */
+aidg_status aidg_degrid(aidg_plan* plan, const void* grid, void* vis_out, void* hip_stream);
+
+void aidg_plan_destroy(aidg_plan* plan);
+
+/* Thread-local description of the last non-OK status ("" if none). */
+const char* aidg_last_error(void);
+
+int32_t aidg_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AIDG_H */

@@ -1,0 +1,76 @@
+// Internal declarations shared by the host plan code and the HIP kernels.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/aidg.h"
+
+namespace aidg {
+
+constexpr double kSpeedOfLight = 299792458.0;
+constexpr int kMaxSubgridVisDefault = 1024;
+constexpr int kReseedDefault = 32;
+constexpr int64_t kWorkspaceDefault = int64_t(2) << 30;
+
+// Per-subgrid record the kernels read (device copy of the partition).
+struct alignas(16) SubgridDev {
+  int32_t t0, nt, c0, nc;      // sub-table
+  int32_t U0, V0, wlayer, R;   // centre cell, layer, reseed interval (1: every channel)
+  int32_t ap, aq, bl, pad;     // A-term plane index (aint * n_st + station) of p and q
+  int64_t vis0;                // flat visibility index of (bl, t0, c0)
+  int64_t uvw0;                // flat uvw row index of (bl, t0)
+  double dfc;                  // channel spacing / c (s/m * Hz ... i.e. 1/m) for the recurrence
+  double w0;                   // layer w, wavelengths
+};
+static_assert(sizeof(SubgridDev) == 80, "SubgridDev layout");
+
+// Geometry after validation, with derived quantities.
+struct Geometry {
+  int N, L, K, aterm_interval, precision, R, strict, max_sg_vis;
+  double dl, fov, du, beta, w_step;
+  int64_t workspace;
+};
+
+// Host-side partition (library's own algorithm); table entries are aidg_subgrid.
+struct PartitionResult {
+  std::vector<aidg_subgrid> table;
+  std::vector<int64_t> excluded;  // flat visibility indices
+  double w_step = 0.0;            // 0: single layer
+  int64_t jmin = 0, jmax = 0;
+};
+
+aidg_status validate_geometry(const aidg_geometry* g, Geometry* out, std::string* err);
+double auto_w_step(const Geometry& g);
+aidg_status partition(const Geometry& g, int n_st, int nbl, int nt, int nc, const int32_t* baselines,
+                      const double* uvw, const double* freqs, PartitionResult* out, std::string* err);
+aidg_status adopt_table(const Geometry& g, int n_st, int nbl, int nt, int nc,
+                        const int32_t* baselines, const aidg_subgrid* table, int64_t n_table,
+                        PartitionResult* out, std::string* err);
+std::vector<aidg_subgrid> split_large(const std::vector<aidg_subgrid>& t, int max_vis, int nt_total,
+                                      int nc_total);
+void kaiser_bessel_taper(int L, double beta, std::vector<double>* T);
+
+// Kernel launch parameters common to all kernels of a plan.
+struct KernelArgs {
+  const SubgridDev* sg;     // device subgrid table
+  const double* uvw;        // device [nbl][nt][3] metres
+  const double* fc;         // device [nc] f / c
+  const void* aterms;       // device [n_int][n_st][L][L][4]
+  const void* taper;        // device [L][L] taper times (-1)^(x+y)
+  const void* twiddle;      // device [L] exp(-2 pi i k / L)
+  void* scratch;            // device subgrid stack [batch][4][L][L]
+  int nt_total, nc_total, N, pad;
+  double du;                // uv cell size, wavelengths
+  double lstep;             // FOV / L, subgrid lattice spacing in direction cosines
+};
+
+// Kernel launchers (kernels.hip).  Return a hipError_t as int.
+int launch_grid_batch(int L, int precision, const KernelArgs& a, int64_t sg_begin, int64_t n_sg,
+                      const void* vis, void* grid, void* stream);
+int launch_degrid_batch(int L, int precision, const KernelArgs& a, int64_t sg_begin, int64_t n_sg,
+                        const void* grid, void* vis, void* stream, int max_nv);
+int launch_zero_vis(int precision, const int64_t* idx, int64_t n, void* vis, void* stream);
+
+}  // namespace aidg

@@ -1,0 +1,412 @@
+// C ABI of the A-term IDG library: plan creation (host partition + device
+// upload), batched gridding/degridding launches and error reporting.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "aidg_internal.h"
+
+using namespace aidg;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+aidg_status fail(aidg_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+aidg_status hip_fail(hipError_t e, const char* what) {
+  return fail(AIDG_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+}  // namespace
+
+struct aidg_plan {
+  Geometry g{};
+  int n_st = 0, nbl = 0, nt = 0, nc = 0, n_int = 0, W = 1, max_nv = 1, device = 0;
+  std::vector<aidg_subgrid> table;
+  std::vector<double> w0;
+  int64_t n_excluded = 0;
+  int64_t batch = 1;
+  size_t elem = 8, aterm_bytes = 0, device_bytes = 0, scratch_bytes = 0;
+  SubgridDev* d_sg = nullptr;
+  double* d_uvw = nullptr;
+  double* d_fc = nullptr;
+  void* d_aterms = nullptr;
+  void* d_taper = nullptr;
+  void* d_tw = nullptr;
+  void* d_scratch = nullptr;
+  int64_t* d_excl = nullptr;
+  hipEvent_t last = nullptr;
+  std::atomic<bool> busy{false};
+
+  KernelArgs args() const {
+    KernelArgs a;
+    a.sg = d_sg;
+    a.uvw = d_uvw;
+    a.fc = d_fc;
+    a.aterms = d_aterms;
+    a.taper = d_taper;
+    a.twiddle = d_tw;
+    a.scratch = d_scratch;
+    a.nt_total = nt;
+    a.nc_total = nc;
+    a.N = g.N;
+    a.pad = 0;
+    a.du = g.du;
+    a.lstep = g.fov / g.L;
+    return a;
+  }
+
+  void release() {
+    void* ptrs[] = {d_sg, d_uvw, d_fc, d_aterms, d_taper, d_tw, d_scratch, d_excl};
+    for (void* p : ptrs)
+      if (p) (void)hipFree(p);
+    if (last) (void)hipEventDestroy(last);
+    d_sg = nullptr;
+    d_uvw = d_fc = nullptr;
+    d_aterms = d_taper = d_tw = d_scratch = nullptr;
+    d_excl = nullptr;
+    last = nullptr;
+  }
+};
+
+namespace {
+
+struct BusyGuard {
+  aidg_plan* p;
+  bool ok;
+  explicit BusyGuard(aidg_plan* q) : p(q) {
+    bool expected = false;
+    ok = p->busy.compare_exchange_strong(expected, true);
+  }
+  ~BusyGuard() {
+    if (ok) p->busy.store(false);
+  }
+};
+
+bool gpu_subgrid_size(int L) { return L == 32 || L == 64 || L == 96; }
+
+template <typename T>
+aidg_status dalloc(T** p, size_t bytes, aidg_plan* plan, const char* what) {
+  void* q = nullptr;
+  const hipError_t e = hipMalloc(&q, std::max<size_t>(bytes, 256));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(AIDG_E_NOMEM, std::string("device allocation of ") + what + " failed: " +
+                                  hipGetErrorString(e));
+  }
+  *p = reinterpret_cast<T*>(q);
+  plan->device_bytes += std::max<size_t>(bytes, 256);
+  return AIDG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t aidg_abi_version(void) { return AIDG_ABI_VERSION; }
+
+const char* aidg_last_error(void) { return g_last_error.c_str(); }
+
+aidg_status aidg_partition(const aidg_geometry* geo, int32_t n_stations, int32_t n_baselines,
+                           int32_t n_times, int32_t n_chans, const int32_t* baselines,
+                           const double* uvw_m, const double* freqs_hz, aidg_subgrid* out,
+                           int64_t cap, int64_t* n_out, double* w_step_out) {
+  try {
+    Geometry g;
+    std::string err;
+    aidg_status st = validate_geometry(geo, &g, &err);
+    if (st != AIDG_OK) return fail(st, err);
+    PartitionResult pr;
+    st = partition(g, n_stations, n_baselines, n_times, n_chans, baselines, uvw_m, freqs_hz, &pr, &err);
+    if (st != AIDG_OK) return fail(st, err);
+    if (n_out) *n_out = (int64_t)pr.table.size();
+    if (w_step_out) *w_step_out = pr.w_step;
+    if ((int64_t)pr.table.size() > cap || (pr.table.size() && !out))
+      return fail(AIDG_E_INVALID, "output capacity too small for the partition");
+    std::copy(pr.table.begin(), pr.table.end(), out);
+    return AIDG_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(AIDG_E_NOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(AIDG_E_INVALID, "unexpected host exception");
+  }
+}
+
+aidg_status aidg_plan_create(const aidg_geometry* geo, int32_t n_stations, int32_t n_baselines,
+                             int32_t n_times, int32_t n_chans, const int32_t* baselines,
+                             const double* uvw_m, const double* freqs_hz, const void* aterms,
+                             const aidg_subgrid* table, int64_t n_table, void* hip_stream,
+                             aidg_plan** out) {
+  if (!out) return fail(AIDG_E_INVALID, "out is NULL");
+  *out = nullptr;
+  aidg_plan* plan = nullptr;
+  try {
+    plan = new aidg_plan();
+    Geometry& g = plan->g;
+    std::string err;
+    aidg_status st = validate_geometry(geo, &g, &err);
+    if (st != AIDG_OK) {
+      delete plan;
+      return fail(st, err);
+    }
+    if (!gpu_subgrid_size(g.L)) {
+      delete plan;
+      return fail(AIDG_E_UNSUPPORTED, "the GPU kernels support subgrid sizes 32, 64 and 96");
+    }
+    if (!aterms || n_baselines < 1 || n_times < 1 || n_chans < 1 || n_stations < 1) {
+      delete plan;
+      return fail(AIDG_E_INVALID, "empty observation or NULL A-terms");
+    }
+    plan->n_st = n_stations;
+    plan->nbl = n_baselines;
+    plan->nt = n_times;
+    plan->nc = n_chans;
+    plan->n_int = (n_times + g.aterm_interval - 1) / g.aterm_interval;
+    plan->elem = g.precision == AIDG_FP32 ? 8 : 16;
+
+    PartitionResult pr;
+    if (!baselines || !uvw_m || !freqs_hz) {
+      st = AIDG_E_INVALID;
+      err = "NULL host arrays";
+    } else if (!table) {
+      st = partition(g, n_stations, n_baselines, n_times, n_chans, baselines, uvw_m, freqs_hz, &pr,
+                     &err);
+    } else if (n_table < 0) {
+      st = AIDG_E_INVALID;
+      err = "negative table size";
+    } else {
+      st = adopt_table(g, n_stations, n_baselines, n_times, n_chans, baselines, table, n_table, &pr,
+                       &err);
+    }
+    if (st != AIDG_OK) {
+      delete plan;
+      return fail(st, err);
+    }
+    plan->table = split_large(pr.table, g.max_sg_vis, n_times, n_chans);
+    plan->n_excluded = (int64_t)pr.excluded.size();
+    if (table) {
+      int32_t wmax = 0;
+      for (const auto& s : plan->table) wmax = std::max(wmax, s.wlayer);
+      plan->W = wmax + 1;
+      plan->w0.assign(plan->W, 0.0);
+      for (const auto& s : plan->table) plan->w0[s.wlayer] = s.w0;
+    } else {
+      plan->W = (int)(pr.jmax - pr.jmin + 1);
+      plan->w0.resize(plan->W);
+      for (int j = 0; j < plan->W; ++j) plan->w0[j] = pr.w_step > 0 ? (pr.jmin + j) * pr.w_step : 0.0;
+    }
+    plan->max_nv = 1;
+    for (const auto& s : plan->table) plan->max_nv = std::max(plan->max_nv, s.nt * s.nc);
+
+    // device records
+    const double inv_c = 1.0 / kSpeedOfLight;
+    std::vector<SubgridDev> dev(plan->table.size());
+    for (size_t i = 0; i < plan->table.size(); ++i) {
+      const aidg_subgrid& s = plan->table[i];
+      SubgridDev& d = dev[i];
+      std::memset(&d, 0, sizeof(d));
+      d.t0 = s.t0;
+      d.nt = s.nt;
+      d.c0 = s.c0;
+      d.nc = s.nc;
+      d.U0 = s.U0;
+      d.V0 = s.V0;
+      d.wlayer = s.wlayer;
+      d.ap = s.aint * n_stations + s.st1;
+      d.aq = s.aint * n_stations + s.st2;
+      d.bl = s.bl;
+      d.vis0 = s.vis_offset;
+      d.uvw0 = (int64_t)s.bl * n_times + s.t0;
+      d.w0 = s.w0;
+      const double df = s.nc > 1 ? freqs_hz[s.c0 + 1] - freqs_hz[s.c0] : 0.0;
+      bool uniform = true;
+      for (int c = s.c0 + 1; c < s.c0 + s.nc; ++c)
+        if (std::fabs((freqs_hz[c] - freqs_hz[c - 1]) - df) > 1e-9 * std::fabs(df)) uniform = false;
+      d.dfc = df * inv_c;
+      d.R = uniform ? g.R : 1;
+    }
+    std::vector<double> fc(n_chans);
+    for (int c = 0; c < n_chans; ++c) fc[c] = freqs_hz[c] * inv_c;
+    const int L = g.L;
+    std::vector<double> T;
+    kaiser_bessel_taper(L, g.beta, &T);
+    for (int y = 0; y < L; ++y)
+      for (int x = 0; x < L; ++x)
+        if ((x + y) & 1) T[(size_t)y * L + x] = -T[(size_t)y * L + x];
+    std::vector<double> tw(2 * L);
+    for (int k = 0; k < L; ++k) {
+      const double ang = -2.0 * M_PI * k / L;
+      tw[2 * k] = std::cos(ang);
+      tw[2 * k + 1] = std::sin(ang);
+    }
+    const bool f32 = g.precision == AIDG_FP32;
+    std::vector<float> Tf(T.begin(), T.end()), twf(tw.begin(), tw.end());
+
+    plan->aterm_bytes = (size_t)plan->n_int * n_stations * L * L * 4 * plan->elem;
+    const size_t per_sg = (size_t)4 * L * L * plan->elem;
+    const int64_t nsg = (int64_t)plan->table.size();
+    plan->batch = std::max<int64_t>(1, std::min<int64_t>(g.workspace / (int64_t)per_sg, 65535));
+    plan->batch = std::min<int64_t>(plan->batch, std::max<int64_t>(nsg, 1));
+    plan->scratch_bytes = (size_t)plan->batch * per_sg;
+
+    hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+    hipError_t e = hipGetDevice(&plan->device);
+    if (e != hipSuccess) {
+      delete plan;
+      return hip_fail(e, "hipGetDevice");
+    }
+    if ((st = dalloc(&plan->d_sg, dev.size() * sizeof(SubgridDev), plan, "subgrid table")) ||
+        (st = dalloc(&plan->d_uvw, (size_t)n_baselines * n_times * 3 * sizeof(double), plan, "uvw")) ||
+        (st = dalloc(&plan->d_fc, fc.size() * sizeof(double), plan, "frequencies")) ||
+        (st = dalloc(&plan->d_aterms, plan->aterm_bytes, plan, "A-terms")) ||
+        (st = dalloc(&plan->d_taper, (size_t)L * L * (f32 ? 4 : 8), plan, "taper")) ||
+        (st = dalloc(&plan->d_tw, (size_t)L * (f32 ? 8 : 16), plan, "twiddles")) ||
+        (st = dalloc(&plan->d_excl, pr.excluded.size() * sizeof(int64_t), plan, "excluded list")) ||
+        (st = dalloc(&plan->d_scratch, plan->scratch_bytes, plan, "subgrid workspace"))) {
+      plan->release();
+      delete plan;
+      return st;
+    }
+    struct Copy {
+      void* dst;
+      const void* src;
+      size_t n;
+      hipMemcpyKind kind;
+    } copies[] = {
+        {plan->d_sg, dev.data(), dev.size() * sizeof(SubgridDev), hipMemcpyHostToDevice},
+        {plan->d_uvw, uvw_m, (size_t)n_baselines * n_times * 3 * sizeof(double), hipMemcpyHostToDevice},
+        {plan->d_fc, fc.data(), fc.size() * sizeof(double), hipMemcpyHostToDevice},
+        {plan->d_aterms, aterms, plan->aterm_bytes, hipMemcpyDeviceToDevice},
+        {plan->d_taper, f32 ? (const void*)Tf.data() : (const void*)T.data(), (size_t)L * L * (f32 ? 4 : 8),
+         hipMemcpyHostToDevice},
+        {plan->d_tw, f32 ? (const void*)twf.data() : (const void*)tw.data(), (size_t)L * (f32 ? 8 : 16),
+         hipMemcpyHostToDevice},
+        {plan->d_excl, pr.excluded.data(), pr.excluded.size() * sizeof(int64_t), hipMemcpyHostToDevice},
+    };
+    for (const Copy& c : copies) {
+      if (!c.n) continue;
+      e = hipMemcpyAsync(c.dst, c.src, c.n, c.kind, stream);
+      if (e != hipSuccess) {
+        plan->release();
+        delete plan;
+        return hip_fail(e, "hipMemcpyAsync (plan upload)");
+      }
+    }
+    if ((e = hipEventCreateWithFlags(&plan->last, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventRecord(plan->last, stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(stream)) != hipSuccess) {
+      plan->release();
+      delete plan;
+      return hip_fail(e, "plan upload");
+    }
+    *out = plan;
+    return AIDG_OK;
+  } catch (const std::bad_alloc&) {
+    if (plan) {
+      plan->release();
+      delete plan;
+    }
+    return fail(AIDG_E_NOMEM, "host allocation failed");
+  }
+}
+
+aidg_status aidg_plan_info_get(const aidg_plan* plan, aidg_plan_info* info) {
+  if (!plan || !info) return fail(AIDG_E_INVALID, "NULL plan or info");
+  std::memset(info, 0, sizeof(*info));
+  info->n_subgrids = (int64_t)plan->table.size();
+  info->n_vis = (int64_t)plan->nbl * plan->nt * plan->nc;
+  info->n_excluded = plan->n_excluded;
+  info->n_wlayers = plan->W;
+  info->subgrid_size = plan->g.L;
+  info->w_step = plan->g.w_step;
+  info->device_bytes = (int64_t)plan->device_bytes;
+  info->workspace_bytes = (int64_t)plan->scratch_bytes;
+  info->grid_bytes = (int64_t)plan->W * 4 * plan->g.N * plan->g.N * (int64_t)plan->elem;
+  info->vis_bytes = info->n_vis * 4 * (int64_t)plan->elem;
+  const int64_t n = info->n_subgrids;
+  info->n_batches = n ? (n + plan->batch - 1) / plan->batch : 0;
+  info->max_subgrid_vis = plan->max_nv;
+  return AIDG_OK;
+}
+
+aidg_status aidg_plan_subgrids(const aidg_plan* plan, aidg_subgrid* out, int64_t cap) {
+  if (!plan || (!out && cap > 0)) return fail(AIDG_E_INVALID, "NULL plan or output");
+  const int64_t n = std::min<int64_t>(cap, (int64_t)plan->table.size());
+  if (n > 0) std::memcpy(out, plan->table.data(), (size_t)n * sizeof(aidg_subgrid));
+  return AIDG_OK;
+}
+
+aidg_status aidg_plan_wlayers(const aidg_plan* plan, double* w0, int32_t cap) {
+  if (!plan || (!w0 && cap > 0)) return fail(AIDG_E_INVALID, "NULL plan or output");
+  for (int j = 0; j < std::min(cap, (int32_t)plan->W); ++j) w0[j] = plan->w0[j];
+  return AIDG_OK;
+}
+
+aidg_status aidg_plan_set_aterms(aidg_plan* plan, const void* aterms, void* hip_stream) {
+  if (!plan || !aterms) return fail(AIDG_E_INVALID, "NULL plan or A-terms");
+  BusyGuard guard(plan);
+  if (!guard.ok) return fail(AIDG_E_BUSY, "plan in use by another thread");
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  hipError_t e = hipStreamWaitEvent(st, plan->last, 0);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(plan->d_aterms, aterms, plan->aterm_bytes, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = hipEventRecord(plan->last, st);
+  return e == hipSuccess ? AIDG_OK : hip_fail(e, "A-term copy");
+}
+
+aidg_status aidg_grid(aidg_plan* plan, const void* vis, void* grid, void* hip_stream) {
+  if (!plan || !vis || !grid) return fail(AIDG_E_INVALID, "NULL plan, vis or grid");
+  BusyGuard guard(plan);
+  if (!guard.ok) return fail(AIDG_E_BUSY, "plan in use by another thread");
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  hipError_t e = hipStreamWaitEvent(st, plan->last, 0);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
+  const KernelArgs a = plan->args();
+  const int64_t n = (int64_t)plan->table.size();
+  for (int64_t b0 = 0; b0 < n; b0 += plan->batch) {
+    const int rc = launch_grid_batch(plan->g.L, plan->g.precision, a, b0,
+                                     std::min(plan->batch, n - b0), vis, grid, hip_stream);
+    if (rc != 0) return hip_fail((hipError_t)rc, "gridding kernel launch");
+  }
+  e = hipEventRecord(plan->last, st);
+  return e == hipSuccess ? AIDG_OK : hip_fail(e, "hipEventRecord");
+}
+
+aidg_status aidg_degrid(aidg_plan* plan, const void* grid, void* vis_out, void* hip_stream) {
+  if (!plan || !vis_out || !grid) return fail(AIDG_E_INVALID, "NULL plan, grid or vis");
+  BusyGuard guard(plan);
+  if (!guard.ok) return fail(AIDG_E_BUSY, "plan in use by another thread");
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  hipError_t e = hipStreamWaitEvent(st, plan->last, 0);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
+  int rc = launch_zero_vis(plan->g.precision, plan->d_excl, plan->n_excluded, vis_out, hip_stream);
+  if (rc != 0) return hip_fail((hipError_t)rc, "zeroing excluded visibilities");
+  const KernelArgs a = plan->args();
+  const int64_t n = (int64_t)plan->table.size();
+  for (int64_t b0 = 0; b0 < n; b0 += plan->batch) {
+    rc = launch_degrid_batch(plan->g.L, plan->g.precision, a, b0, std::min(plan->batch, n - b0), grid,
+                             vis_out, hip_stream, plan->max_nv);
+    if (rc != 0) return hip_fail((hipError_t)rc, "degridding kernel launch");
+  }
+  e = hipEventRecord(plan->last, st);
+  return e == hipSuccess ? AIDG_OK : hip_fail(e, "hipEventRecord");
+}
+
+void aidg_plan_destroy(aidg_plan* plan) {
+  if (!plan) return;
+  if (plan->last) (void)hipEventSynchronize(plan->last);
+  plan->release();
+  delete plan;
+}
+
+}  // extern "C"

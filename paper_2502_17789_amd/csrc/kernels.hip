@@ -1,0 +1,595 @@
+// HIP kernels for A-term image-domain gridding on gfx950 (CDNA4).
+//
+// Gridding of one batch of subgrids (Sec. 2.5 imaging, steps 2a-2c):
+//   grid_dft   one workgroup per (1024-pixel chunk, subgrid); each lane owns 4
+//              subgrid pixels and sums every visibility of the subgrid onto them
+//              (Eq. withw).  Visibilities and uvw rows are wave-uniform loads
+//              (scalar unit), so each visibility costs 16 FMA for the 2x2 complex
+//              accumulation plus 4 for the phasor step per pixel.  Phasors come
+//              from a per-channel recurrence: an FP64 phase origin per (row,
+//              pixel) reduced to a quarter turn, an accurate FP32 sin/cos, then
+//              ph <- ph * step, re-seeded from FP64 every R channels.  The
+//              epilogue applies T (-1)^(x+y) A_p^H S A_q (Sec. 3.3).
+//   fft_add    one workgroup per (polarisation, subgrid): Stockham FFT of the
+//              L x L plane in LDS (radix 4/2/3), then (-1)^(a+b) and an atomic
+//              add onto the subgrid's window of its w-layer (Eq. shiftback).
+// Degridding (prediction, step 3), the adjoint chain:
+//   split_ifft one workgroup per (polarisation, subgrid): copy the window times
+//              (-1)^(a+b) into LDS (splitter), inverse FFT, store the plane.
+//   degrid_dft one workgroup per subgrid; lanes own pixels and apply
+//              T (-1)^(x+y) A_p S A_q^H once; for each group of 4 channels every
+//              lane forms its 4 pixels' partial sums (32 floats), a wave-wide
+//              transpose-reduction (permlane32/permlane16 swaps, then DPP) leaves
+//              each lane with one reduced value, and waves combine through LDS
+//              atomics; the finished visibilities are written once (Eq. degridder).
+//
+// The centred DFT of Sec. 2.3 relates to a plain FFT by a checkerboard:
+//   sum_{x,y} s(x,y) e^{-2 pi i [(a-L/2)(x-L/2) + (b-L/2)(y-L/2)]/L}
+//     = (-1)^(a+b) FFT[(-1)^(x+y) s](a,b)     (even L),
+// so the (-1)^(x+y) factor is folded into the taper table and (-1)^(a+b) into
+// the adder/splitter.
+
+#include <hip/hip_runtime.h>
+
+#include "aidg_internal.h"
+
+namespace aidg {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kPix = 4;                     // pixels per lane (gridder and degridder)
+constexpr int kChunk = kThreads * kPix;     // pixels per workgroup pass
+constexpr int kVisGroup = 4;                // channels per degridder reduction
+
+template <typename R> struct C2;
+template <> struct C2<float> { using T = float2; };
+template <> struct C2<double> { using T = double2; };
+
+template <typename R>
+__device__ __forceinline__ typename C2<R>::T cmul(typename C2<R>::T a, typename C2<R>::T b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+
+// exp(2 pi i theta) for a phase theta in turns, FP32 result.  The quarter-turn
+// reduction happens in FP64 (theta = q/4 + t, |t| <= 1/8, exact), t is rounded
+// once to FP32, and sin/cos(2 pi t) come from their Taylor series to degree 9
+// and 10 (truncation < 2e-9 for |2 pi t| <= pi/4), evaluated by Horner in FP32.
+__device__ __forceinline__ float2 phasor(double theta, float) {
+  const double q = rint(4.0 * theta);
+  const float t = (float)fma(q, -0.25, theta);
+  const int qi = (int)(int64_t)q;
+  const float t2 = t * t;
+  float s = fmaf(t2, 42.058693944897634f, -76.70585975306136f);
+  s = fmaf(t2, s, 81.60524927607504f);
+  s = fmaf(t2, s, -41.341702240399755f);
+  s = fmaf(t2, s, 6.283185307179586f);
+  s = s * t;
+  float c = fmaf(t2, -26.426256783374388f, 60.24464137187664f);
+  c = fmaf(t2, c, -85.45681720669371f);
+  c = fmaf(t2, c, 64.93939402266828f);
+  c = fmaf(t2, c, -19.739208802178716f);
+  c = fmaf(t2, c, 1.0f);
+  // rotate by qi quarter turns
+  const bool odd = qi & 1, neg_c = (qi + 1) & 2, neg_s = qi & 2;
+  const float cc = odd ? s : c, ss = odd ? c : s;
+  return {neg_c ? -cc : cc, neg_s ? -ss : ss};
+}
+
+// FP64 variant: reduction to [-1/2, 1/2] and the device library's sincospi.
+__device__ __forceinline__ double2 phasor(double theta, double) {
+  const double r = theta - rint(theta);
+  double s, c;
+  sincospi(2.0 * r, &s, &c);
+  return {c, s};
+}
+
+struct Pixel {
+  int pix, x, y;
+  double l, m, n1;
+};
+
+template <int L>
+__device__ __forceinline__ Pixel pixel_at(int pix, double lstep) {
+  Pixel p;
+  p.pix = pix;
+  p.x = pix % L;
+  p.y = pix / L;
+  p.l = (p.x - L / 2) * lstep;
+  p.m = (p.y - L / 2) * lstep;
+  const double r2 = p.l * p.l + p.m * p.m;
+  p.n1 = -r2 / (1.0 + sqrt(1.0 - r2));
+  return p;
+}
+
+// ------------------------------------------------------------------ gridder
+
+template <int L, typename R>
+__global__ __launch_bounds__(kThreads) void grid_dft(KernelArgs a, int64_t sg_begin,
+                                                     const R* __restrict__ vis,
+                                                     R* __restrict__ scratch) {
+  using V2 = typename C2<R>::T;
+  const int local = blockIdx.y;
+  const SubgridDev s = a.sg[sg_begin + local];
+  Pixel px[kPix];
+#pragma unroll
+  for (int p = 0; p < kPix; ++p)
+    px[p] = pixel_at<L>(blockIdx.x * kChunk + p * kThreads + threadIdx.x, a.lstep);
+
+  R acc[kPix][8];
+#pragma unroll
+  for (int p = 0; p < kPix; ++p)
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc[p][i] = 0;
+
+  const double u0 = (s.U0 - a.N / 2) * a.du, v0 = (s.V0 - a.N / 2) * a.du;
+  for (int t = 0; t < s.nt; ++t) {
+    const double* uvw = a.uvw + 3 * (s.uvw0 + t);
+    const double um = uvw[0], vm = uvw[1], wm = uvw[2];
+    const R* vrow = vis + 8 * (s.vis0 + (int64_t)t * a.nc_total);
+    V2 st[kPix], ph[kPix];
+    {
+      const double su = um * s.dfc, sv = vm * s.dfc, sw = wm * s.dfc;
+#pragma unroll
+      for (int p = 0; p < kPix; ++p) st[p] = phasor(su * px[p].l + sv * px[p].m + sw * px[p].n1, R());
+    }
+    for (int j0 = 0; j0 < s.nc; j0 += s.R) {
+      const double fc = a.fc[s.c0 + j0];
+      const double cu = um * fc - u0, cv = vm * fc - v0, cw = wm * fc - s.w0;
+#pragma unroll
+      for (int p = 0; p < kPix; ++p) ph[p] = phasor(cu * px[p].l + cv * px[p].m + cw * px[p].n1, R());
+      const int jn = min(s.nc, j0 + s.R);
+      for (int j = j0; j < jn; ++j) {
+        const R* v = vrow + 8 * j;
+        R vv[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) vv[i] = v[i];
+#pragma unroll
+        for (int p = 0; p < kPix; ++p) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            acc[p][2 * q] = fma(vv[2 * q], ph[p].x, acc[p][2 * q]);
+            acc[p][2 * q] = fma(-vv[2 * q + 1], ph[p].y, acc[p][2 * q]);
+            acc[p][2 * q + 1] = fma(vv[2 * q], ph[p].y, acc[p][2 * q + 1]);
+            acc[p][2 * q + 1] = fma(vv[2 * q + 1], ph[p].x, acc[p][2 * q + 1]);
+          }
+          ph[p] = cmul<R>(ph[p], st[p]);
+        }
+      }
+    }
+  }
+
+  // epilogue: S' = T (-1)^(x+y) A_p^H S A_q, one plane per polarisation
+  const V2* At = reinterpret_cast<const V2*>(a.aterms);
+  const R* taper = reinterpret_cast<const R*>(a.taper);
+  V2* out = reinterpret_cast<V2*>(scratch) + (int64_t)local * 4 * L * L;
+#pragma unroll
+  for (int p = 0; p < kPix; ++p) {
+    const int pix = px[p].pix;
+    const V2* Ap = At + ((int64_t)s.ap * L * L + pix) * 4;
+    const V2* Aq = At + ((int64_t)s.aq * L * L + pix) * 4;
+    V2 a0 = Ap[0], a1 = Ap[1], a2 = Ap[2], a3 = Ap[3];
+    a0.y = -a0.y; a1.y = -a1.y; a2.y = -a2.y; a3.y = -a3.y;  // conj
+    const V2 b0 = Aq[0], b1 = Aq[1], b2 = Aq[2], b3 = Aq[3];
+    const V2 s0 = {acc[p][0], acc[p][1]}, s1 = {acc[p][2], acc[p][3]};
+    const V2 s2 = {acc[p][4], acc[p][5]}, s3 = {acc[p][6], acc[p][7]};
+    // A_p^H = [[conj a0, conj a2], [conj a1, conj a3]]
+    const V2 t0 = cmul<R>(a0, s0) + cmul<R>(a2, s2);
+    const V2 t1 = cmul<R>(a0, s1) + cmul<R>(a2, s3);
+    const V2 t2 = cmul<R>(a1, s0) + cmul<R>(a3, s2);
+    const V2 t3 = cmul<R>(a1, s1) + cmul<R>(a3, s3);
+    const R w = taper[pix];
+    out[0 * L * L + pix] = (cmul<R>(t0, b0) + cmul<R>(t1, b2)) * w;
+    out[1 * L * L + pix] = (cmul<R>(t0, b1) + cmul<R>(t1, b3)) * w;
+    out[2 * L * L + pix] = (cmul<R>(t2, b0) + cmul<R>(t3, b2)) * w;
+    out[3 * L * L + pix] = (cmul<R>(t2, b1) + cmul<R>(t3, b3)) * w;
+  }
+}
+
+// ------------------------------------------------------------------ subgrid FFT
+
+template <int L> struct Radices;
+template <> struct Radices<32> { static constexpr int n = 3, r[4] = {4, 4, 2, 1}; };
+template <> struct Radices<64> { static constexpr int n = 3, r[4] = {4, 4, 4, 1}; };
+template <> struct Radices<96> { static constexpr int n = 4, r[4] = {4, 4, 2, 3}; };
+
+template <typename V2, int R, int DIR>
+__device__ __forceinline__ void butterfly(V2* v) {
+  using Rt = decltype(v[0].x);
+  if constexpr (R == 2) {
+    const V2 a = v[0], b = v[1];
+    v[0] = a + b;
+    v[1] = a - b;
+  } else if constexpr (R == 4) {
+    const V2 t0 = v[0] + v[2], t1 = v[0] - v[2], t2 = v[1] + v[3];
+    const V2 d = v[1] - v[3];
+    const V2 t3 = {Rt(-DIR) * d.y, Rt(DIR) * d.x};  // (DIR i) d
+    v[0] = t0 + t2;
+    v[1] = t1 + t3;
+    v[2] = t0 - t2;
+    v[3] = t1 - t3;
+  } else if constexpr (R == 3) {
+    const Rt c = Rt(-0.5), dd = Rt(DIR) * Rt(0.86602540378443864676);
+    const V2 t1 = v[1] + v[2], t2 = v[1] - v[2];
+    const V2 m = v[0] + t1 * c;
+    const V2 n = {-dd * t2.y, dd * t2.x};
+    v[0] = v[0] + t1;
+    v[1] = m + n;
+    v[2] = m - n;
+  }
+}
+
+constexpr int pitch(int L) { return L + 1; }
+
+// One Stockham pass (radix R, NS = product of earlier radices) over every line of
+// the plane held in LDS; lines are rows (stride 1) or columns (stride L+1).
+template <int L, int R, int NS, int DIR, bool ROWS, typename V2>
+__device__ __forceinline__ void stockham_pass(V2* buf, const V2* tw) {
+  constexpr int NB = L / R, TOTAL = L * NB, PER = (TOTAL + kThreads - 1) / kThreads;
+  constexpr int TSTEP = L / (NS * R);
+  V2 v[PER][R];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int b = threadIdx.x + i * kThreads;
+    if (b < TOTAL) {
+      const int line = ROWS ? b / NB : b % L, j = ROWS ? b % NB : b / L;
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const int idx = j + q * NB;
+        v[i][q] = buf[ROWS ? line * pitch(L) + idx : idx * pitch(L) + line];
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int b = threadIdx.x + i * kThreads;
+    if (b < TOTAL) {
+      const int line = ROWS ? b / NB : b % L, j = ROWS ? b % NB : b / L;
+      const int k = j % NS;
+#pragma unroll
+      for (int q = 1; q < R; ++q) {
+        V2 w = tw[(k * q * TSTEP) % L];
+        if (DIR > 0) w.y = -w.y;
+        v[i][q] = {v[i][q].x * w.x - v[i][q].y * w.y, v[i][q].x * w.y + v[i][q].y * w.x};
+      }
+      butterfly<V2, R, DIR>(v[i]);
+      const int base = (j / NS) * NS * R + k;
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const int idx = base + q * NS;
+        buf[ROWS ? line * pitch(L) + idx : idx * pitch(L) + line] = v[i][q];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <int L, int DIR, bool ROWS, typename V2>
+__device__ __forceinline__ void fft_lines(V2* buf, const V2* tw) {
+  using Rd = Radices<L>;
+  constexpr int r0 = Rd::r[0], r1 = Rd::r[1], r2 = Rd::r[2], r3 = Rd::r[3];
+  stockham_pass<L, r0, 1, DIR, ROWS>(buf, tw);
+  stockham_pass<L, r1, r0, DIR, ROWS>(buf, tw);
+  stockham_pass<L, r2, r0 * r1, DIR, ROWS>(buf, tw);
+  if constexpr (Rd::n == 4) stockham_pass<L, r3, r0 * r1 * r2, DIR, ROWS>(buf, tw);
+}
+
+template <int L, typename R>
+__global__ __launch_bounds__(kThreads) void fft_add(KernelArgs a, int64_t sg_begin,
+                                                    const R* __restrict__ scratch, R* grid) {
+  using V2 = typename C2<R>::T;
+  __shared__ V2 buf[L * pitch(L)];
+  __shared__ V2 tw[L];
+  const int pol = blockIdx.x, local = blockIdx.y;
+  const SubgridDev s = a.sg[sg_begin + local];
+  const V2* in = reinterpret_cast<const V2*>(scratch) + ((int64_t)local * 4 + pol) * L * L;
+  for (int e = threadIdx.x; e < L * L; e += kThreads) buf[(e / L) * pitch(L) + e % L] = in[e];
+  for (int e = threadIdx.x; e < L; e += kThreads) tw[e] = reinterpret_cast<const V2*>(a.twiddle)[e];
+  __syncthreads();
+  fft_lines<L, -1, true>(buf, tw);
+  fft_lines<L, -1, false>(buf, tw);
+  R* g = grid + 2 * ((((int64_t)s.wlayer * 4 + pol) * a.N + (s.V0 - L / 2)) * a.N + (s.U0 - L / 2));
+  for (int e = threadIdx.x; e < L * L; e += kThreads) {
+    const int b = e / L, c = e % L;
+    V2 val = buf[b * pitch(L) + c];
+    if ((b + c) & 1) val = -val;
+    R* dst = g + 2 * ((int64_t)b * a.N + c);
+    unsafeAtomicAdd(dst, val.x);
+    unsafeAtomicAdd(dst + 1, val.y);
+  }
+}
+
+template <int L, typename R>
+__global__ __launch_bounds__(kThreads) void split_ifft(KernelArgs a, int64_t sg_begin,
+                                                       const R* __restrict__ grid,
+                                                       R* __restrict__ scratch) {
+  using V2 = typename C2<R>::T;
+  __shared__ V2 buf[L * pitch(L)];
+  __shared__ V2 tw[L];
+  const int pol = blockIdx.x, local = blockIdx.y;
+  const SubgridDev s = a.sg[sg_begin + local];
+  const V2* g = reinterpret_cast<const V2*>(grid) +
+                (((int64_t)s.wlayer * 4 + pol) * a.N + (s.V0 - L / 2)) * a.N + (s.U0 - L / 2);
+  for (int e = threadIdx.x; e < L * L; e += kThreads) {
+    const int b = e / L, c = e % L;
+    V2 val = g[(int64_t)b * a.N + c];
+    if ((b + c) & 1) val = -val;
+    buf[b * pitch(L) + c] = val;
+  }
+  for (int e = threadIdx.x; e < L; e += kThreads) tw[e] = reinterpret_cast<const V2*>(a.twiddle)[e];
+  __syncthreads();
+  fft_lines<L, +1, true>(buf, tw);
+  fft_lines<L, +1, false>(buf, tw);
+  V2* out = reinterpret_cast<V2*>(scratch) + ((int64_t)local * 4 + pol) * L * L;
+  for (int e = threadIdx.x; e < L * L; e += kThreads) out[e] = buf[(e / L) * pitch(L) + e % L];
+}
+
+// ------------------------------------------------------------------ degridder
+
+__device__ __forceinline__ void swap32(float& x, float& y) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+  x = __uint_as_float(r[0]);
+  y = __uint_as_float(r[1]);
+}
+__device__ __forceinline__ void swap16(float& x, float& y) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+  x = __uint_as_float(r[0]);
+  y = __uint_as_float(r[1]);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ void swap32(double& x, double& y) {
+  float xl = __uint_as_float((unsigned)__double_as_longlong(x));
+  float xh = __uint_as_float((unsigned)(__double_as_longlong(x) >> 32));
+  float yl = __uint_as_float((unsigned)__double_as_longlong(y));
+  float yh = __uint_as_float((unsigned)(__double_as_longlong(y) >> 32));
+  swap32(xl, yl);
+  swap32(xh, yh);
+  x = __longlong_as_double(((long long)__float_as_uint(xh) << 32) | __float_as_uint(xl));
+  y = __longlong_as_double(((long long)__float_as_uint(yh) << 32) | __float_as_uint(yl));
+}
+__device__ __forceinline__ void swap16(double& x, double& y) {
+  float xl = __uint_as_float((unsigned)__double_as_longlong(x));
+  float xh = __uint_as_float((unsigned)(__double_as_longlong(x) >> 32));
+  float yl = __uint_as_float((unsigned)__double_as_longlong(y));
+  float yh = __uint_as_float((unsigned)(__double_as_longlong(y) >> 32));
+  swap16(xl, yl);
+  swap16(xh, yh);
+  x = __longlong_as_double(((long long)__float_as_uint(xh) << 32) | __float_as_uint(xl));
+  y = __longlong_as_double(((long long)__float_as_uint(yh) << 32) | __float_as_uint(yl));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+constexpr int kDppRowRor8 = 0x128, kDppHalfMirror = 0x141, kDppXor2 = 0x4E, kDppXor1 = 0xB1;
+
+// Sum 32 per-lane values over the 64 lanes of a wave.  On return lane `ln` holds
+// the full sum of value index (ln >> 1) (both lanes of a pair hold it).
+template <typename R>
+__device__ __forceinline__ R transpose_reduce32(R (&a)[32], int ln) {
+  // lanes ln, ln^32: halves of a wave (permlane32 swap)
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    swap32(a[i], a[i + 16]);
+    a[i] = a[i] + a[i + 16];  // lanes 0-31: value i, lanes 32-63: value i+16
+  }
+  // lanes ln, ln^16: rows of 16 (permlane16 swap)
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    swap16(a[i], a[i + 8]);
+    a[i] = a[i] + a[i + 8];  // row r holds value i + 8r
+  }
+  // lanes ln, ln^8 (row rotate by 8)
+  const bool b3 = ln & 8, b2 = ln & 4, b1 = ln & 2;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const R keep = b3 ? a[i + 4] : a[i], send = b3 ? a[i] : a[i + 4];
+    a[i] = keep + dpp<kDppRowRor8>(send);  // value i + 4 b3 + 8 row
+  }
+  // lanes ln, ln^7 (half-row mirror)
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const R keep = b2 ? a[i + 2] : a[i], send = b2 ? a[i] : a[i + 2];
+    a[i] = keep + dpp<kDppHalfMirror>(send);  // value i + 2 b2 + 4 b3 + 8 row
+  }
+  // lanes ln, ln^2
+  {
+    const R keep = b1 ? a[1] : a[0], send = b1 ? a[0] : a[1];
+    a[0] = keep + dpp<kDppXor2>(send);  // value b1 + 2 b2 + 4 b3 + 8 row = ln >> 1
+  }
+  // lanes ln, ln^1 hold the same value index: add
+  return a[0] + dpp<kDppXor1>(a[0]);
+}
+
+template <int L, typename R>
+__global__ __launch_bounds__(kThreads) void degrid_dft(KernelArgs a, int64_t sg_begin,
+                                                       const R* __restrict__ scratch,
+                                                       R* __restrict__ vis) {
+  using V2 = typename C2<R>::T;
+  extern __shared__ unsigned char smem_raw[];
+  R* accs = reinterpret_cast<R*>(smem_raw);
+  const int local = blockIdx.x;
+  const SubgridDev s = a.sg[sg_begin + local];
+  const int nv = s.nt * s.nc;
+  for (int i = threadIdx.x; i < nv * 8; i += kThreads) accs[i] = 0;
+  __syncthreads();
+  const int ln = threadIdx.x & 63;
+  const V2* At = reinterpret_cast<const V2*>(a.aterms);
+  const R* taper = reinterpret_cast<const R*>(a.taper);
+  const V2* img = reinterpret_cast<const V2*>(scratch) + (int64_t)local * 4 * L * L;
+  const double u0 = (s.U0 - a.N / 2) * a.du, v0 = (s.V0 - a.N / 2) * a.du;
+
+  for (int chunk = 0; chunk < (L * L) / kChunk; ++chunk) {
+    Pixel px[kPix];
+    V2 sp[kPix][4];
+#pragma unroll
+    for (int p = 0; p < kPix; ++p) {
+      px[p] = pixel_at<L>(chunk * kChunk + p * kThreads + threadIdx.x, a.lstep);
+      const int pix = px[p].pix;
+      // prologue: S' = T (-1)^(x+y) A_p S A_q^H
+      const V2* Ap = At + ((int64_t)s.ap * L * L + pix) * 4;
+      const V2* Aq = At + ((int64_t)s.aq * L * L + pix) * 4;
+      const V2 a0 = Ap[0], a1 = Ap[1], a2 = Ap[2], a3 = Ap[3];
+      V2 b0 = Aq[0], b1 = Aq[1], b2 = Aq[2], b3 = Aq[3];
+      b0.y = -b0.y; b1.y = -b1.y; b2.y = -b2.y; b3.y = -b3.y;  // conj
+      const V2 s0 = img[0 * L * L + pix], s1 = img[1 * L * L + pix];
+      const V2 s2 = img[2 * L * L + pix], s3 = img[3 * L * L + pix];
+      const V2 t0 = cmul<R>(a0, s0) + cmul<R>(a1, s2);
+      const V2 t1 = cmul<R>(a0, s1) + cmul<R>(a1, s3);
+      const V2 t2 = cmul<R>(a2, s0) + cmul<R>(a3, s2);
+      const V2 t3 = cmul<R>(a2, s1) + cmul<R>(a3, s3);
+      const R w = taper[pix];
+      // A_q^H = [[conj b0, conj b2], [conj b1, conj b3]]
+      sp[p][0] = (cmul<R>(t0, b0) + cmul<R>(t1, b1)) * w;
+      sp[p][1] = (cmul<R>(t0, b2) + cmul<R>(t1, b3)) * w;
+      sp[p][2] = (cmul<R>(t2, b0) + cmul<R>(t3, b1)) * w;
+      sp[p][3] = (cmul<R>(t2, b2) + cmul<R>(t3, b3)) * w;
+    }
+    for (int t = 0; t < s.nt; ++t) {
+      const double* uvw = a.uvw + 3 * (s.uvw0 + t);
+      const double um = uvw[0], vm = uvw[1], wm = uvw[2];
+      V2 st[kPix], ph[kPix];
+      {
+        const double su = um * s.dfc, sv = vm * s.dfc, sw = wm * s.dfc;
+#pragma unroll
+        for (int p = 0; p < kPix; ++p)
+          st[p] = phasor(-(su * px[p].l + sv * px[p].m + sw * px[p].n1), R());
+      }
+      for (int g0 = 0; g0 < s.nc; g0 += kVisGroup) {
+        R part[32];
+#pragma unroll
+        for (int v = 0; v < kVisGroup; ++v) {
+          const int j = g0 + v;
+#pragma unroll
+          for (int i = 0; i < 8; ++i) part[8 * v + i] = 0;
+          if (j < s.nc) {
+            if (j % s.R == 0) {
+              const double fc = a.fc[s.c0 + j];
+              const double cu = um * fc - u0, cv = vm * fc - v0, cw = wm * fc - s.w0;
+#pragma unroll
+              for (int p = 0; p < kPix; ++p)
+                ph[p] = phasor(-(cu * px[p].l + cv * px[p].m + cw * px[p].n1), R());
+            }
+#pragma unroll
+            for (int p = 0; p < kPix; ++p) {
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                R re = part[8 * v + 2 * q], im = part[8 * v + 2 * q + 1];
+                re = fma(sp[p][q].x, ph[p].x, re);
+                re = fma(-sp[p][q].y, ph[p].y, re);
+                im = fma(sp[p][q].x, ph[p].y, im);
+                im = fma(sp[p][q].y, ph[p].x, im);
+                part[8 * v + 2 * q] = re;
+                part[8 * v + 2 * q + 1] = im;
+              }
+              ph[p] = cmul<R>(ph[p], st[p]);
+            }
+          }
+        }
+        const R val = transpose_reduce32<R>(part, ln);
+        const int idx = ln >> 1, v = idx >> 3, comp = idx & 7;
+        if (!(ln & 1) && g0 + v < s.nc) atomicAdd(&accs[(t * s.nc + g0 + v) * 8 + comp], val);
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nv * 8; i += kThreads) {
+    const int r = i / (s.nc * 8), rem = i % (s.nc * 8);
+    vis[(s.vis0 + (int64_t)r * a.nc_total) * 8 + rem] = accs[i];
+  }
+}
+
+template <typename R>
+__global__ void zero_vis(const int64_t* __restrict__ idx, int64_t n, R* vis) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n * 8) vis[idx[i / 8] * 8 + i % 8] = 0;
+}
+
+template <int L, typename R>
+int grid_batch(const KernelArgs& a, int64_t sg_begin, int64_t n_sg, const void* vis, void* grid,
+               hipStream_t st) {
+  const R* v = reinterpret_cast<const R*>(vis);
+  R* scratch = reinterpret_cast<R*>(a.scratch);
+  hipLaunchKernelGGL((grid_dft<L, R>), dim3((L * L) / kChunk, (unsigned)n_sg), dim3(kThreads), 0, st,
+                     a, sg_begin, v, scratch);
+  hipLaunchKernelGGL((fft_add<L, R>), dim3(4, (unsigned)n_sg), dim3(kThreads), 0, st, a, sg_begin,
+                     scratch, reinterpret_cast<R*>(grid));
+  return (int)hipGetLastError();
+}
+
+template <int L, typename R>
+int degrid_batch(const KernelArgs& a, int64_t sg_begin, int64_t n_sg, const void* grid, void* vis,
+                 hipStream_t st, int max_nv) {
+  R* scratch = reinterpret_cast<R*>(a.scratch);
+  hipLaunchKernelGGL((split_ifft<L, R>), dim3(4, (unsigned)n_sg), dim3(kThreads), 0, st, a, sg_begin,
+                     reinterpret_cast<const R*>(grid), scratch);
+  hipLaunchKernelGGL((degrid_dft<L, R>), dim3((unsigned)n_sg), dim3(kThreads),
+                     (size_t)max_nv * 8 * sizeof(R), st, a, sg_begin, scratch,
+                     reinterpret_cast<R*>(vis));
+  return (int)hipGetLastError();
+}
+
+}  // namespace
+
+int launch_grid_batch(int L, int precision, const KernelArgs& a, int64_t sg_begin, int64_t n_sg,
+                      const void* vis, void* grid, void* stream) {
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (n_sg <= 0) return 0;
+  if (precision == AIDG_FP32) {
+    switch (L) {
+      case 32: return grid_batch<32, float>(a, sg_begin, n_sg, vis, grid, st);
+      case 64: return grid_batch<64, float>(a, sg_begin, n_sg, vis, grid, st);
+      case 96: return grid_batch<96, float>(a, sg_begin, n_sg, vis, grid, st);
+    }
+  } else {
+    switch (L) {
+      case 32: return grid_batch<32, double>(a, sg_begin, n_sg, vis, grid, st);
+      case 64: return grid_batch<64, double>(a, sg_begin, n_sg, vis, grid, st);
+      case 96: return grid_batch<96, double>(a, sg_begin, n_sg, vis, grid, st);
+    }
+  }
+  return (int)hipErrorInvalidValue;
+}
+
+int launch_degrid_batch(int L, int precision, const KernelArgs& a, int64_t sg_begin, int64_t n_sg,
+                        const void* grid, void* vis, void* stream, int max_nv) {
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (n_sg <= 0) return 0;
+  if (precision == AIDG_FP32) {
+    switch (L) {
+      case 32: return degrid_batch<32, float>(a, sg_begin, n_sg, grid, vis, st, max_nv);
+      case 64: return degrid_batch<64, float>(a, sg_begin, n_sg, grid, vis, st, max_nv);
+      case 96: return degrid_batch<96, float>(a, sg_begin, n_sg, grid, vis, st, max_nv);
+    }
+  } else {
+    switch (L) {
+      case 32: return degrid_batch<32, double>(a, sg_begin, n_sg, grid, vis, st, max_nv);
+      case 64: return degrid_batch<64, double>(a, sg_begin, n_sg, grid, vis, st, max_nv);
+      case 96: return degrid_batch<96, double>(a, sg_begin, n_sg, grid, vis, st, max_nv);
+    }
+  }
+  return (int)hipErrorInvalidValue;
+}
+
+int launch_zero_vis(int precision, const int64_t* idx, int64_t n, void* vis, void* stream) {
+  if (n <= 0) return 0;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const int64_t threads = n * 8;
+  const unsigned blocks = (unsigned)((threads + 255) / 256);
+  if (precision == AIDG_FP32)
+    hipLaunchKernelGGL(zero_vis<float>, dim3(blocks), dim3(256), 0, st, idx, n,
+                       reinterpret_cast<float*>(vis));
+  else
+    hipLaunchKernelGGL(zero_vis<double>, dim3(blocks), dim3(256), 0, st, idx, n,
+                       reinterpret_cast<double*>(vis));
+  return (int)hipGetLastError();
+}
+
+}  // namespace aidg

@@ -1,0 +1,365 @@
+// Host-side plan logic: geometry validation, w-layer spacing, the sub-table
+// partitioner of Sec. 3.1, adoption of caller partitions and the taper.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "aidg_internal.h"
+
+namespace aidg {
+
+aidg_status validate_geometry(const aidg_geometry* g, Geometry* o, std::string* err) {
+  if (!g) {
+    *err = "geometry is NULL";
+    return AIDG_E_INVALID;
+  }
+  const int N = g->grid_size, L = g->subgrid_size, K = g->kernel_support;
+  if (L < 4 || (L & 1)) {
+    *err = "subgrid_size must be even and >= 4";
+    return AIDG_E_INVALID;
+  }
+  if (N < L || (N & 1)) {
+    *err = "grid_size must be even and >= subgrid_size";
+    return AIDG_E_INVALID;
+  }
+  if (K < 0 || (K & 1) || K >= L) {
+    *err = "kernel_support must be even with 0 <= K < L";
+    return AIDG_E_INVALID;
+  }
+  if (g->aterm_interval < 1) {
+    *err = "aterm_interval must be >= 1";
+    return AIDG_E_INVALID;
+  }
+  if (!(g->pixel_scale > 0) || !std::isfinite(g->pixel_scale)) {
+    *err = "pixel_scale must be positive";
+    return AIDG_E_INVALID;
+  }
+  const double fov = N * g->pixel_scale;
+  // the corner pixel of the subgrid lattice, (-FOV/2, -FOV/2), must be above the horizon
+  if (fov * fov / 2.0 >= 1.0) {
+    *err = "field of view reaches the horizon (FOV/sqrt(2) >= 1)";
+    return AIDG_E_INVALID;
+  }
+  if (g->precision != AIDG_FP32 && g->precision != AIDG_FP64) {
+    *err = "precision must be AIDG_FP32 or AIDG_FP64";
+    return AIDG_E_INVALID;
+  }
+  if (g->reseed_channels < 0 || g->max_subgrid_vis < 0 || g->workspace_bytes < 0 ||
+      !std::isfinite(g->w_step) || !std::isfinite(g->taper_beta) || g->taper_beta < 0) {
+    *err = "negative or non-finite numeric parameter";
+    return AIDG_E_INVALID;
+  }
+  o->N = N;
+  o->L = L;
+  o->K = K;
+  o->aterm_interval = g->aterm_interval;
+  o->precision = g->precision;
+  o->R = g->reseed_channels ? g->reseed_channels : kReseedDefault;
+  o->strict = g->strict_range != 0;
+  o->max_sg_vis = g->max_subgrid_vis ? g->max_subgrid_vis : kMaxSubgridVisDefault;
+  o->dl = g->pixel_scale;
+  o->fov = fov;
+  o->du = 1.0 / fov;
+  o->beta = g->taper_beta > 0 ? g->taper_beta : M_PI * K / 4.0;
+  o->workspace = g->workspace_bytes ? g->workspace_bytes : kWorkspaceDefault;
+  if (g->w_step > 0) o->w_step = g->w_step;
+  else if (g->w_step < 0) o->w_step = 0.0;
+  else o->w_step = auto_w_step(*o);
+  return AIDG_OK;
+}
+
+// w_max (Sec. 2.4 footnote): the w-term's local fringe rate |w - w0| |grad n| must
+// stay within the K/4 cells left beside the taper's main lobe, i.e.
+// |w - w0| rho FOV <= K/4 with rho the largest |grad n| = r / n on the lattice
+// (at its corner).  Layers are spaced by 2 w_max.
+double auto_w_step(const Geometry& g) {
+  if (g.K == 0) return 0.0;
+  const double r = g.fov / std::sqrt(2.0);
+  const double rho = r / std::sqrt(1.0 - r * r);
+  const double wmax = g.K / (4.0 * g.fov * rho);
+  return 2.0 * wmax;
+}
+
+namespace {
+
+struct Ctx {
+  const Geometry& g;
+  int nbl, nt, nc;
+  const double* uvw;
+  const double* freqs;
+  double cell(int bl, int t, int c, int axis) const {
+    return uvw[3 * ((size_t)bl * nt + t) + axis] * freqs[c] / kSpeedOfLight / g.du + g.N / 2;
+  }
+  double wl(int bl, int t, int c) const {
+    return uvw[3 * ((size_t)bl * nt + t) + 2] * freqs[c] / kSpeedOfLight;
+  }
+  bool placeable(int bl, int t, int c) const {
+    const double gu = cell(bl, t, c, 0), gv = cell(bl, t, c, 1);
+    const double lo = g.K / 2.0, hi = g.N - g.K / 2.0;
+    return gu >= lo && gu <= hi && gv >= lo && gv <= hi && std::isfinite(gu) && std::isfinite(gv);
+  }
+  int64_t layer(int bl, int t, int c) const {
+    return g.w_step > 0 ? (int64_t)std::nearbyint(wl(bl, t, c) / g.w_step) : 0;
+  }
+};
+
+struct Box {
+  double ulo = 1e300, uhi = -1e300, vlo = 1e300, vhi = -1e300;
+  void add(double u, double v) {
+    ulo = std::min(ulo, u);
+    uhi = std::max(uhi, u);
+    vlo = std::min(vlo, v);
+    vhi = std::max(vhi, v);
+  }
+};
+
+// Integer centre for a span, clamped to keep the window on the grid; true if
+// every point of the span is within half of it.
+bool centre(double lo, double hi, double half, int L, int N, int* c) {
+  const double mid = 0.5 * (lo + hi);
+  int k = (int)std::floor(mid + 0.5);
+  k = std::min(std::max(k, L / 2), N - L / 2);
+  *c = k;
+  return hi - k <= half && k - lo <= half;
+}
+
+// Add row t, channels [c0, c1), to box b; false if a visibility is unplaceable
+// or in another layer.
+bool add_row(const Ctx& x, int bl, int t, int c0, int c1, int64_t layer, Box* b) {
+  for (int c = c0; c < c1; ++c) {
+    if (!x.placeable(bl, t, c) || x.layer(bl, t, c) != layer) return false;
+    b->add(x.cell(bl, t, c, 0), x.cell(bl, t, c, 1));
+  }
+  return true;
+}
+
+void tile(const Ctx& x, int bl, int ts, int te, int c_lo, int c_hi, PartitionResult* out,
+          std::vector<aidg_subgrid>* sgs, const int32_t* baselines) {
+  if (ts >= te || c_lo >= c_hi) return;
+  const Geometry& g = x.g;
+  const double window = g.L - g.K, half = 0.5 * window, comfy = 0.75 * window;
+  // Row ts of channels [c_lo, c_hi) is split into runs; every run grows
+  // downwards in time, and the rows it leaves below are tiled recursively.
+  int c = c_lo;
+  while (c < c_hi) {
+    if (!x.placeable(bl, ts, c)) {
+      int c2 = c;
+      while (c2 < c_hi && !x.placeable(bl, ts, c2)) {
+        out->excluded.push_back(((int64_t)bl * x.nt + ts) * x.nc + c2);
+        ++c2;
+      }
+      tile(x, bl, ts + 1, te, c, c2, out, sgs, baselines);
+      c = c2;
+      continue;
+    }
+    const int64_t lay = x.layer(bl, ts, c);
+    Box b;
+    b.add(x.cell(bl, ts, c, 0), x.cell(bl, ts, c, 1));
+    int e = c + 1, cu, cv;
+    while (e < c_hi && e - c < g.max_sg_vis) {
+      if (!x.placeable(bl, ts, e) || x.layer(bl, ts, e) != lay) break;
+      Box q = b;
+      q.add(x.cell(bl, ts, e, 0), x.cell(bl, ts, e, 1));
+      if (q.uhi - q.ulo > comfy || q.vhi - q.vlo > comfy) break;
+      if (!centre(q.ulo, q.uhi, half, g.L, g.N, &cu) || !centre(q.vlo, q.vhi, half, g.L, g.N, &cv))
+        break;
+      b = q;
+      ++e;
+    }
+    int t1 = ts + 1;
+    while (t1 < te && (int64_t)(t1 - ts + 1) * (e - c) <= g.max_sg_vis) {
+      Box q = b;
+      if (!add_row(x, bl, t1, c, e, lay, &q)) break;
+      if (!centre(q.ulo, q.uhi, half, g.L, g.N, &cu) || !centre(q.vlo, q.vhi, half, g.L, g.N, &cv))
+        break;
+      b = q;
+      ++t1;
+    }
+    int U0, V0;
+    centre(b.ulo, b.uhi, half, g.L, g.N, &U0);
+    centre(b.vlo, b.vhi, half, g.L, g.N, &V0);
+    aidg_subgrid s;
+    std::memset(&s, 0, sizeof(s));
+    s.bl = bl;
+    s.st1 = baselines[2 * bl];
+    s.st2 = baselines[2 * bl + 1];
+    s.t0 = ts;
+    s.nt = t1 - ts;
+    s.c0 = c;
+    s.nc = e - c;
+    s.U0 = U0;
+    s.V0 = V0;
+    s.wlayer = (int32_t)lay;  // raw layer number, rebased by the caller
+    s.aint = ts / g.aterm_interval;
+    s.w0 = g.w_step > 0 ? lay * g.w_step : 0.0;
+    s.vis_offset = ((int64_t)bl * x.nt + ts) * x.nc + c;
+    sgs->push_back(s);
+    tile(x, bl, t1, te, c, e, out, sgs, baselines);
+    c = e;
+  }
+}
+
+}  // namespace
+
+aidg_status partition(const Geometry& g, int n_st, int nbl, int nt, int nc, const int32_t* baselines,
+                      const double* uvw, const double* freqs, PartitionResult* out,
+                      std::string* err) {
+  if (n_st < 1 || nbl < 0 || nt < 0 || nc < 0 || (nbl && (!baselines || !uvw)) || (nc && !freqs)) {
+    *err = "bad observation sizes or NULL host arrays";
+    return AIDG_E_INVALID;
+  }
+  for (int b = 0; b < nbl; ++b) {
+    const int p = baselines[2 * b], q = baselines[2 * b + 1];
+    if (p < 0 || q < 0 || p >= n_st || q >= n_st) {
+      *err = "baseline station index out of range";
+      return AIDG_E_INVALID;
+    }
+  }
+  for (int c = 0; c < nc; ++c)
+    if (!(freqs[c] > 0) || (c && !(freqs[c] > freqs[c - 1]))) {
+      *err = "frequencies must be positive and strictly increasing";
+      return AIDG_E_INVALID;
+    }
+  for (size_t i = 0; i < (size_t)nbl * nt * 3; ++i)
+    if (!std::isfinite(uvw[i])) {
+      *err = "non-finite uvw";
+      return AIDG_E_INVALID;
+    }
+  Ctx x{g, nbl, nt, nc, uvw, freqs};
+  out->table.clear();
+  out->excluded.clear();
+  out->w_step = g.w_step;
+  std::vector<aidg_subgrid> sgs;
+  for (int bl = 0; bl < nbl; ++bl)
+    for (int ta = 0; ta < nt; ta += g.aterm_interval)
+      tile(x, bl, ta, std::min(nt, ta + g.aterm_interval), 0, nc, out, &sgs, baselines);
+  int64_t jmin = 0, jmax = 0;
+  for (size_t i = 0; i < sgs.size(); ++i) {
+    jmin = i ? std::min<int64_t>(jmin, sgs[i].wlayer) : sgs[i].wlayer;
+    jmax = i ? std::max<int64_t>(jmax, sgs[i].wlayer) : sgs[i].wlayer;
+  }
+  for (auto& s : sgs) s.wlayer = (int32_t)(s.wlayer - jmin);
+  out->jmin = jmin;
+  out->jmax = jmax;
+  out->table.swap(sgs);
+  std::sort(out->excluded.begin(), out->excluded.end());
+  if (g.strict && !out->excluded.empty()) {
+    *err = "visibilities outside the grid (strict_range)";
+    return AIDG_E_RANGE;
+  }
+  return AIDG_OK;
+}
+
+aidg_status adopt_table(const Geometry& g, int n_st, int nbl, int nt, int nc,
+                        const int32_t* baselines, const aidg_subgrid* table, int64_t n_table,
+                        PartitionResult* out, std::string* err) {
+  out->table.assign(table, table + n_table);
+  out->excluded.clear();
+  std::vector<uint8_t> cover((size_t)nbl * nt * nc, 0);
+  int32_t wmax = -1;
+  for (int64_t i = 0; i < n_table; ++i) wmax = std::max(wmax, table[i].wlayer);
+  std::vector<double> w0(wmax + 1, NAN);
+  for (int64_t i = 0; i < n_table; ++i) {
+    const aidg_subgrid& s = table[i];
+    char msg[160];
+    snprintf(msg, sizeof msg, "subgrid %lld: ", (long long)i);
+    if (s.bl < 0 || s.bl >= nbl || s.st1 != baselines[2 * s.bl] || s.st2 != baselines[2 * s.bl + 1] ||
+        s.st1 < 0 || s.st1 >= n_st || s.st2 < 0 || s.st2 >= n_st) {
+      *err = std::string(msg) + "bad baseline or stations";
+      return AIDG_E_INVALID;
+    }
+    if (s.nt < 1 || s.nc < 1 || s.t0 < 0 || s.c0 < 0 || s.t0 + s.nt > nt || s.c0 + s.nc > nc) {
+      *err = std::string(msg) + "sub-table outside the visibility table";
+      return AIDG_E_INVALID;
+    }
+    if (s.t0 / g.aterm_interval != (s.t0 + s.nt - 1) / g.aterm_interval ||
+        s.aint != s.t0 / g.aterm_interval) {
+      *err = std::string(msg) + "sub-table spans two A-term intervals";
+      return AIDG_E_INVALID;
+    }
+    if (s.U0 - g.L / 2 < 0 || s.U0 + g.L / 2 > g.N || s.V0 - g.L / 2 < 0 || s.V0 + g.L / 2 > g.N) {
+      *err = std::string(msg) + "window not on the grid";
+      return AIDG_E_INVALID;
+    }
+    if (s.wlayer < 0 || !std::isfinite(s.w0) ||
+        (!std::isnan(w0[s.wlayer]) && w0[s.wlayer] != s.w0)) {
+      *err = std::string(msg) + "w-layer index without a single w0";
+      return AIDG_E_INVALID;
+    }
+    w0[s.wlayer] = s.w0;
+    if (s.vis_offset != ((int64_t)s.bl * nt + s.t0) * nc + s.c0) {
+      *err = std::string(msg) + "vis_offset does not match (bl, t0, c0)";
+      return AIDG_E_INVALID;
+    }
+    for (int t = s.t0; t < s.t0 + s.nt; ++t)
+      for (int c = s.c0; c < s.c0 + s.nc; ++c) {
+        uint8_t& k = cover[((size_t)s.bl * nt + t) * nc + c];
+        if (k) {
+          *err = std::string(msg) + "visibility already in another subgrid";
+          return AIDG_E_INVALID;
+        }
+        k = 1;
+      }
+  }
+  for (size_t k = 0; k < cover.size(); ++k)
+    if (!cover[k]) out->excluded.push_back((int64_t)k);
+  if (g.strict && !out->excluded.empty()) {
+    *err = "table leaves visibilities out (strict_range)";
+    return AIDG_E_RANGE;
+  }
+  out->w_step = g.w_step;
+  out->jmin = 0;
+  out->jmax = wmax;
+  return AIDG_OK;
+}
+
+// Sub-tables with more than max_vis visibilities are cut into pieces of whole
+// rows (or, for a single over-long row, channel ranges) with the same centre and
+// layer; the sum over subgrids, and so the grid, is unchanged by this.
+std::vector<aidg_subgrid> split_large(const std::vector<aidg_subgrid>& t, int max_vis, int nt_total,
+                                      int nc_total) {
+  std::vector<aidg_subgrid> out;
+  out.reserve(t.size());
+  for (const aidg_subgrid& s : t) {
+    if ((int64_t)s.nt * s.nc <= max_vis) {
+      out.push_back(s);
+      continue;
+    }
+    if (s.nc <= max_vis) {
+      const int rows = std::max(1, max_vis / s.nc);
+      for (int t = 0; t < s.nt; t += rows) {
+        aidg_subgrid p = s;
+        p.t0 = s.t0 + t;
+        p.nt = std::min(rows, s.nt - t);
+        p.vis_offset = ((int64_t)p.bl * nt_total + p.t0) * nc_total + p.c0;
+        out.push_back(p);
+      }
+    } else {
+      for (int t = 0; t < s.nt; ++t)
+        for (int c = 0; c < s.nc; c += max_vis) {
+          aidg_subgrid p = s;
+          p.t0 = s.t0 + t;
+          p.nt = 1;
+          p.c0 = s.c0 + c;
+          p.nc = std::min(max_vis, s.nc - c);
+          p.vis_offset = ((int64_t)p.bl * nt_total + p.t0) * nc_total + p.c0;
+          out.push_back(p);
+        }
+    }
+  }
+  return out;
+}
+
+void kaiser_bessel_taper(int L, double beta, std::vector<double>* T) {
+  std::vector<double> t(L);
+  const double i0b = std::cyl_bessel_i(0.0, beta);
+  for (int x = 0; x < L; ++x) {
+    const double f = double(x - L / 2) / L;
+    t[x] = std::cyl_bessel_i(0.0, beta * std::sqrt(std::max(0.0, 1.0 - 4.0 * f * f))) / i0b;
+  }
+  T->resize((size_t)L * L);
+  for (int y = 0; y < L; ++y)
+    for (int x = 0; x < L; ++x) (*T)[(size_t)y * L + x] = t[x] * t[y];
+}
+
+}  // namespace aidg
