@@ -1,0 +1,193 @@
+"""Throughput of A-term IDG gridding + degridding on one MI355X.
+
+One step = one gridding job and one degridding job over the whole MWA-like
+observation (128 stations, 8128 baselines x 60 timesteps x 96 channels = 46.8M
+4-pol visibilities; grid 8000^2 at 15 arcsec, subgrid 96^2, kernel support 24,
+A-terms every 8 timesteps), inputs already resident in HBM:
+    grid.zero_(); aidg_grid(V -> grid); aidg_degrid(grid -> V')
+value = visibilities / (time per step), in Mvis/s gridded + degridded.
+
+Also reported: grid and degrid rates separately, p50/p99 job latency over the
+timed steps, the roofline position of the dominant kernel (per-kernel HIP event
+times on the launch stream, algorithmic FMA work per visibility x pixel) and the
+FP64 CPU oracle timed on a bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Algorithmic work per (visibility, subgrid pixel): the 2x2 complex multiply-
+# accumulate is 16 FP32 FMAs, the phasor step ph <- ph * step is 4 FP32 ops
+# (2 mul + 2 FMA); each occupies one FMA issue slot, counted as 2 FLOP.
+FLOP_PER_VP = 40
+# FP32 issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz x 2 FLOP/FMA.  Packed
+# FP32 instructions are disabled in this build, so this is the attainable rate.
+PEAK_FP32_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12   # 78.64
+PEAK_FP32_PACKED_TFLOPS = 157.3                       # published vector peak (packed FMA)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-baselines", type=int, default=12)
+    return ap.parse_args()
+
+
+def workload_description(wl, info):
+    return {
+        "workload": "MWA-like A-term IDG grid+degrid: 128 stations in a 5 km disc, 8128 baselines "
+                    "x 60 x 2 s x 96 ch (140-170 MHz), 4-pol complex64; grid 8000^2 at 15 arcsec, "
+                    "subgrid 96^2, K=24; A-terms 8 intervals x 128 stations (Gaussian beam x "
+                    "Kolmogorov screen 2 rad rms)",
+        "n_vis": int(wl.n_vis), "grid_size": wl.grid_size, "subgrid_size": wl.subgrid_size,
+        "kernel_support": wl.kernel_support, "n_subgrids": int(info["n_subgrids"]),
+        "n_wlayers": int(info["n_wlayers"]), "precision": "fp32 (fp64 phase origins)",
+    }
+
+
+def cpu_baseline(wl, n_bl: int):
+    """FP64 oracle (test infrastructure) on a fixed random subset of baselines."""
+    import oracle
+    import synth
+    rng = np.random.default_rng(2)
+    sel = np.sort(rng.choice(wl.n_baselines, n_bl, replace=False))
+    sub = synth.Workload("mwa-sample", wl.n_stations, np.ascontiguousarray(wl.baselines[sel]),
+                         np.ascontiguousarray(wl.uvw[sel]), wl.freqs, wl.grid_size, wl.subgrid_size,
+                         wl.kernel_support, wl.pixel_scale, wl.aterm_interval, wl.aterms)
+    V = synth.random_vis((n_bl, wl.n_times, wl.n_chans), rng)
+    table = oracle.partition(sub, 0.0)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    G = oracle.grid(sub, V, table, nthreads=threads)
+    t1 = time.perf_counter()
+    oracle.degrid(sub, G, table, nthreads=threads)
+    t2 = time.perf_counter()
+    n = sub.n_vis
+    return {"value": round(n / (t2 - t0) / 1e6, 6), "unit": "Mvis/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n_bl} random baselines (seed 2) of the same observation, all 60 x 96 "
+                      f"visibilities each ({n} vis, {table.shape[0]} subgrids), grid then degrid at "
+                      f"full N, L, K; grid {t1 - t0:.2f} s, degrid {t2 - t1:.2f} s"}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (the design "
+              "would shard baselines across GPUs and all-reduce the grid); run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2502_17789_amd as aidg
+    import synth
+
+    torch.cuda.set_device(0)
+    wl = synth.config_mwa(seed=2)
+    geo = aidg.Geometry(wl.grid_size, wl.subgrid_size, wl.kernel_support, wl.pixel_scale,
+                        aterm_interval=wl.aterm_interval)
+    A = torch.from_numpy(wl.aterms.astype(np.complex64)).cuda()
+    t0 = time.perf_counter()
+    plan = aidg.Plan(geo, wl.n_stations, wl.baselines, wl.uvw, wl.freqs, A)
+    plan_s = time.perf_counter() - t0
+    info = plan.info
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(2)
+    V = torch.randn(plan.vis_shape(), dtype=torch.complex64, device="cuda", generator=gen)
+    G = torch.zeros(plan.grid_shape(), dtype=torch.complex64, device="cuda")
+    Vout = torch.empty_like(V)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        G.zero_()
+        plan.grid(V, G)
+        plan.degrid(G, Vout)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    print(f"# plan {plan_s:.2f} s, {info['n_subgrids']} subgrids, {info['n_batches']} batches; "
+          f"warmup done", file=sys.stderr, flush=True)
+
+    plan.set_profiling(True)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record(stream)
+        G.zero_()
+        plan.grid(V, G)
+        ev[i][1].record(stream)
+        plan.degrid(G, Vout)
+        ev[i][2].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    kt = plan.kernel_times()
+    plan.set_profiling(False)
+    t_grid = np.array([e[0].elapsed_time(e[1]) for e in ev])
+    t_degrid = np.array([e[1].elapsed_time(e[2]) for e in ev])
+    t_job = t_grid + t_degrid
+    n = wl.n_vis
+    ms_per_step = wall * 1e3 / args.steps
+
+    dom = max(("grid_dft", "degrid_dft", "fft_add", "split_ifft"), key=lambda k: kt[k]["ms"])
+    k = kt[dom]
+    if dom in ("grid_dft", "degrid_dft"):
+        achieved = k["vis_pixels"] * FLOP_PER_VP / (k["ms"] * 1e-3) / 1e12
+        roof = {"kernel": dom, "bound": "alu", "achieved": round(achieved, 3),
+                "peak": round(PEAK_FP32_TFLOPS, 2), "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "frac_of_packed_peak": round(achieved / PEAK_FP32_PACKED_TFLOPS, 4),
+                "avg_launch_ms": round(k["ms"] / max(k["launches"], 1), 4),
+                "launches": k["launches"]}
+    else:
+        roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": 8000.0, "unit": "GB/s",
+                "frac": None, "traffic": None}
+    kernels = {name: {"ms_per_step": round(v["ms"] / args.steps, 3),
+                      "launches_per_step": v["launches"] / args.steps,
+                      **({"tflops": round(v["vis_pixels"] * FLOP_PER_VP / (v["ms"] * 1e-3) / 1e12, 3)}
+                         if v["vis_pixels"] and v["ms"] > 0 else {})}
+               for name, v in kt.items()}
+    out = {
+        "metric": "Mvisibilities/sec gridded+degridded (with A-terms) at 1e-5 rel err; p50/p99 job latency",
+        "value": round(n / (ms_per_step * 1e-3) / 1e6, 3),
+        "unit": "Mvis/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": workload_description(wl, info),
+        "grid_mvis_s": round(n / (np.median(t_grid) * 1e-3) / 1e6, 3),
+        "degrid_mvis_s": round(n / (np.median(t_degrid) * 1e-3) / 1e6, 3),
+        "latency_ms": {"p50": round(float(np.percentile(t_job, 50)), 3),
+                       "p99": round(float(np.percentile(t_job, 99)), 3),
+                       "job": "one grid job + one degrid job of the whole observation"},
+        "plan_build_s": round(plan_s, 3),
+        "roofline": roof,
+        "kernels": kernels,
+    }
+    plan.close()
+    del V, G, Vout, A
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_baselines)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -170,6 +170,27 @@ aidg_status aidg_grid(aidg_plan* plan, const void* vis, void* grid, void* hip_st
  * visibilities that belong to no subgrid are set to zero. */
 aidg_status aidg_degrid(aidg_plan* plan, const void* grid, void* vis_out, void* hip_stream);
 
+/* Per-kernel device timing (the paper's per-subroutine breakdown, Sec. 5.4).
+ * Kernel classes: 0 gridder DFT + Jones/taper epilogue, 1 FFT + adder,
+ * 2 splitter + inverse FFT, 3 degridder DFT with Jones/taper prologue,
+ * 4 zeroing of excluded visibilities. */
+#define AIDG_KERNEL_CLASSES 5
+typedef struct {
+  double ms[AIDG_KERNEL_CLASSES];            /* summed device time of the class */
+  int64_t launches[AIDG_KERNEL_CLASSES];     /* kernel launches timed */
+  int64_t vis_pixels[AIDG_KERNEL_CLASSES];   /* sum of (visibilities x L^2) over the
+                                                subgrids the launches processed */
+  int64_t subgrids[AIDG_KERNEL_CLASSES];     /* subgrids the launches processed */
+} aidg_kernel_times;
+
+/* Enable (1) or disable (0) timing: while enabled, aidg_grid / aidg_degrid record
+ * a HIP event on their stream before and after every kernel (events come from a
+ * pool created here; up to 8192 launches are timed between two reads). */
+aidg_status aidg_plan_set_profiling(aidg_plan* plan, int32_t enable);
+
+/* Wait for the recorded events, return the sums since the last read, and reset. */
+aidg_status aidg_plan_kernel_times(aidg_plan* plan, aidg_kernel_times* out);
+
 void aidg_plan_destroy(aidg_plan* plan);
 
 /* Thread-local description of the last non-OK status ("" if none). */

@@ -52,6 +52,14 @@ class _PlanInfo(ctypes.Structure):
                 ("n_batches", ctypes.c_int64), ("max_subgrid_vis", ctypes.c_int64)]
 
 
+KERNEL_CLASSES = ("grid_dft", "fft_add", "split_ifft", "degrid_dft", "zero_vis")
+
+
+class _KernelTimes(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 5), ("launches", ctypes.c_int64 * 5),
+                ("vis_pixels", ctypes.c_int64 * 5), ("subgrids", ctypes.c_int64 * 5)]
+
+
 @dataclasses.dataclass
 class Geometry:
     """Mirror of ``aidg_geometry``."""
@@ -99,6 +107,8 @@ def library() -> ctypes.CDLL:
         "aidg_plan_set_aterms": (I32, [P, P, P]),
         "aidg_grid": (I32, [P, P, P, P]),
         "aidg_degrid": (I32, [P, P, P, P]),
+        "aidg_plan_set_profiling": (I32, [P, I32]),
+        "aidg_plan_kernel_times": (I32, [P, P]),
         "aidg_plan_destroy": (None, [P]),
     }
     for name, (res, args) in sig.items():
@@ -230,6 +240,17 @@ class Plan:
         self._check_tensor(out, self.vis_shape(), "vis")
         _check(library().aidg_degrid(self._h, _dptr(grid), _dptr(out), _stream_handle(stream)))
         return out
+
+    def set_profiling(self, enable: bool = True):
+        """Time every kernel launch with HIP events on its stream (aidg_plan_set_profiling)."""
+        _check(library().aidg_plan_set_profiling(self._h, 1 if enable else 0))
+
+    def kernel_times(self) -> dict:
+        """Per kernel class: summed ms, launches, vis x pixels, subgrids; resets the sums."""
+        kt = _KernelTimes()
+        _check(library().aidg_plan_kernel_times(self._h, ctypes.byref(kt)))
+        return {name: {"ms": kt.ms[i], "launches": kt.launches[i], "vis_pixels": kt.vis_pixels[i],
+                       "subgrids": kt.subgrids[i]} for i, name in enumerate(KERNEL_CLASSES)}
 
     def close(self):
         if getattr(self, "_h", None):

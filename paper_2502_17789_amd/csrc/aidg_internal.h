@@ -66,11 +66,14 @@ struct KernelArgs {
   double lstep;             // FOV / L, subgrid lattice spacing in direction cosines
 };
 
-// Kernel launchers (kernels.hip).  Return a hipError_t as int.
-int launch_grid_batch(int L, int precision, const KernelArgs& a, int64_t sg_begin, int64_t n_sg,
-                      const void* vis, void* grid, void* stream);
-int launch_degrid_batch(int L, int precision, const KernelArgs& a, int64_t sg_begin, int64_t n_sg,
-                        const void* grid, void* vis, void* stream, int max_nv);
+// Kernel classes, in the order of aidg_kernel_times.
+enum KernelClass { kGridDft = 0, kFftAdd = 1, kSplitIfft = 2, kDegridDft = 3, kZeroVis = 4 };
+
+// Launch one kernel class over subgrids [sg_begin, sg_begin + n_sg) (kernels.hip).
+// in/out: visibilities and scratch or grid as the class requires.  Returns a
+// hipError_t as int.
+int launch_kernel(KernelClass k, int L, int precision, const KernelArgs& a, int64_t sg_begin,
+                  int64_t n_sg, const void* in, void* out, void* stream, int max_nv);
 int launch_zero_vis(int precision, const int64_t* idx, int64_t n, void* vis, void* stream);
 
 }  // namespace aidg

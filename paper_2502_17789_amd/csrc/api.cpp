@@ -47,6 +47,17 @@ struct aidg_plan {
   int64_t* d_excl = nullptr;
   hipEvent_t last = nullptr;
   std::atomic<bool> busy{false};
+  // profiling: events around each kernel launch
+  struct Timed {
+    int kind;
+    int64_t vp, nsg;
+    hipEvent_t a, b;
+  };
+  bool profiling = false;
+  std::vector<hipEvent_t> pool;
+  size_t pool_next = 0;
+  std::vector<Timed> timed;
+  std::vector<int64_t> vp_prefix;  // prefix sums of n_vis * L^2 over the table
 
   KernelArgs args() const {
     KernelArgs a;
@@ -71,6 +82,9 @@ struct aidg_plan {
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
     if (last) (void)hipEventDestroy(last);
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    pool.clear();
+    timed.clear();
     d_sg = nullptr;
     d_uvw = d_fc = nullptr;
     d_aterms = d_taper = d_tw = d_scratch = nullptr;
@@ -94,6 +108,32 @@ struct BusyGuard {
 };
 
 bool gpu_subgrid_size(int L) { return L == 32 || L == 64 || L == 96; }
+
+// Launch one kernel class over a batch, bracketed by timing events when profiling.
+aidg_status run(aidg_plan* p, KernelClass k, int64_t b0, int64_t n, const void* in, void* out,
+                void* stream) {
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  hipEvent_t ea = nullptr, eb = nullptr;
+  if (p->profiling && p->pool_next + 2 <= p->pool.size()) {
+    ea = p->pool[p->pool_next++];
+    eb = p->pool[p->pool_next++];
+    const hipError_t e = hipEventRecord(ea, st);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+  }
+  int rc;
+  if (k == kZeroVis)
+    rc = launch_zero_vis(p->g.precision, p->d_excl, p->n_excluded, out, stream);
+  else
+    rc = launch_kernel(k, p->g.L, p->g.precision, p->args(), b0, n, in, out, stream, p->max_nv);
+  if (rc != 0) return hip_fail((hipError_t)rc, "kernel launch");
+  if (ea) {
+    const hipError_t e = hipEventRecord(eb, st);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    const int64_t vp = k == kZeroVis ? 0 : p->vp_prefix[b0 + n] - p->vp_prefix[b0];
+    p->timed.push_back({(int)k, vp, k == kZeroVis ? 0 : n, ea, eb});
+  }
+  return AIDG_OK;
+}
 
 template <typename T>
 aidg_status dalloc(T** p, size_t bytes, aidg_plan* plan, const char* what) {
@@ -206,7 +246,12 @@ aidg_status aidg_plan_create(const aidg_geometry* geo, int32_t n_stations, int32
       for (int j = 0; j < plan->W; ++j) plan->w0[j] = pr.w_step > 0 ? (pr.jmin + j) * pr.w_step : 0.0;
     }
     plan->max_nv = 1;
-    for (const auto& s : plan->table) plan->max_nv = std::max(plan->max_nv, s.nt * s.nc);
+    plan->vp_prefix.assign(plan->table.size() + 1, 0);
+    for (size_t i = 0; i < plan->table.size(); ++i) {
+      const aidg_subgrid& s = plan->table[i];
+      plan->max_nv = std::max(plan->max_nv, s.nt * s.nc);
+      plan->vp_prefix[i + 1] = plan->vp_prefix[i] + (int64_t)s.nt * s.nc * g.L * g.L;
+    }
 
     // device records
     const double inv_c = 1.0 / kSpeedOfLight;
@@ -371,12 +416,12 @@ aidg_status aidg_grid(aidg_plan* plan, const void* vis, void* grid, void* hip_st
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   hipError_t e = hipStreamWaitEvent(st, plan->last, 0);
   if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
-  const KernelArgs a = plan->args();
   const int64_t n = (int64_t)plan->table.size();
   for (int64_t b0 = 0; b0 < n; b0 += plan->batch) {
-    const int rc = launch_grid_batch(plan->g.L, plan->g.precision, a, b0,
-                                     std::min(plan->batch, n - b0), vis, grid, hip_stream);
-    if (rc != 0) return hip_fail((hipError_t)rc, "gridding kernel launch");
+    const int64_t nb = std::min(plan->batch, n - b0);
+    aidg_status r = run(plan, kGridDft, b0, nb, vis, nullptr, hip_stream);
+    if (r == AIDG_OK) r = run(plan, kFftAdd, b0, nb, nullptr, grid, hip_stream);
+    if (r != AIDG_OK) return r;
   }
   e = hipEventRecord(plan->last, st);
   return e == hipSuccess ? AIDG_OK : hip_fail(e, "hipEventRecord");
@@ -389,17 +434,56 @@ aidg_status aidg_degrid(aidg_plan* plan, const void* grid, void* vis_out, void* 
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   hipError_t e = hipStreamWaitEvent(st, plan->last, 0);
   if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
-  int rc = launch_zero_vis(plan->g.precision, plan->d_excl, plan->n_excluded, vis_out, hip_stream);
-  if (rc != 0) return hip_fail((hipError_t)rc, "zeroing excluded visibilities");
-  const KernelArgs a = plan->args();
+  aidg_status r = AIDG_OK;
+  if (plan->n_excluded > 0) r = run(plan, kZeroVis, 0, 0, nullptr, vis_out, hip_stream);
+  if (r != AIDG_OK) return r;
   const int64_t n = (int64_t)plan->table.size();
   for (int64_t b0 = 0; b0 < n; b0 += plan->batch) {
-    rc = launch_degrid_batch(plan->g.L, plan->g.precision, a, b0, std::min(plan->batch, n - b0), grid,
-                             vis_out, hip_stream, plan->max_nv);
-    if (rc != 0) return hip_fail((hipError_t)rc, "degridding kernel launch");
+    const int64_t nb = std::min(plan->batch, n - b0);
+    r = run(plan, kSplitIfft, b0, nb, grid, nullptr, hip_stream);
+    if (r == AIDG_OK) r = run(plan, kDegridDft, b0, nb, nullptr, vis_out, hip_stream);
+    if (r != AIDG_OK) return r;
   }
   e = hipEventRecord(plan->last, st);
   return e == hipSuccess ? AIDG_OK : hip_fail(e, "hipEventRecord");
+}
+
+aidg_status aidg_plan_set_profiling(aidg_plan* plan, int32_t enable) {
+  if (!plan) return fail(AIDG_E_INVALID, "NULL plan");
+  BusyGuard guard(plan);
+  if (!guard.ok) return fail(AIDG_E_BUSY, "plan in use by another thread");
+  if (enable && plan->pool.empty()) {
+    const size_t n = 2 * 4096;
+    plan->pool.reserve(n);
+    for (size_t i = 0; i < n; ++i) {
+      hipEvent_t e;
+      const hipError_t err = hipEventCreate(&e);
+      if (err != hipSuccess) return hip_fail(err, "hipEventCreate");
+      plan->pool.push_back(e);
+    }
+  }
+  plan->profiling = enable != 0;
+  return AIDG_OK;
+}
+
+aidg_status aidg_plan_kernel_times(aidg_plan* plan, aidg_kernel_times* out) {
+  if (!plan || !out) return fail(AIDG_E_INVALID, "NULL plan or output");
+  BusyGuard guard(plan);
+  if (!guard.ok) return fail(AIDG_E_BUSY, "plan in use by another thread");
+  std::memset(out, 0, sizeof(*out));
+  for (const auto& t : plan->timed) {
+    hipError_t e = hipEventSynchronize(t.b);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, t.a, t.b);
+    if (e != hipSuccess) return hip_fail(e, "reading kernel timers");
+    out->ms[t.kind] += ms;
+    out->launches[t.kind] += 1;
+    out->vis_pixels[t.kind] += t.vp;
+    out->subgrids[t.kind] += t.nsg;
+  }
+  plan->timed.clear();
+  plan->pool_next = 0;
+  return AIDG_OK;
 }
 
 void aidg_plan_destroy(aidg_plan* plan) {

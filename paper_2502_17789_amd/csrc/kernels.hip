@@ -513,66 +513,50 @@ __global__ void zero_vis(const int64_t* __restrict__ idx, int64_t n, R* vis) {
 }
 
 template <int L, typename R>
-int grid_batch(const KernelArgs& a, int64_t sg_begin, int64_t n_sg, const void* vis, void* grid,
-               hipStream_t st) {
-  const R* v = reinterpret_cast<const R*>(vis);
+int launch_one(KernelClass k, const KernelArgs& a, int64_t sg_begin, int64_t n_sg, const void* in,
+               void* out, hipStream_t st, int max_nv) {
   R* scratch = reinterpret_cast<R*>(a.scratch);
-  hipLaunchKernelGGL((grid_dft<L, R>), dim3((L * L) / kChunk, (unsigned)n_sg), dim3(kThreads), 0, st,
-                     a, sg_begin, v, scratch);
-  hipLaunchKernelGGL((fft_add<L, R>), dim3(4, (unsigned)n_sg), dim3(kThreads), 0, st, a, sg_begin,
-                     scratch, reinterpret_cast<R*>(grid));
-  return (int)hipGetLastError();
-}
-
-template <int L, typename R>
-int degrid_batch(const KernelArgs& a, int64_t sg_begin, int64_t n_sg, const void* grid, void* vis,
-                 hipStream_t st, int max_nv) {
-  R* scratch = reinterpret_cast<R*>(a.scratch);
-  hipLaunchKernelGGL((split_ifft<L, R>), dim3(4, (unsigned)n_sg), dim3(kThreads), 0, st, a, sg_begin,
-                     reinterpret_cast<const R*>(grid), scratch);
-  hipLaunchKernelGGL((degrid_dft<L, R>), dim3((unsigned)n_sg), dim3(kThreads),
-                     (size_t)max_nv * 8 * sizeof(R), st, a, sg_begin, scratch,
-                     reinterpret_cast<R*>(vis));
+  const unsigned n = (unsigned)n_sg;
+  switch (k) {
+    case kGridDft:
+      hipLaunchKernelGGL((grid_dft<L, R>), dim3((L * L) / kChunk, n), dim3(kThreads), 0, st, a,
+                         sg_begin, reinterpret_cast<const R*>(in), scratch);
+      break;
+    case kFftAdd:
+      hipLaunchKernelGGL((fft_add<L, R>), dim3(4, n), dim3(kThreads), 0, st, a, sg_begin,
+                         (const R*)scratch, reinterpret_cast<R*>(out));
+      break;
+    case kSplitIfft:
+      hipLaunchKernelGGL((split_ifft<L, R>), dim3(4, n), dim3(kThreads), 0, st, a, sg_begin,
+                         reinterpret_cast<const R*>(in), scratch);
+      break;
+    case kDegridDft:
+      hipLaunchKernelGGL((degrid_dft<L, R>), dim3(n), dim3(kThreads), (size_t)max_nv * 8 * sizeof(R),
+                         st, a, sg_begin, (const R*)scratch, reinterpret_cast<R*>(out));
+      break;
+    default:
+      return (int)hipErrorInvalidValue;
+  }
   return (int)hipGetLastError();
 }
 
 }  // namespace
 
-int launch_grid_batch(int L, int precision, const KernelArgs& a, int64_t sg_begin, int64_t n_sg,
-                      const void* vis, void* grid, void* stream) {
+int launch_kernel(KernelClass k, int L, int precision, const KernelArgs& a, int64_t sg_begin,
+                  int64_t n_sg, const void* in, void* out, void* stream, int max_nv) {
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   if (n_sg <= 0) return 0;
   if (precision == AIDG_FP32) {
     switch (L) {
-      case 32: return grid_batch<32, float>(a, sg_begin, n_sg, vis, grid, st);
-      case 64: return grid_batch<64, float>(a, sg_begin, n_sg, vis, grid, st);
-      case 96: return grid_batch<96, float>(a, sg_begin, n_sg, vis, grid, st);
+      case 32: return launch_one<32, float>(k, a, sg_begin, n_sg, in, out, st, max_nv);
+      case 64: return launch_one<64, float>(k, a, sg_begin, n_sg, in, out, st, max_nv);
+      case 96: return launch_one<96, float>(k, a, sg_begin, n_sg, in, out, st, max_nv);
     }
   } else {
     switch (L) {
-      case 32: return grid_batch<32, double>(a, sg_begin, n_sg, vis, grid, st);
-      case 64: return grid_batch<64, double>(a, sg_begin, n_sg, vis, grid, st);
-      case 96: return grid_batch<96, double>(a, sg_begin, n_sg, vis, grid, st);
-    }
-  }
-  return (int)hipErrorInvalidValue;
-}
-
-int launch_degrid_batch(int L, int precision, const KernelArgs& a, int64_t sg_begin, int64_t n_sg,
-                        const void* grid, void* vis, void* stream, int max_nv) {
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  if (n_sg <= 0) return 0;
-  if (precision == AIDG_FP32) {
-    switch (L) {
-      case 32: return degrid_batch<32, float>(a, sg_begin, n_sg, grid, vis, st, max_nv);
-      case 64: return degrid_batch<64, float>(a, sg_begin, n_sg, grid, vis, st, max_nv);
-      case 96: return degrid_batch<96, float>(a, sg_begin, n_sg, grid, vis, st, max_nv);
-    }
-  } else {
-    switch (L) {
-      case 32: return degrid_batch<32, double>(a, sg_begin, n_sg, grid, vis, st, max_nv);
-      case 64: return degrid_batch<64, double>(a, sg_begin, n_sg, grid, vis, st, max_nv);
-      case 96: return degrid_batch<96, double>(a, sg_begin, n_sg, grid, vis, st, max_nv);
+      case 32: return launch_one<32, double>(k, a, sg_begin, n_sg, in, out, st, max_nv);
+      case 64: return launch_one<64, double>(k, a, sg_begin, n_sg, in, out, st, max_nv);
+      case 96: return launch_one<96, double>(k, a, sg_begin, n_sg, in, out, st, max_nv);
     }
   }
   return (int)hipErrorInvalidValue;
