@@ -245,6 +245,23 @@ aidg_status aidg_plan_create(const aidg_geometry* geo, int32_t n_stations, int32
       plan->w0.resize(plan->W);
       for (int j = 0; j < plan->W; ++j) plan->w0[j] = pr.w_step > 0 ? (pr.jmin + j) * pr.w_step : 0.0;
     }
+    // Order: A-term interval first (a batch then touches one interval's A-terms),
+    // then baseline; inside each batch the largest sub-tables go first so that the
+    // longest workgroups start early (longest-processing-time-first).
+    {
+      auto& t = plan->table;
+      std::stable_sort(t.begin(), t.end(), [](const aidg_subgrid& x, const aidg_subgrid& y) {
+        return x.aint != y.aint ? x.aint < y.aint : x.bl < y.bl;
+      });
+      const size_t per_sg = (size_t)4 * g.L * g.L * plan->elem;
+      const int64_t bsz = std::max<int64_t>(1, std::min<int64_t>(g.workspace / (int64_t)per_sg, 65535));
+      for (size_t b0 = 0; b0 < t.size(); b0 += (size_t)bsz) {
+        const size_t b1 = std::min(t.size(), b0 + (size_t)bsz);
+        std::stable_sort(t.begin() + b0, t.begin() + b1, [](const aidg_subgrid& x, const aidg_subgrid& y) {
+          return x.nt * x.nc > y.nt * y.nc;
+        });
+      }
+    }
     plan->max_nv = 1;
     plan->vp_prefix.assign(plan->table.size() + 1, 0);
     for (size_t i = 0; i < plan->table.size(); ++i) {

@@ -33,6 +33,10 @@
 
 #include "aidg_internal.h"
 
+#ifndef DEGRID_PIX96
+#define DEGRID_PIX96 9
+#endif
+
 namespace aidg {
 namespace {
 
@@ -40,6 +44,13 @@ constexpr int kThreads = 256;
 constexpr int kPix = 4;                     // pixels per lane (gridder and degridder)
 constexpr int kChunk = kThreads * kPix;     // pixels per workgroup pass
 constexpr int kVisGroup = 4;                // channels per degridder reduction
+
+// Degridder pixels per lane: more pixels per lane amortise the per-visibility
+// cross-lane reduction; 256 * P must divide L^2.
+template <int L> struct DegridPix;
+template <> struct DegridPix<32> { static constexpr int P = 4; };
+template <> struct DegridPix<64> { static constexpr int P = 8; };
+template <> struct DegridPix<96> { static constexpr int P = DEGRID_PIX96; };
 
 template <typename R> struct C2;
 template <> struct C2<float> { using T = float2; };
@@ -57,7 +68,7 @@ __device__ __forceinline__ typename C2<R>::T cmul(typename C2<R>::T a, typename 
 __device__ __forceinline__ float2 phasor(double theta, float) {
   const double q = rint(4.0 * theta);
   const float t = (float)fma(q, -0.25, theta);
-  const int qi = (int)(int64_t)q;
+  const int qi = (int)q;  // |theta| is bounded by the grid size in turns
   const float t2 = t * t;
   float s = fmaf(t2, 42.058693944897634f, -76.70585975306136f);
   s = fmaf(t2, s, 81.60524927607504f);
@@ -413,6 +424,8 @@ __global__ __launch_bounds__(kThreads) void degrid_dft(KernelArgs a, int64_t sg_
                                                        const R* __restrict__ scratch,
                                                        R* __restrict__ vis) {
   using V2 = typename C2<R>::T;
+  constexpr int P = DegridPix<L>::P, CH = kThreads * P;
+  static_assert((L * L) % CH == 0, "pixel chunks must tile the subgrid");
   extern __shared__ unsigned char smem_raw[];
   R* accs = reinterpret_cast<R*>(smem_raw);
   const int local = blockIdx.x;
@@ -426,26 +439,29 @@ __global__ __launch_bounds__(kThreads) void degrid_dft(KernelArgs a, int64_t sg_
   const V2* img = reinterpret_cast<const V2*>(scratch) + (int64_t)local * 4 * L * L;
   const double u0 = (s.U0 - a.N / 2) * a.du, v0 = (s.V0 - a.N / 2) * a.du;
 
-  for (int chunk = 0; chunk < (L * L) / kChunk; ++chunk) {
-    Pixel px[kPix];
-    V2 sp[kPix][4];
+  for (int chunk = 0; chunk < (L * L) / CH; ++chunk) {
+    int pix[P];
+    double n1[P];
+    V2 sp[P][4];
 #pragma unroll
-    for (int p = 0; p < kPix; ++p) {
-      px[p] = pixel_at<L>(chunk * kChunk + p * kThreads + threadIdx.x, a.lstep);
-      const int pix = px[p].pix;
+    for (int p = 0; p < P; ++p) {
+      pix[p] = chunk * CH + p * kThreads + threadIdx.x;
+      const double l = (pix[p] % L - L / 2) * a.lstep, m = (pix[p] / L - L / 2) * a.lstep;
+      const double r2 = l * l + m * m;
+      n1[p] = -r2 / (1.0 + sqrt(1.0 - r2));
       // prologue: S' = T (-1)^(x+y) A_p S A_q^H
-      const V2* Ap = At + ((int64_t)s.ap * L * L + pix) * 4;
-      const V2* Aq = At + ((int64_t)s.aq * L * L + pix) * 4;
+      const V2* Ap = At + ((int64_t)s.ap * L * L + pix[p]) * 4;
+      const V2* Aq = At + ((int64_t)s.aq * L * L + pix[p]) * 4;
       const V2 a0 = Ap[0], a1 = Ap[1], a2 = Ap[2], a3 = Ap[3];
       V2 b0 = Aq[0], b1 = Aq[1], b2 = Aq[2], b3 = Aq[3];
       b0.y = -b0.y; b1.y = -b1.y; b2.y = -b2.y; b3.y = -b3.y;  // conj
-      const V2 s0 = img[0 * L * L + pix], s1 = img[1 * L * L + pix];
-      const V2 s2 = img[2 * L * L + pix], s3 = img[3 * L * L + pix];
+      const V2 s0 = img[0 * L * L + pix[p]], s1 = img[1 * L * L + pix[p]];
+      const V2 s2 = img[2 * L * L + pix[p]], s3 = img[3 * L * L + pix[p]];
       const V2 t0 = cmul<R>(a0, s0) + cmul<R>(a1, s2);
       const V2 t1 = cmul<R>(a0, s1) + cmul<R>(a1, s3);
       const V2 t2 = cmul<R>(a2, s0) + cmul<R>(a3, s2);
       const V2 t3 = cmul<R>(a2, s1) + cmul<R>(a3, s3);
-      const R w = taper[pix];
+      const R w = taper[pix[p]];
       // A_q^H = [[conj b0, conj b2], [conj b1, conj b3]]
       sp[p][0] = (cmul<R>(t0, b0) + cmul<R>(t1, b1)) * w;
       sp[p][1] = (cmul<R>(t0, b2) + cmul<R>(t1, b3)) * w;
@@ -455,13 +471,16 @@ __global__ __launch_bounds__(kThreads) void degrid_dft(KernelArgs a, int64_t sg_
     for (int t = 0; t < s.nt; ++t) {
       const double* uvw = a.uvw + 3 * (s.uvw0 + t);
       const double um = uvw[0], vm = uvw[1], wm = uvw[2];
-      V2 st[kPix], ph[kPix];
+      V2 st[P], ph[P];
       {
         const double su = um * s.dfc, sv = vm * s.dfc, sw = wm * s.dfc;
 #pragma unroll
-        for (int p = 0; p < kPix; ++p)
-          st[p] = phasor(-(su * px[p].l + sv * px[p].m + sw * px[p].n1), R());
+        for (int p = 0; p < P; ++p) {
+          const double l = (pix[p] % L - L / 2) * a.lstep, m = (pix[p] / L - L / 2) * a.lstep;
+          st[p] = phasor(-(su * l + sv * m + sw * n1[p]), R());
+        }
       }
+      int since_seed = s.R;  // channels since the last FP64 re-seed
       for (int g0 = 0; g0 < s.nc; g0 += kVisGroup) {
         R part[32];
 #pragma unroll
@@ -470,15 +489,19 @@ __global__ __launch_bounds__(kThreads) void degrid_dft(KernelArgs a, int64_t sg_
 #pragma unroll
           for (int i = 0; i < 8; ++i) part[8 * v + i] = 0;
           if (j < s.nc) {
-            if (j % s.R == 0) {
+            if (since_seed == s.R) {
+              since_seed = 0;
               const double fc = a.fc[s.c0 + j];
               const double cu = um * fc - u0, cv = vm * fc - v0, cw = wm * fc - s.w0;
 #pragma unroll
-              for (int p = 0; p < kPix; ++p)
-                ph[p] = phasor(-(cu * px[p].l + cv * px[p].m + cw * px[p].n1), R());
+              for (int p = 0; p < P; ++p) {
+                const double l = (pix[p] % L - L / 2) * a.lstep, m = (pix[p] / L - L / 2) * a.lstep;
+                ph[p] = phasor(-(cu * l + cv * m + cw * n1[p]), R());
+              }
             }
+            ++since_seed;
 #pragma unroll
-            for (int p = 0; p < kPix; ++p) {
+            for (int p = 0; p < P; ++p) {
 #pragma unroll
               for (int q = 0; q < 4; ++q) {
                 R re = part[8 * v + 2 * q], im = part[8 * v + 2 * q + 1];
