@@ -193,6 +193,42 @@ aidg_status aidg_plan_kernel_times(aidg_plan* plan, aidg_kernel_times* out);
 
 void aidg_plan_destroy(aidg_plan* plan);
 
+/* ---- Serving: grouped execution of work from many plans (continuous batching).
+ * Gridding and degridding decompose into independent subgrids (Sec. 2.2: the
+ * full grid is a sum over subgrids, and each visibility belongs to one), so a
+ * range of one job's subgrids can share a kernel launch with ranges of other
+ * jobs.  An executor owns a subgrid workspace on the device; aidg_execute packs
+ * the given ranges into launches of at most 16 ranges each, grouped by
+ * direction, subgrid size and precision. */
+enum { AIDG_DIR_GRID = 0, AIDG_DIR_DEGRID = 1 };
+
+typedef struct aidg_executor aidg_executor;
+
+typedef struct {
+  aidg_plan* plan;
+  int32_t direction;   /* AIDG_DIR_GRID: accumulate vis `in` into grid `out`;
+                          AIDG_DIR_DEGRID: write the visibilities of the range from grid `in`
+                          into vis `out` (a range starting at 0 also zeroes the plan's
+                          excluded visibilities) */
+  int32_t reserved;    /* 0 */
+  const void* in;      /* device buffer, layout as in aidg_grid / aidg_degrid */
+  void* out;           /* device buffer */
+  int64_t sg_begin;    /* range of the plan's subgrid table (aidg_plan_subgrids order) */
+  int64_t sg_end;
+} aidg_work;
+
+/* Create an executor with a workspace of workspace_bytes (0 = 2 GiB) on the current device. */
+aidg_status aidg_executor_create(int64_t workspace_bytes, aidg_executor** out);
+
+/* Queue the work items on hip_stream.  Ranges of one plan within a call must not
+ * overlap.  Every plan named waits for its earlier work (on any stream) first; the
+ * executor's workspace makes calls on one executor run one after another.  The call
+ * never allocates and never synchronises the host.  AIDG_E_BUSY if a plan or the
+ * executor is in use by another host thread. */
+aidg_status aidg_execute(aidg_executor* ex, const aidg_work* items, int32_t n_items, void* hip_stream);
+
+void aidg_executor_destroy(aidg_executor* ex);
+
 /* Thread-local description of the last non-OK status ("" if none). */
 const char* aidg_last_error(void);
 

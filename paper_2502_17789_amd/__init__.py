@@ -53,6 +53,13 @@ class _PlanInfo(ctypes.Structure):
 
 
 KERNEL_CLASSES = ("grid_dft", "fft_add", "split_ifft", "degrid_dft", "zero_vis")
+DIR_GRID, DIR_DEGRID = 0, 1
+
+
+class _Work(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_void_p), ("direction", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("in_", ctypes.c_void_p), ("out", ctypes.c_void_p), ("sg_begin", ctypes.c_int64),
+                ("sg_end", ctypes.c_int64)]
 
 
 class _KernelTimes(ctypes.Structure):
@@ -110,6 +117,9 @@ def library() -> ctypes.CDLL:
         "aidg_plan_set_profiling": (I32, [P, I32]),
         "aidg_plan_kernel_times": (I32, [P, P]),
         "aidg_plan_destroy": (None, [P]),
+        "aidg_executor_create": (I32, [I64, P]),
+        "aidg_execute": (I32, [P, P, I32, P]),
+        "aidg_executor_destroy": (None, [P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -268,3 +278,31 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class Executor:
+    """Grouped execution of subgrid ranges from many plans (``aidg_execute``)."""
+
+    def __init__(self, workspace_bytes: int = 0):
+        h = ctypes.c_void_p()
+        _check(library().aidg_executor_create(int(workspace_bytes), ctypes.byref(h)))
+        self._h = h
+
+    def execute(self, items, stream=None):
+        """items: iterable of (plan, direction, in_tensor, out_tensor, sg_begin, sg_end)."""
+        items = list(items)
+        arr = (_Work * max(len(items), 1))()
+        for i, (plan, direction, tin, tout, b, e) in enumerate(items):
+            arr[i] = _Work(plan._h.value, int(direction), 0, tin.data_ptr(), tout.data_ptr(), int(b), int(e))
+        _check(library().aidg_execute(self._h, arr, len(items), _stream_handle(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            library().aidg_executor_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,57 @@
+"""Differentiable gridding and degridding (torch.autograd.Function).
+
+Degridding V = D(G) and gridding G = D^H(V) are exact adjoints of each other on
+complex tensors (the gridder applies A_p^H . A_q and the forward FFT where the
+degridder applies A_p . A_q^H and the inverse FFT, with the same taper and
+phasors conjugated).  For a C-linear map y = M x, PyTorch's vector-Jacobian
+product with an incoming gradient g is M^H g, so
+    DegridFn.backward(gV) = grid(gV)       GridFn.backward(gG) = degrid(gG),
+each computed by the other hand-written kernel chain on the current stream.
+Visibilities that belong to no subgrid are ignored by gridding and set to zero
+by degridding, which keeps the pair adjoint.
+"""
+from __future__ import annotations
+
+import torch
+
+
+class DegridFn(torch.autograd.Function):
+    """V = degrid(G): grid [W, 4, N, N] -> visibilities [nbl, nt, nc, 4]."""
+
+    @staticmethod
+    def forward(ctx, grid: torch.Tensor, plan) -> torch.Tensor:
+        ctx.plan = plan
+        return plan.degrid(grid.contiguous())
+
+    @staticmethod
+    def backward(ctx, g_vis: torch.Tensor):
+        plan = ctx.plan
+        g_grid = None
+        if ctx.needs_input_grad[0]:
+            g_grid = plan.grid(g_vis.contiguous())
+        return g_grid, None
+
+
+class GridFn(torch.autograd.Function):
+    """G = grid(V): visibilities [nbl, nt, nc, 4] -> grid [W, 4, N, N]."""
+
+    @staticmethod
+    def forward(ctx, vis: torch.Tensor, plan) -> torch.Tensor:
+        ctx.plan = plan
+        return plan.grid(vis.contiguous())
+
+    @staticmethod
+    def backward(ctx, g_grid: torch.Tensor):
+        plan = ctx.plan
+        g_vis = None
+        if ctx.needs_input_grad[0]:
+            g_vis = plan.degrid(g_grid.contiguous())
+        return g_vis, None
+
+
+def degrid(grid: torch.Tensor, plan) -> torch.Tensor:
+    return DegridFn.apply(grid, plan)
+
+
+def grid(vis: torch.Tensor, plan) -> torch.Tensor:
+    return GridFn.apply(vis, plan)

@@ -52,7 +52,7 @@ std::vector<aidg_subgrid> split_large(const std::vector<aidg_subgrid>& t, int ma
                                       int nc_total);
 void kaiser_bessel_taper(int L, double beta, std::vector<double>* T);
 
-// Kernel launch parameters common to all kernels of a plan.
+// Launch parameters of one plan; the plan keeps a device copy that kernels read.
 struct KernelArgs {
   const SubgridDev* sg;     // device subgrid table
   const double* uvw;        // device [nbl][nt][3] metres
@@ -60,20 +60,36 @@ struct KernelArgs {
   const void* aterms;       // device [n_int][n_st][L][L][4]
   const void* taper;        // device [L][L] taper times (-1)^(x+y)
   const void* twiddle;      // device [L] exp(-2 pi i k / L)
-  void* scratch;            // device subgrid stack [batch][4][L][L]
   int nt_total, nc_total, N, pad;
   double du;                // uv cell size, wavelengths
   double lstep;             // FOV / L, subgrid lattice spacing in direction cosines
 };
 
+// A grouped launch: consecutive ranges of subgrids from up to kMaxGroup plans
+// share one kernel launch.  Workgroup slot s belongs to the last job whose
+// slot_begin <= s; its subgrid is sg_begin + (s - slot_begin) of that plan, and
+// its subgrid image lives at scratch slot s.
+constexpr int kMaxGroup = 16;
+struct JobRef {
+  const KernelArgs* args;   // device copy of the plan's parameters
+  const void* in;           // visibilities (gridder) or grid (splitter)
+  void* out;                // grid (adder) or visibilities (degridder)
+  int64_t sg_begin;         // first subgrid of the range in the plan's table
+  int64_t slot_begin;       // first slot of the range in this launch
+};
+struct Group {
+  int32_t n, pad;
+  int64_t total;            // slots (subgrids) in the launch
+  void* scratch;            // [total][4][L][L] subgrid images
+  JobRef job[kMaxGroup];
+};
+
 // Kernel classes, in the order of aidg_kernel_times.
 enum KernelClass { kGridDft = 0, kFftAdd = 1, kSplitIfft = 2, kDegridDft = 3, kZeroVis = 4 };
 
-// Launch one kernel class over subgrids [sg_begin, sg_begin + n_sg) (kernels.hip).
-// in/out: visibilities and scratch or grid as the class requires.  Returns a
-// hipError_t as int.
-int launch_kernel(KernelClass k, int L, int precision, const KernelArgs& a, int64_t sg_begin,
-                  int64_t n_sg, const void* in, void* out, void* stream, int max_nv);
+// Launch one kernel class over a group (kernels.hip).  max_nv: the largest
+// sub-table of the group (degridder LDS).  Returns a hipError_t as int.
+int launch_group(KernelClass k, int L, int precision, const Group& g, void* stream, int max_nv);
 int launch_zero_vis(int precision, const int64_t* idx, int64_t n, void* vis, void* stream);
 
 }  // namespace aidg

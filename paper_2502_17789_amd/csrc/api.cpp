@@ -45,6 +45,7 @@ struct aidg_plan {
   void* d_tw = nullptr;
   void* d_scratch = nullptr;
   int64_t* d_excl = nullptr;
+  KernelArgs* d_args = nullptr;  // device copy of args()
   hipEvent_t last = nullptr;
   std::atomic<bool> busy{false};
   // profiling: events around each kernel launch
@@ -67,7 +68,6 @@ struct aidg_plan {
     a.aterms = d_aterms;
     a.taper = d_taper;
     a.twiddle = d_tw;
-    a.scratch = d_scratch;
     a.nt_total = nt;
     a.nc_total = nc;
     a.N = g.N;
@@ -78,7 +78,7 @@ struct aidg_plan {
   }
 
   void release() {
-    void* ptrs[] = {d_sg, d_uvw, d_fc, d_aterms, d_taper, d_tw, d_scratch, d_excl};
+    void* ptrs[] = {d_sg, d_uvw, d_fc, d_aterms, d_taper, d_tw, d_scratch, d_excl, d_args};
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
     if (last) (void)hipEventDestroy(last);
@@ -89,8 +89,17 @@ struct aidg_plan {
     d_uvw = d_fc = nullptr;
     d_aterms = d_taper = d_tw = d_scratch = nullptr;
     d_excl = nullptr;
+    d_args = nullptr;
     last = nullptr;
   }
+};
+
+struct aidg_executor {
+  void* d_scratch = nullptr;
+  int64_t bytes = 0;
+  int device = 0;
+  hipEvent_t last = nullptr;
+  std::atomic<bool> busy{false};
 };
 
 namespace {
@@ -109,29 +118,44 @@ struct BusyGuard {
 
 bool gpu_subgrid_size(int L) { return L == 32 || L == 64 || L == 96; }
 
-// Launch one kernel class over a batch, bracketed by timing events when profiling.
+// Record a timing event pair around a launch when the plan is profiling.
+struct TimedLaunch {
+  aidg_plan* p;
+  hipStream_t st;
+  hipEvent_t ea = nullptr, eb = nullptr;
+  TimedLaunch(aidg_plan* plan, hipStream_t stream) : p(plan), st(stream) {
+    if (p && p->profiling && p->pool_next + 2 <= p->pool.size()) {
+      ea = p->pool[p->pool_next++];
+      eb = p->pool[p->pool_next++];
+      (void)hipEventRecord(ea, st);
+    }
+  }
+  void done(KernelClass k, int64_t vp, int64_t nsg) {
+    if (!ea) return;
+    (void)hipEventRecord(eb, st);
+    p->timed.push_back({(int)k, vp, nsg, ea, eb});
+  }
+};
+
+// Launch one kernel class over subgrids [b0, b0 + n) of one plan.
 aidg_status run(aidg_plan* p, KernelClass k, int64_t b0, int64_t n, const void* in, void* out,
                 void* stream) {
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  hipEvent_t ea = nullptr, eb = nullptr;
-  if (p->profiling && p->pool_next + 2 <= p->pool.size()) {
-    ea = p->pool[p->pool_next++];
-    eb = p->pool[p->pool_next++];
-    const hipError_t e = hipEventRecord(ea, st);
-    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
-  }
+  TimedLaunch tl(p, st);
   int rc;
-  if (k == kZeroVis)
+  if (k == kZeroVis) {
     rc = launch_zero_vis(p->g.precision, p->d_excl, p->n_excluded, out, stream);
-  else
-    rc = launch_kernel(k, p->g.L, p->g.precision, p->args(), b0, n, in, out, stream, p->max_nv);
-  if (rc != 0) return hip_fail((hipError_t)rc, "kernel launch");
-  if (ea) {
-    const hipError_t e = hipEventRecord(eb, st);
-    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
-    const int64_t vp = k == kZeroVis ? 0 : p->vp_prefix[b0 + n] - p->vp_prefix[b0];
-    p->timed.push_back({(int)k, vp, k == kZeroVis ? 0 : n, ea, eb});
+  } else {
+    Group g;
+    std::memset(&g, 0, sizeof(g));
+    g.n = 1;
+    g.total = n;
+    g.scratch = p->d_scratch;
+    g.job[0] = {p->d_args, in, out, b0, 0};
+    rc = launch_group(k, p->g.L, p->g.precision, g, stream, p->max_nv);
   }
+  if (rc != 0) return hip_fail((hipError_t)rc, "kernel launch");
+  tl.done(k, k == kZeroVis ? 0 : p->vp_prefix[b0 + n] - p->vp_prefix[b0], k == kZeroVis ? 0 : n);
   return AIDG_OK;
 }
 
@@ -334,11 +358,13 @@ aidg_status aidg_plan_create(const aidg_geometry* geo, int32_t n_stations, int32
         (st = dalloc(&plan->d_taper, (size_t)L * L * (f32 ? 4 : 8), plan, "taper")) ||
         (st = dalloc(&plan->d_tw, (size_t)L * (f32 ? 8 : 16), plan, "twiddles")) ||
         (st = dalloc(&plan->d_excl, pr.excluded.size() * sizeof(int64_t), plan, "excluded list")) ||
-        (st = dalloc(&plan->d_scratch, plan->scratch_bytes, plan, "subgrid workspace"))) {
+        (st = dalloc(&plan->d_scratch, plan->scratch_bytes, plan, "subgrid workspace")) ||
+        (st = dalloc(&plan->d_args, sizeof(KernelArgs), plan, "launch parameters"))) {
       plan->release();
       delete plan;
       return st;
     }
+    const KernelArgs host_args = plan->args();
     struct Copy {
       void* dst;
       const void* src;
@@ -354,6 +380,7 @@ aidg_status aidg_plan_create(const aidg_geometry* geo, int32_t n_stations, int32
         {plan->d_tw, f32 ? (const void*)twf.data() : (const void*)tw.data(), (size_t)L * (f32 ? 8 : 16),
          hipMemcpyHostToDevice},
         {plan->d_excl, pr.excluded.data(), pr.excluded.size() * sizeof(int64_t), hipMemcpyHostToDevice},
+        {plan->d_args, &host_args, sizeof(KernelArgs), hipMemcpyHostToDevice},
     };
     for (const Copy& c : copies) {
       if (!c.n) continue;
@@ -501,6 +528,130 @@ aidg_status aidg_plan_kernel_times(aidg_plan* plan, aidg_kernel_times* out) {
   plan->timed.clear();
   plan->pool_next = 0;
   return AIDG_OK;
+}
+
+aidg_status aidg_executor_create(int64_t workspace_bytes, aidg_executor** out) {
+  if (!out || workspace_bytes < 0) return fail(AIDG_E_INVALID, "NULL output or negative size");
+  *out = nullptr;
+  aidg_executor* ex = new (std::nothrow) aidg_executor();
+  if (!ex) return fail(AIDG_E_NOMEM, "host allocation failed");
+  ex->bytes = workspace_bytes ? workspace_bytes : kWorkspaceDefault;
+  hipError_t e = hipGetDevice(&ex->device);
+  if (e == hipSuccess) e = hipMalloc(&ex->d_scratch, (size_t)ex->bytes);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&ex->last, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    if (ex->d_scratch) (void)hipFree(ex->d_scratch);
+    delete ex;
+    return fail(e == hipErrorOutOfMemory ? AIDG_E_NOMEM : AIDG_E_DEVICE,
+                std::string("executor workspace: ") + hipGetErrorString(e));
+  }
+  *out = ex;
+  return AIDG_OK;
+}
+
+aidg_status aidg_execute(aidg_executor* ex, const aidg_work* items, int32_t n_items, void* hip_stream) {
+  if (!ex || (n_items > 0 && !items) || n_items < 0) return fail(AIDG_E_INVALID, "bad executor or items");
+  for (int32_t i = 0; i < n_items; ++i) {
+    const aidg_work& w = items[i];
+    if (!w.plan || !w.in || !w.out || (w.direction != AIDG_DIR_GRID && w.direction != AIDG_DIR_DEGRID) ||
+        w.sg_begin < 0 || w.sg_end < w.sg_begin || w.sg_end > (int64_t)w.plan->table.size())
+      return fail(AIDG_E_INVALID, "work item " + std::to_string(i) + ": bad plan, buffers, direction or range");
+  }
+  bool expected = false;
+  if (!ex->busy.compare_exchange_strong(expected, true)) return fail(AIDG_E_BUSY, "executor in use");
+  std::vector<aidg_plan*> plans;
+  for (int32_t i = 0; i < n_items; ++i)
+    if (std::find(plans.begin(), plans.end(), items[i].plan) == plans.end()) plans.push_back(items[i].plan);
+  size_t held = 0;
+  for (; held < plans.size(); ++held) {
+    bool ex2 = false;
+    if (!plans[held]->busy.compare_exchange_strong(ex2, true)) break;
+  }
+  auto release = [&]() {
+    for (size_t k = 0; k < held; ++k) plans[k]->busy.store(false);
+    ex->busy.store(false);
+  };
+  if (held < plans.size()) {
+    release();
+    return fail(AIDG_E_BUSY, "a plan is in use by another thread");
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  aidg_status r = AIDG_OK;
+  hipError_t e = hipStreamWaitEvent(st, ex->last, 0);
+  for (aidg_plan* p : plans)
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, p->last, 0);
+  if (e != hipSuccess) r = hip_fail(e, "hipStreamWaitEvent");
+  // degridding ranges that start the table also clear the excluded visibilities
+  for (int32_t i = 0; i < n_items && r == AIDG_OK; ++i) {
+    const aidg_work& w = items[i];
+    if (w.direction == AIDG_DIR_DEGRID && w.sg_begin == 0 && w.plan->n_excluded > 0) {
+      const int rc = launch_zero_vis(w.plan->g.precision, w.plan->d_excl, w.plan->n_excluded, w.out,
+                                     hip_stream);
+      if (rc != 0) r = hip_fail((hipError_t)rc, "zeroing excluded visibilities");
+    }
+  }
+  // group by (direction, L, precision); pack ranges into launches
+  std::vector<bool> done(n_items, false);
+  for (int32_t i0 = 0; i0 < n_items && r == AIDG_OK; ++i0) {
+    if (done[i0]) continue;
+    const int dir = items[i0].direction, L = items[i0].plan->g.L, prec = items[i0].plan->g.precision;
+    const int64_t per_sg = (int64_t)4 * L * L * (prec == AIDG_FP32 ? 8 : 16);
+    const int64_t cap = std::min<int64_t>(ex->bytes / per_sg, 65535);
+    if (cap < 1) {
+      r = fail(AIDG_E_INVALID, "executor workspace smaller than one subgrid");
+      break;
+    }
+    Group g;
+    std::memset(&g, 0, sizeof(g));
+    g.scratch = ex->d_scratch;
+    int max_nv = 1;
+    auto flush = [&]() -> aidg_status {
+      if (g.total == 0) return AIDG_OK;
+      const KernelClass k0 = dir == AIDG_DIR_GRID ? kGridDft : kSplitIfft;
+      const KernelClass k1 = dir == AIDG_DIR_GRID ? kFftAdd : kDegridDft;
+      int rc = launch_group(k0, L, prec, g, hip_stream, max_nv);
+      if (rc == 0) rc = launch_group(k1, L, prec, g, hip_stream, max_nv);
+      std::memset(&g, 0, sizeof(g));
+      g.scratch = ex->d_scratch;
+      max_nv = 1;
+      return rc == 0 ? AIDG_OK : hip_fail((hipError_t)rc, "grouped kernel launch");
+    };
+    for (int32_t i = i0; i < n_items && r == AIDG_OK; ++i) {
+      const aidg_work& w = items[i];
+      if (done[i] || w.direction != dir || w.plan->g.L != L || w.plan->g.precision != prec) continue;
+      done[i] = true;
+      for (int64_t b = w.sg_begin; b < w.sg_end && r == AIDG_OK;) {
+        if (g.n == kMaxGroup || g.total == cap) r = flush();
+        if (r != AIDG_OK) break;
+        const int64_t take = std::min(w.sg_end - b, cap - g.total);
+        g.job[g.n] = {w.plan->d_args, w.in, w.out, b, g.total};
+        g.n += 1;
+        g.total += take;
+        max_nv = std::max(max_nv, w.plan->max_nv);
+        b += take;
+      }
+    }
+    if (r == AIDG_OK) r = flush();
+  }
+  if (r == AIDG_OK) {
+    e = hipEventRecord(ex->last, st);
+    for (aidg_plan* p : plans)
+      if (e == hipSuccess) e = hipEventRecord(p->last, st);
+    if (e != hipSuccess) r = hip_fail(e, "hipEventRecord");
+  }
+  release();
+  return r;
+}
+
+void aidg_executor_destroy(aidg_executor* ex) {
+  if (!ex) return;
+  if (ex->last) {
+    (void)hipEventSynchronize(ex->last);
+    (void)hipEventDestroy(ex->last);
+  }
+  if (ex->d_scratch) (void)hipFree(ex->d_scratch);
+  delete ex;
 }
 
 void aidg_plan_destroy(aidg_plan* plan) {

@@ -112,15 +112,73 @@ __device__ __forceinline__ Pixel pixel_at(int pix, double lstep) {
   return p;
 }
 
+// Values every lane of a wave holds identically, moved to scalar registers word
+// by word so that loop bounds and addresses derived from them stay wave-uniform
+// (scalar branches, scalar loads of visibilities and uvw).
+template <typename T>
+__device__ __forceinline__ T uniform(const T& v) {
+  static_assert(sizeof(T) % 4 == 0, "word-sized");
+  int w[sizeof(T) / 4];
+  __builtin_memcpy(w, &v, sizeof(T));
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+  T r;
+  __builtin_memcpy(&r, w, sizeof(T));
+  return r;
+}
+
+// Read-only view of memory no kernel writes while the launch runs: wave-uniform
+// loads through it become scalar loads (the scalar data cache broadcasts them).
+template <typename T>
+using const_view = const __attribute__((address_space(4))) T*;
+template <typename T>
+__device__ __forceinline__ const_view<T> as_const(const T* p) {
+  return (const_view<T>)(uintptr_t)p;
+}
+
+// A record every lane reads from the same address: scalar loads word by word.
+template <typename T>
+__device__ __forceinline__ T load_uniform(const T* p) {
+  static_assert(sizeof(T) % 4 == 0, "word-sized");
+  const_view<int> q = as_const(reinterpret_cast<const int*>(p));
+  int w[sizeof(T) / 4];
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) w[i] = __builtin_amdgcn_readfirstlane(q[i]);
+  T r;
+  __builtin_memcpy(&r, w, sizeof(T));
+  return r;
+}
+
+// The job of a workgroup slot in a grouped launch, its parameters and subgrid.
+struct Slot {
+  KernelArgs a;
+  SubgridDev s;
+  const void* in;
+  void* out;
+};
+__device__ __forceinline__ Slot resolve(const Group& g, int64_t slot) {
+  int j = 0;
+  for (int i = 1; i < g.n; ++i)
+    if (slot >= g.job[i].slot_begin) j = i;
+  Slot r;
+  r.a = load_uniform(g.job[j].args);
+  r.s = load_uniform(r.a.sg + g.job[j].sg_begin + (slot - g.job[j].slot_begin));
+  r.in = uniform(g.job[j].in);
+  r.out = uniform(g.job[j].out);
+  return r;
+}
+
 // ------------------------------------------------------------------ gridder
 
 template <int L, typename R>
-__global__ __launch_bounds__(kThreads) void grid_dft(KernelArgs a, int64_t sg_begin,
-                                                     const R* __restrict__ vis,
-                                                     R* __restrict__ scratch) {
+__global__ __launch_bounds__(kThreads) void grid_dft(const Group g) {
   using V2 = typename C2<R>::T;
-  const int local = blockIdx.y;
-  const SubgridDev s = a.sg[sg_begin + local];
+  const int64_t local = blockIdx.y;
+  const Slot sl = resolve(g, local);
+  const KernelArgs& a = sl.a;
+  const SubgridDev& s = sl.s;
+  const R* __restrict__ vis = reinterpret_cast<const R*>(sl.in);
+  R* __restrict__ scratch = reinterpret_cast<R*>(g.scratch);
   Pixel px[kPix];
 #pragma unroll
   for (int p = 0; p < kPix; ++p)
@@ -134,9 +192,9 @@ __global__ __launch_bounds__(kThreads) void grid_dft(KernelArgs a, int64_t sg_be
 
   const double u0 = (s.U0 - a.N / 2) * a.du, v0 = (s.V0 - a.N / 2) * a.du;
   for (int t = 0; t < s.nt; ++t) {
-    const double* uvw = a.uvw + 3 * (s.uvw0 + t);
+    const_view<double> uvw = as_const(a.uvw + 3 * (s.uvw0 + t));
     const double um = uvw[0], vm = uvw[1], wm = uvw[2];
-    const R* vrow = vis + 8 * (s.vis0 + (int64_t)t * a.nc_total);
+    const_view<R> vrow = as_const(vis + 8 * (s.vis0 + (int64_t)t * a.nc_total));
     V2 st[kPix], ph[kPix];
     {
       const double su = um * s.dfc, sv = vm * s.dfc, sw = wm * s.dfc;
@@ -144,13 +202,13 @@ __global__ __launch_bounds__(kThreads) void grid_dft(KernelArgs a, int64_t sg_be
       for (int p = 0; p < kPix; ++p) st[p] = phasor(su * px[p].l + sv * px[p].m + sw * px[p].n1, R());
     }
     for (int j0 = 0; j0 < s.nc; j0 += s.R) {
-      const double fc = a.fc[s.c0 + j0];
+      const double fc = as_const(a.fc)[s.c0 + j0];
       const double cu = um * fc - u0, cv = vm * fc - v0, cw = wm * fc - s.w0;
 #pragma unroll
       for (int p = 0; p < kPix; ++p) ph[p] = phasor(cu * px[p].l + cv * px[p].m + cw * px[p].n1, R());
       const int jn = min(s.nc, j0 + s.R);
       for (int j = j0; j < jn; ++j) {
-        const R* v = vrow + 8 * j;
+        const_view<R> v = vrow + 8 * j;
         R vv[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) vv[i] = v[i];
@@ -172,7 +230,7 @@ __global__ __launch_bounds__(kThreads) void grid_dft(KernelArgs a, int64_t sg_be
   // epilogue: S' = T (-1)^(x+y) A_p^H S A_q, one plane per polarisation
   const V2* At = reinterpret_cast<const V2*>(a.aterms);
   const R* taper = reinterpret_cast<const R*>(a.taper);
-  V2* out = reinterpret_cast<V2*>(scratch) + (int64_t)local * 4 * L * L;
+  V2* out = reinterpret_cast<V2*>(scratch) + local * 4 * L * L;
 #pragma unroll
   for (int p = 0; p < kPix; ++p) {
     const int pix = px[p].pix;
@@ -286,44 +344,50 @@ __device__ __forceinline__ void fft_lines(V2* buf, const V2* tw) {
 }
 
 template <int L, typename R>
-__global__ __launch_bounds__(kThreads) void fft_add(KernelArgs a, int64_t sg_begin,
-                                                    const R* __restrict__ scratch, R* grid) {
+__global__ __launch_bounds__(kThreads) void fft_add(const Group g) {
   using V2 = typename C2<R>::T;
   __shared__ V2 buf[L * pitch(L)];
   __shared__ V2 tw[L];
-  const int pol = blockIdx.x, local = blockIdx.y;
-  const SubgridDev s = a.sg[sg_begin + local];
-  const V2* in = reinterpret_cast<const V2*>(scratch) + ((int64_t)local * 4 + pol) * L * L;
+  const int pol = blockIdx.x;
+  const int64_t local = blockIdx.y;
+  const Slot sl = resolve(g, local);
+  const KernelArgs& a = sl.a;
+  const SubgridDev& s = sl.s;
+  R* grid = reinterpret_cast<R*>(sl.out);
+  const V2* in = reinterpret_cast<const V2*>(g.scratch) + (local * 4 + pol) * L * L;
   for (int e = threadIdx.x; e < L * L; e += kThreads) buf[(e / L) * pitch(L) + e % L] = in[e];
   for (int e = threadIdx.x; e < L; e += kThreads) tw[e] = reinterpret_cast<const V2*>(a.twiddle)[e];
   __syncthreads();
   fft_lines<L, -1, true>(buf, tw);
   fft_lines<L, -1, false>(buf, tw);
-  R* g = grid + 2 * ((((int64_t)s.wlayer * 4 + pol) * a.N + (s.V0 - L / 2)) * a.N + (s.U0 - L / 2));
+  R* win = grid + 2 * ((((int64_t)s.wlayer * 4 + pol) * a.N + (s.V0 - L / 2)) * a.N + (s.U0 - L / 2));
   for (int e = threadIdx.x; e < L * L; e += kThreads) {
     const int b = e / L, c = e % L;
     V2 val = buf[b * pitch(L) + c];
     if ((b + c) & 1) val = -val;
-    R* dst = g + 2 * ((int64_t)b * a.N + c);
+    R* dst = win + 2 * ((int64_t)b * a.N + c);
     unsafeAtomicAdd(dst, val.x);
     unsafeAtomicAdd(dst + 1, val.y);
   }
 }
 
 template <int L, typename R>
-__global__ __launch_bounds__(kThreads) void split_ifft(KernelArgs a, int64_t sg_begin,
-                                                       const R* __restrict__ grid,
-                                                       R* __restrict__ scratch) {
+__global__ __launch_bounds__(kThreads) void split_ifft(const Group g) {
   using V2 = typename C2<R>::T;
   __shared__ V2 buf[L * pitch(L)];
   __shared__ V2 tw[L];
-  const int pol = blockIdx.x, local = blockIdx.y;
-  const SubgridDev s = a.sg[sg_begin + local];
-  const V2* g = reinterpret_cast<const V2*>(grid) +
-                (((int64_t)s.wlayer * 4 + pol) * a.N + (s.V0 - L / 2)) * a.N + (s.U0 - L / 2);
+  const int pol = blockIdx.x;
+  const int64_t local = blockIdx.y;
+  const Slot sl = resolve(g, local);
+  const KernelArgs& a = sl.a;
+  const SubgridDev& s = sl.s;
+  const R* __restrict__ grid = reinterpret_cast<const R*>(sl.in);
+  R* __restrict__ scratch = reinterpret_cast<R*>(g.scratch);
+  const V2* win = reinterpret_cast<const V2*>(grid) +
+                  (((int64_t)s.wlayer * 4 + pol) * a.N + (s.V0 - L / 2)) * a.N + (s.U0 - L / 2);
   for (int e = threadIdx.x; e < L * L; e += kThreads) {
     const int b = e / L, c = e % L;
-    V2 val = g[(int64_t)b * a.N + c];
+    V2 val = win[(int64_t)b * a.N + c];
     if ((b + c) & 1) val = -val;
     buf[b * pitch(L) + c] = val;
   }
@@ -331,7 +395,7 @@ __global__ __launch_bounds__(kThreads) void split_ifft(KernelArgs a, int64_t sg_
   __syncthreads();
   fft_lines<L, +1, true>(buf, tw);
   fft_lines<L, +1, false>(buf, tw);
-  V2* out = reinterpret_cast<V2*>(scratch) + ((int64_t)local * 4 + pol) * L * L;
+  V2* out = reinterpret_cast<V2*>(scratch) + (local * 4 + pol) * L * L;
   for (int e = threadIdx.x; e < L * L; e += kThreads) out[e] = buf[(e / L) * pitch(L) + e % L];
 }
 
@@ -420,23 +484,25 @@ __device__ __forceinline__ R transpose_reduce32(R (&a)[32], int ln) {
 }
 
 template <int L, typename R>
-__global__ __launch_bounds__(kThreads) void degrid_dft(KernelArgs a, int64_t sg_begin,
-                                                       const R* __restrict__ scratch,
-                                                       R* __restrict__ vis) {
+__global__ __launch_bounds__(kThreads) void degrid_dft(const Group g) {
   using V2 = typename C2<R>::T;
   constexpr int P = DegridPix<L>::P, CH = kThreads * P;
   static_assert((L * L) % CH == 0, "pixel chunks must tile the subgrid");
   extern __shared__ unsigned char smem_raw[];
   R* accs = reinterpret_cast<R*>(smem_raw);
-  const int local = blockIdx.x;
-  const SubgridDev s = a.sg[sg_begin + local];
+  const int64_t local = blockIdx.x;
+  const Slot sl = resolve(g, local);
+  const KernelArgs& a = sl.a;
+  const SubgridDev& s = sl.s;
+  const R* __restrict__ scratch = reinterpret_cast<const R*>(g.scratch);
+  R* __restrict__ vis = reinterpret_cast<R*>(sl.out);
   const int nv = s.nt * s.nc;
   for (int i = threadIdx.x; i < nv * 8; i += kThreads) accs[i] = 0;
   __syncthreads();
   const int ln = threadIdx.x & 63;
   const V2* At = reinterpret_cast<const V2*>(a.aterms);
   const R* taper = reinterpret_cast<const R*>(a.taper);
-  const V2* img = reinterpret_cast<const V2*>(scratch) + (int64_t)local * 4 * L * L;
+  const V2* img = reinterpret_cast<const V2*>(scratch) + local * 4 * L * L;
   const double u0 = (s.U0 - a.N / 2) * a.du, v0 = (s.V0 - a.N / 2) * a.du;
 
   for (int chunk = 0; chunk < (L * L) / CH; ++chunk) {
@@ -469,7 +535,7 @@ __global__ __launch_bounds__(kThreads) void degrid_dft(KernelArgs a, int64_t sg_
       sp[p][3] = (cmul<R>(t2, b2) + cmul<R>(t3, b3)) * w;
     }
     for (int t = 0; t < s.nt; ++t) {
-      const double* uvw = a.uvw + 3 * (s.uvw0 + t);
+      const_view<double> uvw = as_const(a.uvw + 3 * (s.uvw0 + t));
       const double um = uvw[0], vm = uvw[1], wm = uvw[2];
       V2 st[P], ph[P];
       {
@@ -491,7 +557,7 @@ __global__ __launch_bounds__(kThreads) void degrid_dft(KernelArgs a, int64_t sg_
           if (j < s.nc) {
             if (since_seed == s.R) {
               since_seed = 0;
-              const double fc = a.fc[s.c0 + j];
+              const double fc = as_const(a.fc)[s.c0 + j];
               const double cu = um * fc - u0, cv = vm * fc - v0, cw = wm * fc - s.w0;
 #pragma unroll
               for (int p = 0; p < P; ++p) {
@@ -536,26 +602,21 @@ __global__ void zero_vis(const int64_t* __restrict__ idx, int64_t n, R* vis) {
 }
 
 template <int L, typename R>
-int launch_one(KernelClass k, const KernelArgs& a, int64_t sg_begin, int64_t n_sg, const void* in,
-               void* out, hipStream_t st, int max_nv) {
-  R* scratch = reinterpret_cast<R*>(a.scratch);
-  const unsigned n = (unsigned)n_sg;
+int launch_one(KernelClass k, const Group& g, hipStream_t st, int max_nv) {
+  const unsigned n = (unsigned)g.total;
   switch (k) {
     case kGridDft:
-      hipLaunchKernelGGL((grid_dft<L, R>), dim3((L * L) / kChunk, n), dim3(kThreads), 0, st, a,
-                         sg_begin, reinterpret_cast<const R*>(in), scratch);
+      hipLaunchKernelGGL((grid_dft<L, R>), dim3((L * L) / kChunk, n), dim3(kThreads), 0, st, g);
       break;
     case kFftAdd:
-      hipLaunchKernelGGL((fft_add<L, R>), dim3(4, n), dim3(kThreads), 0, st, a, sg_begin,
-                         (const R*)scratch, reinterpret_cast<R*>(out));
+      hipLaunchKernelGGL((fft_add<L, R>), dim3(4, n), dim3(kThreads), 0, st, g);
       break;
     case kSplitIfft:
-      hipLaunchKernelGGL((split_ifft<L, R>), dim3(4, n), dim3(kThreads), 0, st, a, sg_begin,
-                         reinterpret_cast<const R*>(in), scratch);
+      hipLaunchKernelGGL((split_ifft<L, R>), dim3(4, n), dim3(kThreads), 0, st, g);
       break;
     case kDegridDft:
       hipLaunchKernelGGL((degrid_dft<L, R>), dim3(n), dim3(kThreads), (size_t)max_nv * 8 * sizeof(R),
-                         st, a, sg_begin, (const R*)scratch, reinterpret_cast<R*>(out));
+                         st, g);
       break;
     default:
       return (int)hipErrorInvalidValue;
@@ -565,21 +626,20 @@ int launch_one(KernelClass k, const KernelArgs& a, int64_t sg_begin, int64_t n_s
 
 }  // namespace
 
-int launch_kernel(KernelClass k, int L, int precision, const KernelArgs& a, int64_t sg_begin,
-                  int64_t n_sg, const void* in, void* out, void* stream, int max_nv) {
+int launch_group(KernelClass k, int L, int precision, const Group& g, void* stream, int max_nv) {
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  if (n_sg <= 0) return 0;
+  if (g.total <= 0 || g.n < 1 || g.n > kMaxGroup) return g.total <= 0 ? 0 : (int)hipErrorInvalidValue;
   if (precision == AIDG_FP32) {
     switch (L) {
-      case 32: return launch_one<32, float>(k, a, sg_begin, n_sg, in, out, st, max_nv);
-      case 64: return launch_one<64, float>(k, a, sg_begin, n_sg, in, out, st, max_nv);
-      case 96: return launch_one<96, float>(k, a, sg_begin, n_sg, in, out, st, max_nv);
+      case 32: return launch_one<32, float>(k, g, st, max_nv);
+      case 64: return launch_one<64, float>(k, g, st, max_nv);
+      case 96: return launch_one<96, float>(k, g, st, max_nv);
     }
   } else {
     switch (L) {
-      case 32: return launch_one<32, double>(k, a, sg_begin, n_sg, in, out, st, max_nv);
-      case 64: return launch_one<64, double>(k, a, sg_begin, n_sg, in, out, st, max_nv);
-      case 96: return launch_one<96, double>(k, a, sg_begin, n_sg, in, out, st, max_nv);
+      case 32: return launch_one<32, double>(k, g, st, max_nv);
+      case 64: return launch_one<64, double>(k, g, st, max_nv);
+      case 96: return launch_one<96, double>(k, g, st, max_nv);
     }
   }
   return (int)hipErrorInvalidValue;

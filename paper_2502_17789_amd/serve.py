@@ -1,0 +1,340 @@
+"""Serving loop for gridding and degridding jobs: continuous batching on one GPU.
+
+Jobs of uneven size (different observations, grids, subgrid sizes, directions)
+arrive at any time.  The server:
+  * admits queued jobs first-in first-out while the sum of their device
+    footprints (plan metadata and A-terms, input, output) stays within an HBM
+    budget, and refuses a job that could never fit;
+  * builds each admitted job's plan (host partition + upload) and its device
+    buffers, and keeps them resident until the job completes;
+  * every scheduling round takes one range of subgrids from every admitted job
+    (round-robin) and hands all ranges to one grouped execution call, which
+    packs them into shared kernel launches (gridding decomposes into
+    independent subgrids, Sec. 2.2).  A job that arrives while others run is
+    in the very next round; a large job is interleaved with small ones instead
+    of blocking them;
+  * keeps a bounded number of rounds queued on the stream, retires a job when
+    the round holding its last range has finished, records its latency
+    (arrival to output final on the device) and frees its memory, which lets
+    the next queued jobs in.
+
+The device work is done by a backend (``GpuBackend``: the HIP library through
+``Plan`` and ``Executor``); the scheduler itself only orders work, so it can be
+exercised with any object that provides the same methods.
+"""
+from __future__ import annotations
+
+import collections
+import concurrent.futures
+import dataclasses
+import math
+import threading
+import time
+
+import numpy as np
+
+from . import DIR_DEGRID, DIR_GRID, FP32, Executor, Geometry, Plan
+
+
+@dataclasses.dataclass
+class Job:
+    """One gridding ("grid": data = visibilities [nbl, nt, nc, 4]) or degridding
+    ("degrid": data = grid [W, 4, N, N]) request."""
+
+    direction: str
+    geometry: Geometry
+    n_stations: int
+    baselines: np.ndarray
+    uvw: np.ndarray
+    freqs: np.ndarray
+    aterms: object   # host complex array or device tensor [n_int, n_st, L, L, 4]
+    data: object     # host array or device tensor
+    tag: object = None
+    table: object = None   # optional caller partition (aidg_subgrid records)
+
+
+@dataclasses.dataclass
+class JobResult:
+    output: object          # device tensor: grid (gridding) or visibilities (degridding)
+    tag: object
+    n_vis: int
+    n_subgrids: int
+    arrival: float
+    admitted: float
+    finished: float
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+class _Active:
+    __slots__ = ("job", "future", "handle", "n_sg", "next_sg", "arrival", "admitted", "footprint",
+                 "last_token")
+
+    def __init__(self, job, future, arrival):
+        self.job, self.future, self.arrival = job, future, arrival
+        self.handle = None
+        self.n_sg = self.next_sg = 0
+        self.admitted = 0.0
+        self.footprint = 0
+        self.last_token = None
+
+
+def job_footprint_estimate(job: Job) -> int:
+    """Device bytes a job holds while admitted: grid, visibilities, A-term copy,
+    uvw and subgrid records (upper bound on the number of w-layers)."""
+    g = job.geometry
+    elem = 8 if g.precision == FP32 else 16
+    nbl, nt, nc = job.baselines.shape[0], job.uvw.shape[1], job.freqs.shape[0]
+    n_vis = nbl * nt * nc
+    n_int = (nt + g.aterm_interval - 1) // g.aterm_interval
+    fov = g.grid_size * g.pixel_scale
+    if g.w_step > 0:
+        w_step = g.w_step
+    elif g.w_step == 0 and g.kernel_support > 0:
+        r = fov / math.sqrt(2.0)
+        w_step = 2 * g.kernel_support / (4 * fov * r / math.sqrt(1 - r * r))
+    else:
+        w_step = 0.0
+    wmax = float(np.abs(job.uvw[..., 2]).max(initial=0.0)) * float(job.freqs.max()) / 299792458.0
+    W = 2 * int(math.ceil(wmax / w_step)) + 1 if w_step > 0 else 1
+    grid_b = W * 4 * g.grid_size ** 2 * elem
+    vis_b = n_vis * 4 * elem
+    aterm_b = n_int * job.n_stations * g.subgrid_size ** 2 * 4 * elem
+    meta_b = nbl * nt * 24 + n_vis * 80 // 4 + 4 * g.subgrid_size ** 2 * elem
+    return int(grid_b + vis_b + aterm_b + meta_b)
+
+
+class GpuBackend:
+    """Device side of the server: plans, buffers and grouped execution.  Plans and
+    inputs are uploaded on their own stream; the compute stream waits for them."""
+
+    def __init__(self, workspace_bytes: int = 1 << 30, stream=None):
+        import torch
+        self.torch = torch
+        self.compute = stream if stream is not None else torch.cuda.current_stream()
+        self.upload = torch.cuda.Stream()
+        self.executor = Executor(workspace_bytes)
+
+    def footprint(self, job: Job) -> int:
+        return job_footprint_estimate(job)
+
+    def prepare(self, job: Job):
+        torch = self.torch
+        g = dataclasses.replace(job.geometry)
+        elem = 8 if g.precision == FP32 else 16
+        g.workspace_bytes = 4 * g.subgrid_size ** 2 * elem   # the executor holds the workspace
+        cdt = torch.complex64 if g.precision == FP32 else torch.complex128
+        with torch.cuda.stream(self.upload):
+            A = job.aterms if isinstance(job.aterms, torch.Tensor) else \
+                torch.from_numpy(np.ascontiguousarray(job.aterms)).to(cdt).cuda()
+            plan = Plan(g, job.n_stations, job.baselines, job.uvw, job.freqs, A.contiguous(),
+                        table=job.table, stream=self.upload)
+            data = job.data if isinstance(job.data, torch.Tensor) else \
+                torch.from_numpy(np.ascontiguousarray(job.data)).to(cdt).cuda()
+            if job.direction == "grid":
+                out = torch.zeros(plan.grid_shape(), dtype=cdt, device="cuda")
+            else:
+                out = torch.empty(plan.vis_shape(), dtype=cdt, device="cuda")
+            ready = torch.cuda.Event()
+            ready.record(self.upload)
+        self.compute.wait_event(ready)
+        return {"plan": plan, "in": data.contiguous(), "out": out, "dir":
+                DIR_GRID if job.direction == "grid" else DIR_DEGRID}
+
+    def n_subgrids(self, h) -> int:
+        return int(h["plan"].info["n_subgrids"])
+
+    def n_vis(self, h) -> int:
+        return int(h["plan"].info["n_vis"])
+
+    def execute(self, ranges):
+        """ranges: list of (handle, sg_begin, sg_end); returns a completion token."""
+        torch = self.torch
+        self.executor.execute([(h["plan"], h["dir"], h["in"], h["out"], b, e) for h, b, e in ranges],
+                              stream=self.compute)
+        ev = torch.cuda.Event()
+        ev.record(self.compute)
+        return ev
+
+    def done(self, token) -> bool:
+        return token.query()
+
+    def wait(self, token):
+        token.synchronize()
+
+    def output(self, h):
+        return h["out"]
+
+    def release(self, h):
+        h["plan"].close()
+        h.clear()
+
+
+class Server:
+    """Continuous-batching request loop (see module docstring)."""
+
+    def __init__(self, backend=None, hbm_budget: int | None = None, range_subgrids: int = 2048,
+                 rounds_in_flight: int = 2, clock=time.perf_counter):
+        self.backend = backend if backend is not None else GpuBackend()
+        if hbm_budget is None:
+            import torch
+            free, _ = torch.cuda.mem_get_info()
+            hbm_budget = int(0.75 * free)
+        self.hbm_budget = int(hbm_budget)
+        self.range_subgrids = int(range_subgrids)
+        self.rounds_in_flight = int(rounds_in_flight)
+        self.clock = clock
+        self._queue: collections.deque[_Active] = collections.deque()
+        self._active: list[_Active] = []
+        self._rounds: collections.deque = collections.deque()   # (token, [jobs retiring])
+        self._in_use = 0
+        self._cv = threading.Condition()
+        self._thread = None
+        self._stop = False
+        self.completed: list[JobResult] = []
+        self.peak_in_use = 0
+        self.rounds = 0
+
+    # ------------------------------------------------------------ client side
+    def submit(self, job: Job) -> concurrent.futures.Future:
+        fut: concurrent.futures.Future = concurrent.futures.Future()
+        with self._cv:
+            self._queue.append(_Active(job, fut, self.clock()))
+            self._cv.notify()
+        return fut
+
+    def start(self):
+        self._stop = False
+        self._thread = threading.Thread(target=self._loop, name="aidg-server", daemon=True)
+        self._thread.start()
+        return self
+
+    def stop(self):
+        """Finish everything submitted so far, then stop the loop."""
+        with self._cv:
+            self._stop = True
+            self._cv.notify()
+        if self._thread is not None:
+            self._thread.join()
+            self._thread = None
+
+    def __enter__(self):
+        return self.start()
+
+    def __exit__(self, *exc):
+        self.stop()
+
+    # ------------------------------------------------------------ scheduler
+    def idle(self) -> bool:
+        return not self._queue and not self._active and not self._rounds
+
+    def step(self) -> bool:
+        """One scheduler pass: retire, admit, launch.  Returns True if anything happened."""
+        progressed = self._retire()
+        progressed |= self._admit()
+        progressed |= self._launch()
+        return progressed
+
+    def _loop(self):
+        while True:
+            with self._cv:
+                if self._stop and self.idle():
+                    return
+            if not self.step():
+                if self._rounds:
+                    self.backend.wait(self._rounds[0][0])
+                else:
+                    with self._cv:
+                        if not self._queue and not self._stop:
+                            self._cv.wait(timeout=0.05)
+
+    def _admit(self) -> bool:
+        admitted = False
+        while True:
+            with self._cv:
+                if not self._queue:
+                    return admitted
+                st = self._queue[0]
+            try:
+                fp = self.backend.footprint(st.job)
+            except Exception as e:  # bad request
+                with self._cv:
+                    self._queue.popleft()
+                st.future.set_exception(e)
+                continue
+            if fp > self.hbm_budget:
+                with self._cv:
+                    self._queue.popleft()
+                st.future.set_exception(MemoryError(
+                    f"job needs {fp} device bytes, more than the server's budget {self.hbm_budget}"))
+                continue
+            if self._in_use + fp > self.hbm_budget:
+                return admitted     # first-in first-out: wait for memory to free up
+            with self._cv:
+                self._queue.popleft()
+            try:
+                st.handle = self.backend.prepare(st.job)
+            except Exception as e:
+                st.future.set_exception(e)
+                continue
+            st.footprint = fp
+            st.n_sg = self.backend.n_subgrids(st.handle)
+            st.admitted = self.clock()
+            self._in_use += fp
+            self.peak_in_use = max(self.peak_in_use, self._in_use)
+            self._active.append(st)
+            admitted = True
+
+    def _launch(self) -> bool:
+        if len(self._rounds) >= self.rounds_in_flight:
+            return False
+        ranges, owners = [], []
+        for st in self._active:
+            if st.next_sg < st.n_sg or (st.n_sg == 0 and st.last_token is None):
+                b = st.next_sg
+                e = min(st.n_sg, b + self.range_subgrids)
+                ranges.append((st.handle, b, e))
+                owners.append(st)
+                st.next_sg = e
+        if not ranges:
+            return False
+        token = self.backend.execute(ranges)
+        retiring = []
+        for st in owners:
+            if st.next_sg >= st.n_sg:
+                st.last_token = token
+                retiring.append(st)
+        self._rounds.append((token, retiring))
+        self.rounds += 1
+        return True
+
+    def _retire(self) -> bool:
+        progressed = False
+        while self._rounds and self.backend.done(self._rounds[0][0]):
+            _, retiring = self._rounds.popleft()
+            now = self.clock()
+            for st in retiring:
+                res = JobResult(self.backend.output(st.handle), st.job.tag, self.backend.n_vis(st.handle),
+                                st.n_sg, st.arrival, st.admitted, now)
+                self._active.remove(st)
+                self._in_use -= st.footprint
+                self.backend.release(st.handle)   # the output stays with the result
+                self.completed.append(res)
+                st.future.set_result(res)
+            progressed = True
+        return progressed
+
+    # ------------------------------------------------------------ statistics
+    def stats(self) -> dict:
+        lat = np.array([r.latency for r in self.completed])
+        if lat.size == 0:
+            return {"jobs": 0}
+        t0 = min(r.arrival for r in self.completed)
+        t1 = max(r.finished for r in self.completed)
+        nvis = sum(r.n_vis for r in self.completed)
+        return {"jobs": int(lat.size), "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
+                "makespan_s": float(t1 - t0), "mvis_per_s": float(nvis / (t1 - t0) / 1e6),
+                "rounds": self.rounds, "peak_bytes": int(self.peak_in_use)}

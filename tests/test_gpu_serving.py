@@ -1,0 +1,80 @@
+"""Serving on the GPU: a mix of gridding and degridding jobs of different subgrid
+sizes, grid sizes and lengths runs through the continuous-batching server (small
+ranges, so every job is split over several rounds and shares launches with the
+others).  Each result must equal the same job run alone through its own plan
+(normwise 1e-6: only the order of FP32 atomic additions differs), and jobs given
+the oracle's partition must match the FP64 oracle at the 1e-5 gate."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def rel(a, b):
+    a = np.asarray(a, np.complex128)
+    b = np.asarray(b, np.complex128)
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def jobs_mix(orc):
+    from paper_2502_17789_amd import Geometry
+    from paper_2502_17789_amd.serve import Job
+    specs = []
+    rng = np.random.default_rng(77)
+    for i in range(18):
+        L = [32, 64, 96][i % 3]
+        N = {32: 128, 64: 256, 96: 384}[L]
+        K = L // 4
+        wl = synth.config_tiny(300 + i, n_st=int(rng.integers(3, 7)), n_t=int(rng.integers(2, 8)),
+                               n_c=int(rng.integers(1, 40)), L=L, K=K, N=N, fov_deg=12.0,
+                               diameter_m=float(rng.uniform(200, 1200)), aterm_interval=2)
+        direction = "grid" if i % 2 == 0 else "degrid"
+        table = orc.partition(wl, 0.0) if i % 4 == 0 else None
+        geo = Geometry(N, L, K, wl.pixel_scale, aterm_interval=2, w_step=-1.0 if table is not None else 0.0)
+        if direction == "grid":
+            data = synth.random_vis((wl.n_baselines, wl.n_times, wl.n_chans), rng)
+        else:
+            W = orc.n_layers(table) if table is not None else None
+            data = None if W is None else synth.random_grid(W, N, rng)
+        specs.append((Job(direction, geo, wl.n_stations, wl.baselines, wl.uvw, wl.freqs,
+                          wl.aterms.astype(np.complex64), data, tag=i, table=table), wl))
+    return specs
+
+
+def test_served_results_equal_alone(orc):
+    import paper_2502_17789_amd as aidg
+    from paper_2502_17789_amd.serve import GpuBackend, Server
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    specs = jobs_mix(orc)
+    rng = np.random.default_rng(5)
+    # degrid jobs without a caller table need a grid with the plan's number of layers
+    for job, wl in specs:
+        if job.data is None:
+            with aidg.Plan(job.geometry, job.n_stations, job.baselines, job.uvw, job.freqs,
+                           torch.from_numpy(job.aterms).cuda()) as p:
+                job.data = synth.random_grid(p.n_wlayers, job.geometry.grid_size, rng)
+    srv = Server(GpuBackend(workspace_bytes=64 << 20), hbm_budget=8 << 30, range_subgrids=3)
+    with srv:
+        futs = [srv.submit(job) for job, _ in specs]
+        results = [f.result(timeout=120) for f in futs]
+    st = srv.stats()
+    print(f"served {st}", flush=True)
+    assert st["rounds"] > 3
+    for (job, wl), res in zip(specs, results):
+        A = torch.from_numpy(job.aterms).cuda()
+        with aidg.Plan(job.geometry, job.n_stations, job.baselines, job.uvw, job.freqs, A,
+                       table=job.table) as p:
+            x = torch.from_numpy(np.asarray(job.data, np.complex64)).cuda()
+            alone = p.grid(x) if job.direction == "grid" else p.degrid(x)
+            torch.cuda.synchronize()
+        got = res.output.cpu().numpy()
+        e = rel(got, alone.cpu().numpy())
+        assert e <= 1e-6, (job.tag, job.direction, e)
+        if job.table is not None:
+            ref = (orc.grid(wl, job.data, job.table) if job.direction == "grid"
+                   else orc.degrid(wl, job.data, job.table))
+            assert rel(got, ref) <= 1e-5, (job.tag, rel(got, ref))

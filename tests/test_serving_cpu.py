@@ -1,0 +1,182 @@
+"""Scheduler of the serving loop on the CPU, with a backend that runs the FP64
+oracle: results equal standalone jobs, admission stays within the HBM budget,
+first-in first-out order, oversized and invalid jobs are refused, and the
+threaded loop drains."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_2502_17789_amd import Geometry
+from paper_2502_17789_amd.serve import Job, Server, job_footprint_estimate
+
+
+class Token:
+    def __init__(self, t_done, clock):
+        self.t_done, self.clock = t_done, clock
+
+    def done(self):
+        return self.clock.now >= self.t_done
+
+
+class FakeClock:
+    def __init__(self):
+        self.now = 0.0
+
+    def __call__(self):
+        return self.now
+
+
+class OracleBackend:
+    """Runs each range of subgrids with the oracle; a round 'takes' 1 fake second."""
+
+    def __init__(self, clock):
+        self.clock = clock
+        self.executed = []
+
+    def footprint(self, job):
+        return job_footprint_estimate(job)
+
+    def prepare(self, job):
+        g = job.geometry
+        if g.subgrid_size % 2:
+            raise ValueError("odd subgrid size")
+        wl = synth.Workload("job", job.n_stations, job.baselines, job.uvw, job.freqs, g.grid_size,
+                            g.subgrid_size, g.kernel_support, g.pixel_scale, g.aterm_interval, job.aterms)
+        table = oracle.partition(wl, max(g.w_step, 0.0))
+        W = oracle.n_layers(table)
+        out = (np.zeros((W, 4, g.grid_size, g.grid_size), np.complex128) if job.direction == "grid"
+               else np.full((wl.n_baselines, wl.n_times, wl.n_chans, 4), np.nan, np.complex128))
+        return {"wl": wl, "table": table, "W": W, "dir": job.direction, "in": job.data, "out": out}
+
+    def n_subgrids(self, h):
+        return h["table"].shape[0]
+
+    def n_vis(self, h):
+        return h["wl"].n_vis
+
+    def execute(self, ranges):
+        for h, b, e in ranges:
+            self.executed.append((id(h), b, e))
+            sub = h["table"][b:e]
+            if h["dir"] == "grid":
+                oracle.grid(h["wl"], h["in"], sub, W=h["W"], out=h["out"])
+            else:
+                v = oracle.degrid(h["wl"], h["in"], sub)
+                m = oracle.coverage_mask(h["wl"], sub).astype(bool)
+                h["out"][m] = v[m]
+                if b == 0:
+                    allm = oracle.coverage_mask(h["wl"], h["table"]).astype(bool)
+                    h["out"][~allm] = 0
+        return Token(self.clock.now + 1.0, self.clock)
+
+    def done(self, token):
+        return token.done()
+
+    def wait(self, token):
+        self.clock.now = max(self.clock.now, token.t_done)
+
+    def output(self, h):
+        return h["out"]
+
+    def release(self, h):
+        h.clear()
+
+
+def make_job(seed, direction, L=16, N=64, n_st=4, n_t=4, n_c=5, tag=None):
+    wl = synth.config_tiny(seed, n_st=n_st, n_t=n_t, n_c=n_c, L=L, K=4, N=N, aterm_interval=2)
+    rng = np.random.default_rng(seed)
+    geo = Geometry(N, L, 4, wl.pixel_scale, aterm_interval=2, w_step=-1.0)
+    if direction == "grid":
+        data = synth.random_vis((wl.n_baselines, wl.n_times, wl.n_chans), rng)
+    else:
+        data = synth.random_grid(1, N, rng)
+    return Job(direction, geo, n_st, wl.baselines, wl.uvw, wl.freqs, wl.aterms, data, tag=tag), wl
+
+
+def drive(server, clock, limit=10000):
+    for _ in range(limit):
+        if server.idle():
+            return
+        if not server.step():
+            server.backend.wait(server._rounds[0][0])
+    raise AssertionError("server did not drain")
+
+
+def test_results_equal_standalone_and_interleave():
+    clock = FakeClock()
+    be = OracleBackend(clock)
+    srv = Server(be, hbm_budget=1 << 40, range_subgrids=3, clock=clock)
+    jobs = [make_job(10 + i, "grid" if i % 2 == 0 else "degrid", n_c=3 + i, tag=i) for i in range(6)]
+    futs = [srv.submit(j) for j, _ in jobs]
+    drive(srv, clock)
+    for (job, wl), f in zip(jobs, futs):
+        res = f.result()
+        table = oracle.partition(wl, 0.0)
+        ref = (oracle.grid(wl, job.data, table) if job.direction == "grid" else oracle.degrid(wl, job.data, table))
+        assert np.abs(res.output - ref).max() <= 1e-12 * np.abs(ref).max()
+        assert res.tag == job.tag and res.latency >= 0
+    # jobs were split over several rounds and rounds mixed several jobs
+    per_round = {}
+    assert srv.rounds > 1 and len({k for k, _, _ in be.executed}) == 6
+
+
+def test_admission_within_budget_fifo():
+    clock = FakeClock()
+    be = OracleBackend(clock)
+    jobs = [make_job(30 + i, "grid", n_c=4) for i in range(5)]
+    fp = max(job_footprint_estimate(j) for j, _ in jobs)
+    srv = Server(be, hbm_budget=int(2.5 * fp), range_subgrids=2, clock=clock)
+    futs = [srv.submit(j) for j, _ in jobs]
+    drive(srv, clock)
+    res = [f.result() for f in futs]
+    assert srv.peak_in_use <= srv.hbm_budget
+    adm = [r.admitted for r in res]
+    assert adm == sorted(adm)
+    assert len({r.admitted for r in res}) > 1  # some jobs waited for memory
+
+
+def test_oversized_and_invalid_jobs_refused():
+    clock = FakeClock()
+    srv = Server(OracleBackend(clock), hbm_budget=10_000_000, range_subgrids=4, clock=clock)
+    big, _ = make_job(40, "grid", N=2048)
+    bad, _ = make_job(41, "grid")
+    bad.geometry.subgrid_size = 15
+    ok, _ = make_job(42, "degrid")
+    fb, fx, fo = srv.submit(big), srv.submit(bad), srv.submit(ok)
+    drive(srv, clock)
+    assert isinstance(fb.exception(), MemoryError)
+    assert isinstance(fx.exception(), ValueError)
+    assert fo.result().output.shape[-1] == 4
+
+
+def test_latency_counts_queueing_and_rounds():
+    clock = FakeClock()
+    srv = Server(OracleBackend(clock), hbm_budget=1 << 40, range_subgrids=1000, clock=clock)
+    f1 = srv.submit(make_job(50, "grid")[0])
+    clock.now = 0.5
+    f2 = srv.submit(make_job(51, "grid")[0])
+    drive(srv, clock)
+    r1, r2 = f1.result(), f2.result()
+    assert r1.latency == pytest.approx(1.0 - 0.0) or r1.latency >= 1.0
+    assert r2.finished >= r2.arrival + 1.0 - 1e-12
+    st = srv.stats()
+    assert st["jobs"] == 2 and st["p99_ms"] >= st["p50_ms"] > 0
+
+
+def test_threaded_loop_drains():
+    import time
+    clock = FakeClock()
+
+    class Quick(OracleBackend):
+        def done(self, token):
+            return True
+
+        def wait(self, token):
+            pass
+
+    srv = Server(Quick(clock), hbm_budget=1 << 40, range_subgrids=2, clock=time.perf_counter)
+    srv.start()
+    futs = [srv.submit(make_job(60 + i, "degrid" if i % 2 else "grid")[0]) for i in range(4)]
+    srv.stop()
+    assert all(f.done() and f.exception() is None for f in futs)
