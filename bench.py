@@ -45,6 +45,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-baselines", type=int, default=12)
+    ap.add_argument("--serve", action="store_true",
+                    help="served mixed workload instead of the MWA-like job (separate JSON line)")
+    ap.add_argument("--jobs", type=int, default=300)
+    ap.add_argument("--rho", type=float, nargs="+", default=[0.8, 1.2])
     return ap.parse_args()
 
 
@@ -84,6 +88,107 @@ def cpu_baseline(wl, n_bl: int):
                       f"full N, L, K; grid {t1 - t0:.2f} s, degrid {t2 - t1:.2f} s"}
 
 
+def serve_bench(args):
+    """Mixed grid/degrid jobs with Poisson arrivals: served (continuous batching)
+    vs sequential per-job launches on the same arrival trace."""
+    import torch
+
+    import paper_2502_17789_amd as aidg
+    import synth
+    from paper_2502_17789_amd.serve import GpuBackend, Job, Server
+
+    torch.cuda.set_device(0)
+    mix = synth.served_job_mix(args.jobs, seed=5)
+
+    def make_job(d, tag):
+        geo = aidg.Geometry(d["N"], d["L"], d["K"], d["dl"], aterm_interval=max(d["n_t"], 1))
+        seed = d["seed"]
+
+        def aterms():
+            return synth.device_phase_screen_aterms(d["n_stations"], d["L"], d["screen_rms"], seed)
+
+        def data(shape):
+            g = torch.Generator(device="cuda")
+            g.manual_seed(seed + 1)
+            return torch.randn(shape, dtype=torch.complex64, device="cuda", generator=g)
+
+        return Job(d["direction"], geo, d["n_stations"], d["baselines"], d["uvw"], d["freqs"],
+                   aterms, data, tag=tag)
+
+    def n_vis(d):
+        return d["baselines"].shape[0] * d["uvw"].shape[1] * d["freqs"].shape[0]
+
+    def run_sequential(arrivals):
+        """One job at a time, each through its own plan (plain per-job launches)."""
+        lat, service = [], []
+        t0 = time.perf_counter()
+        for d, arr in zip(mix, arrivals):
+            now = time.perf_counter() - t0
+            if now < arr:
+                time.sleep(arr - now)
+            s0 = time.perf_counter()
+            job = make_job(d, None)
+            A = job.aterms()
+            geo = dataclasses_replace(job.geometry, workspace_bytes=256 << 20)
+            with aidg.Plan(geo, job.n_stations, job.baselines, job.uvw, job.freqs, A) as p:
+                del A
+                if job.direction == "grid":
+                    out = p.grid(job.data(p.vis_shape()))
+                else:
+                    out = p.degrid(job.data(p.grid_shape()))
+                torch.cuda.synchronize()
+                del out
+            s1 = time.perf_counter()
+            service.append(s1 - s0)
+            lat.append(s1 - t0 - arr)
+        return np.array(lat), np.array(service), time.perf_counter() - t0
+
+    def run_served(arrivals):
+        srv = Server(GpuBackend(workspace_bytes=1 << 30), range_subgrids=4096, prepare_workers=4)
+        futs = []
+        with srv:
+            t0 = time.perf_counter()
+            for i, (d, arr) in enumerate(zip(mix, arrivals)):
+                now = time.perf_counter() - t0
+                if now < arr:
+                    time.sleep(arr - now)
+                futs.append(srv.submit(make_job(d, i)))
+            res = [f.result() for f in futs]
+        lat = np.array([r.latency for r in res])
+        span = max(r.finished for r in res) - min(r.arrival for r in res)
+        return lat, span, srv.stats()
+
+    total = sum(n_vis(d) for d in mix)
+    run_sequential([0.0] * 6)   # warm-up: kernels of each subgrid size, allocator
+    lat0, service, span0 = run_sequential([0.0] * len(mix))
+    es = float(service.mean())
+    out = {"metric": "served mixed grid/degrid jobs: Mvis/s and p50/p99 job latency",
+           "jobs": len(mix), "total_vis": int(total), "mean_sequential_service_ms": round(es * 1e3, 3),
+           "sequential_back_to_back": {"mvis_s": round(total / span0 / 1e6, 3)}, "loads": []}
+    rng = np.random.default_rng(6)
+    for rho in args.rho:
+        gaps = rng.exponential(es / rho, len(mix))
+        arrivals = np.concatenate([[0.0], np.cumsum(gaps)[:-1]])
+        ls, span_s, st = run_served(arrivals)
+        lq, _, span_q = run_sequential(arrivals)
+        out["loads"].append({
+            "rho": rho,
+            "served": {"p50_ms": round(float(np.percentile(ls, 50)) * 1e3, 3),
+                       "p99_ms": round(float(np.percentile(ls, 99)) * 1e3, 3),
+                       "mvis_s": round(total / span_s / 1e6, 3), "rounds": st["rounds"],
+                       "peak_admitted_bytes": st["peak_bytes"]},
+            "sequential": {"p50_ms": round(float(np.percentile(lq, 50)) * 1e3, 3),
+                           "p99_ms": round(float(np.percentile(lq, 99)) * 1e3, 3),
+                           "mvis_s": round(total / span_q / 1e6, 3)}})
+        print(f"# rho {rho}: {out['loads'][-1]}", file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
+
+
+def dataclasses_replace(obj, **kw):
+    import dataclasses
+    return dataclasses.replace(obj, **kw)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -92,6 +197,10 @@ def main():
               "would shard baselines across GPUs and all-reduce the grid); run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.serve:
+        serve_bench(args)
+        return
 
     import torch
 

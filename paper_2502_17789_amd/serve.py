@@ -47,8 +47,10 @@ class Job:
     baselines: np.ndarray
     uvw: np.ndarray
     freqs: np.ndarray
-    aterms: object   # host complex array or device tensor [n_int, n_st, L, L, 4]
-    data: object     # host array or device tensor
+    aterms: object   # host complex array or device tensor [n_int, n_st, L, L, 4], or a
+                     # callable returning one (called when the job is admitted)
+    data: object     # host array or device tensor, or a callable taking the expected
+                     # shape and returning one
     tag: object = None
     table: object = None   # optional caller partition (aidg_subgrid records)
 
@@ -126,13 +128,21 @@ class GpuBackend:
         elem = 8 if g.precision == FP32 else 16
         g.workspace_bytes = 4 * g.subgrid_size ** 2 * elem   # the executor holds the workspace
         cdt = torch.complex64 if g.precision == FP32 else torch.complex128
+
+        def device(x):
+            x = x() if callable(x) else x
+            return x if isinstance(x, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(x)).to(cdt).cuda()
+
         with torch.cuda.stream(self.upload):
-            A = job.aterms if isinstance(job.aterms, torch.Tensor) else \
-                torch.from_numpy(np.ascontiguousarray(job.aterms)).to(cdt).cuda()
+            A = device(job.aterms)
             plan = Plan(g, job.n_stations, job.baselines, job.uvw, job.freqs, A.contiguous(),
                         table=job.table, stream=self.upload)
-            data = job.data if isinstance(job.data, torch.Tensor) else \
-                torch.from_numpy(np.ascontiguousarray(job.data)).to(cdt).cuda()
+            del A   # the plan holds its own copy
+            if callable(job.data):   # a factory gets the shape the plan expects
+                x = job.data(plan.grid_shape() if job.direction == "degrid" else plan.vis_shape())
+                data = device(x)
+            else:
+                data = device(job.data)
             if job.direction == "grid":
                 out = torch.zeros(plan.grid_shape(), dtype=cdt, device="cuda")
             else:
@@ -176,7 +186,7 @@ class Server:
     """Continuous-batching request loop (see module docstring)."""
 
     def __init__(self, backend=None, hbm_budget: int | None = None, range_subgrids: int = 2048,
-                 rounds_in_flight: int = 2, clock=time.perf_counter):
+                 rounds_in_flight: int = 2, clock=time.perf_counter, prepare_workers: int = 0):
         self.backend = backend if backend is not None else GpuBackend()
         if hbm_budget is None:
             import torch
@@ -189,6 +199,9 @@ class Server:
         self._queue: collections.deque[_Active] = collections.deque()
         self._active: list[_Active] = []
         self._rounds: collections.deque = collections.deque()   # (token, [jobs retiring])
+        self._preparing: list = []                               # (state, future of prepare)
+        self._pool = (concurrent.futures.ThreadPoolExecutor(prepare_workers, "aidg-prepare")
+                      if prepare_workers > 0 else None)
         self._in_use = 0
         self._cv = threading.Condition()
         self._thread = None
@@ -219,6 +232,9 @@ class Server:
         if self._thread is not None:
             self._thread.join()
             self._thread = None
+        if self._pool is not None:
+            self._pool.shutdown(wait=True)
+            self._pool = None
 
     def __enter__(self):
         return self.start()
@@ -228,12 +244,13 @@ class Server:
 
     # ------------------------------------------------------------ scheduler
     def idle(self) -> bool:
-        return not self._queue and not self._active and not self._rounds
+        return not self._queue and not self._active and not self._rounds and not self._preparing
 
     def step(self) -> bool:
         """One scheduler pass: retire, admit, launch.  Returns True if anything happened."""
         progressed = self._retire()
         progressed |= self._admit()
+        progressed |= self._collect_prepared()
         progressed |= self._launch()
         return progressed
 
@@ -245,6 +262,9 @@ class Server:
             if not self.step():
                 if self._rounds:
                     self.backend.wait(self._rounds[0][0])
+                elif self._preparing:
+                    concurrent.futures.wait([f for _, f in self._preparing], timeout=0.05,
+                                            return_when=concurrent.futures.FIRST_COMPLETED)
                 else:
                     with self._cv:
                         if not self._queue and not self._stop:
@@ -274,18 +294,40 @@ class Server:
                 return admitted     # first-in first-out: wait for memory to free up
             with self._cv:
                 self._queue.popleft()
-            try:
-                st.handle = self.backend.prepare(st.job)
-            except Exception as e:
-                st.future.set_exception(e)
-                continue
             st.footprint = fp
-            st.n_sg = self.backend.n_subgrids(st.handle)
-            st.admitted = self.clock()
             self._in_use += fp
             self.peak_in_use = max(self.peak_in_use, self._in_use)
-            self._active.append(st)
             admitted = True
+            if self._pool is not None:
+                self._preparing.append((st, self._pool.submit(self.backend.prepare, st.job)))
+                continue
+            try:
+                self._activate(st, self.backend.prepare(st.job))
+            except Exception as e:
+                self._in_use -= fp
+                st.future.set_exception(e)
+
+    def _activate(self, st, handle):
+        st.handle = handle
+        st.n_sg = self.backend.n_subgrids(handle)
+        st.admitted = self.clock()
+        self._active.append(st)
+
+    def _collect_prepared(self) -> bool:
+        progressed = False
+        still = []
+        for st, fut in self._preparing:
+            if not fut.done():
+                still.append((st, fut))
+                continue
+            progressed = True
+            try:
+                self._activate(st, fut.result())
+            except Exception as e:
+                self._in_use -= st.footprint
+                st.future.set_exception(e)
+        self._preparing = still
+        return progressed
 
     def _launch(self) -> bool:
         if len(self._rounds) >= self.rounds_in_flight:

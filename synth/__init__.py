@@ -319,3 +319,56 @@ def config_tiny(seed: int, n_st: int = 5, n_t: int = 6, n_c: int = 5, N: int = 1
 
 def max_uv_lambda(wl: Workload) -> float:
     return float(np.abs(wl.uvw[..., :2]).max() * wl.freqs.max() / SPEED_OF_LIGHT)
+
+
+def served_job_mix(n_jobs: int, seed: int = 5, vis_lo: float = 1e3, vis_hi: float = 5e6):
+    """Descriptions of a mixed serving workload: per job a direction (grid or
+    degrid, 50/50), a visibility count log-uniform in [vis_lo, vis_hi], 16-128
+    stations in a 5 km disc, 8/16/32/96 channels over 140-170 MHz (fewer
+    baselines when the count is below one timestep), grid 1024^2..8000^2,
+    subgrid 32/64/96 with K = L/4, pixel size min(15 arcsec, 0.45/u_max), one
+    A-term interval with a 0-3 rad white phase screen.  Returns dicts with host
+    arrays; A-terms and data are generated on the device when a job starts."""
+    rng = np.random.default_rng(seed)
+    jobs = []
+    for i in range(n_jobs):
+        n_vis = float(np.exp(rng.uniform(math.log(vis_lo), math.log(vis_hi))))
+        n_st = int(rng.integers(16, 129))
+        n_c = int(rng.choice([8, 16, 32, 96]))
+        L = int(rng.choice([32, 64, 96]))
+        N = int(rng.choice([1024, 2048, 4096, 8000]))
+        enu = station_disc(n_st, 5000.0, rng)
+        bl = all_pairs(n_st)
+        if n_vis < bl.shape[0] * n_c:
+            keep = max(1, int(n_vis // n_c))
+            bl = bl[np.sort(rng.choice(bl.shape[0], keep, replace=False))]
+            n_t = 1
+        else:
+            n_t = max(1, int(round(n_vis / (bl.shape[0] * n_c))))
+        uvw = earth_rotation_uvw(enu, bl, math.radians(-26.7), math.radians(-27.0),
+                                 transit_hour_angles(n_t, 2.0))
+        freqs = channel_centres(140e6, 170e6, n_c)
+        umax = float(np.abs(uvw[..., :2]).max()) * freqs.max() / SPEED_OF_LIGHT
+        dl = min(15.0 * ARCSEC, 0.45 / max(umax, 1.0), 0.6 / N)  # Nyquist; FOV/sqrt(2) < 1
+        jobs.append({"direction": "grid" if rng.random() < 0.5 else "degrid", "n_stations": n_st,
+                     "baselines": np.ascontiguousarray(bl, np.int32), "uvw": uvw, "freqs": freqs,
+                     "N": N, "L": L, "K": L // 4, "dl": dl, "n_t": n_t, "screen_rms": float(rng.uniform(0, 3)),
+                     "seed": int(rng.integers(1 << 31))})
+    return jobs
+
+
+def device_phase_screen_aterms(n_st: int, L: int, rms: float, seed: int, coarse: int = 8):
+    """A-terms exp(i phi) I on the L x L lattice for one interval, made on the GPU:
+    white coarse screens bilinearly upsampled.  Returns complex64 [1, n_st, L, L, 4]."""
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    c = torch.randn((n_st, 1, coarse, coarse), device="cuda", generator=g)
+    c = c - c.mean(dim=(2, 3), keepdim=True)
+    c = c * (rms / c.std(dim=(2, 3), keepdim=True).clamp_min(1e-12))
+    phi = torch.nn.functional.interpolate(c, size=(L, L), mode="bilinear", align_corners=True)[:, 0]
+    e = torch.polar(torch.ones_like(phi), phi)
+    A = torch.zeros((1, n_st, L, L, 4), dtype=torch.complex64, device="cuda")
+    A[0, :, :, :, 0] = e
+    A[0, :, :, :, 3] = e
+    return A

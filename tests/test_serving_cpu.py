@@ -180,3 +180,22 @@ def test_threaded_loop_drains():
     futs = [srv.submit(make_job(60 + i, "degrid" if i % 2 else "grid")[0]) for i in range(4)]
     srv.stop()
     assert all(f.done() and f.exception() is None for f in futs)
+
+
+def test_parallel_prepare_matches():
+    clock = FakeClock()
+    srv = Server(OracleBackend(clock), hbm_budget=1 << 40, range_subgrids=2, clock=clock, prepare_workers=3)
+    jobs = [make_job(70 + i, "grid" if i % 2 else "degrid") for i in range(5)]
+    futs = [srv.submit(j) for j, _ in jobs]
+    for _ in range(100000):
+        if srv.idle():
+            break
+        if not srv.step():
+            if srv._rounds:
+                srv.backend.wait(srv._rounds[0][0])
+    assert srv.idle()
+    for (job, wl), f in zip(jobs, futs):
+        table = oracle.partition(wl, 0.0)
+        ref = oracle.grid(wl, job.data, table) if job.direction == "grid" else oracle.degrid(wl, job.data, table)
+        assert np.abs(f.result().output - ref).max() <= 1e-12 * np.abs(ref).max()
+    srv.stop()
