@@ -32,10 +32,28 @@ if ROOT not in sys.path:
 # accumulate is 16 FP32 FMAs, the phasor step ph <- ph * step is 4 FP32 ops
 # (2 mul + 2 FMA); each occupies one FMA issue slot, counted as 2 FLOP.
 FLOP_PER_VP = 40
-# FP32 issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz x 2 FLOP/FMA.  Packed
-# FP32 instructions are disabled in this build, so this is the attainable rate.
-PEAK_FP32_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12   # 78.64
-PEAK_FP32_PACKED_TFLOPS = 157.3                       # published vector peak (packed FMA)
+# FP32 vector peak of MI355X: 256 CUs x 4 SIMDs x 2.4 GHz, each SIMD issuing up to
+# two wave64 VALU instructions per 4 cycles (gfx950 VALU dual issue, counted by
+# SQ_ACTIVE_INST_VALU2) = 128 FMA per clock per CU = 157.3 TFLOP/s at 2 FLOP/FMA.
+# A single issue slot per 4 cycles would give half of it.
+PEAK_FP32_TFLOPS = 256 * 4 * 32 * 2.4e9 * 2 / 1e12   # 157.3
+PEAK_FP32_SINGLE_ISSUE_TFLOPS = PEAK_FP32_TFLOPS / 2
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_mwa.json")
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary, or None once the kernel source has changed since."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+        src = open(os.path.join(ROOT, "paper_2502_17789_amd", "csrc", "kernels.hip"), "rb").read()
+    except OSError:
+        return None
+    if hashlib.sha256(src).hexdigest() != rec.get("kernels_hip_sha256"):
+        return None
+    k = rec["kernels"].get(kernel)
+    return None if k is None else round(k["bytes_per_launch"])
 
 
 def parse():
@@ -49,6 +67,8 @@ def parse():
                     help="served mixed workload instead of the MWA-like job (separate JSON line)")
     ap.add_argument("--jobs", type=int, default=300)
     ap.add_argument("--rho", type=float, nargs="+", default=[0.8, 1.2])
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 1 GiB device-to-device 3 times (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
@@ -201,6 +221,15 @@ def main():
     if args.serve:
         serve_bench(args)
         return
+    if args.copy_probe:
+        import torch
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": a.numel() * 4, "copies": 3}), flush=True)
+        return
 
     import torch
 
@@ -260,9 +289,9 @@ def main():
     if dom in ("grid_dft", "degrid_dft"):
         achieved = k["vis_pixels"] * FLOP_PER_VP / (k["ms"] * 1e-3) / 1e12
         roof = {"kernel": dom, "bound": "alu", "achieved": round(achieved, 3),
-                "peak": round(PEAK_FP32_TFLOPS, 2), "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
-                "frac_of_packed_peak": round(achieved / PEAK_FP32_PACKED_TFLOPS, 4),
+                "peak": round(PEAK_FP32_TFLOPS, 1), "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": measured_traffic(dom),
+                "frac_of_single_issue": round(achieved / PEAK_FP32_SINGLE_ISSUE_TFLOPS, 4),
                 "avg_launch_ms": round(k["ms"] / max(k["launches"], 1), 4),
                 "launches": k["launches"]}
     else:
