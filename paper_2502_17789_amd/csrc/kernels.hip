@@ -41,7 +41,13 @@ namespace aidg {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kPix = 4;                     // pixels per lane (gridder and degridder)
+#ifndef GRID_PIX
+#define GRID_PIX 4
+#endif
+#ifndef DEGRID_WAVES
+#define DEGRID_WAVES 0
+#endif
+constexpr int kPix = GRID_PIX;              // pixels per lane in the gridder
 constexpr int kChunk = kThreads * kPix;     // pixels per workgroup pass
 constexpr int kVisGroup = 4;                // channels per degridder reduction
 
@@ -55,6 +61,9 @@ template <> struct DegridPix<96> { static constexpr int P = DEGRID_PIX96; };
 template <typename R> struct C2;
 template <> struct C2<float> { using T = float2; };
 template <> struct C2<double> { using T = double2; };
+template <typename R> struct C4;
+template <> struct C4<float> { using T = float4; };
+template <> struct C4<double> { using T = double4; };
 
 template <typename R>
 __device__ __forceinline__ typename C2<R>::T cmul(typename C2<R>::T a, typename C2<R>::T b) {
@@ -173,12 +182,25 @@ __device__ __forceinline__ Slot resolve(const Group& g, int64_t slot) {
 template <int L, typename R>
 __global__ __launch_bounds__(kThreads) void grid_dft(const Group g) {
   using V2 = typename C2<R>::T;
+  using V4 = typename C4<R>::T;
+  extern __shared__ unsigned char smem_raw[];
+  V4* vlds = reinterpret_cast<V4*>(smem_raw);  // the subgrid's visibilities, 8 values each
   const int64_t local = blockIdx.y;
   const Slot sl = resolve(g, local);
   const KernelArgs& a = sl.a;
   const SubgridDev& s = sl.s;
   const R* __restrict__ vis = reinterpret_cast<const R*>(sl.in);
   R* __restrict__ scratch = reinterpret_cast<R*>(g.scratch);
+
+  // Stage the sub-table (rows of nc visibilities, coalesced) in LDS; every lane then
+  // reads each visibility by a broadcast LDS load into vector registers, so the
+  // accumulation FMAs take only VGPR operands and can dual-issue.
+  const int nv = s.nt * s.nc;
+  for (int i = threadIdx.x; i < 2 * nv; i += kThreads) {
+    const int k = i >> 1, row = k / s.nc, c = k - row * s.nc;
+    vlds[i] = reinterpret_cast<const V4*>(vis)[(s.vis0 + (int64_t)row * a.nc_total + c) * 2 + (i & 1)];
+  }
+
   Pixel px[kPix];
 #pragma unroll
   for (int p = 0; p < kPix; ++p)
@@ -189,13 +211,16 @@ __global__ __launch_bounds__(kThreads) void grid_dft(const Group g) {
   for (int p = 0; p < kPix; ++p)
 #pragma unroll
     for (int i = 0; i < 8; ++i) acc[p][i] = 0;
+  __syncthreads();
 
   const double u0 = (s.U0 - a.N / 2) * a.du, v0 = (s.V0 - a.N / 2) * a.du;
   for (int t = 0; t < s.nt; ++t) {
     const_view<double> uvw = as_const(a.uvw + 3 * (s.uvw0 + t));
     const double um = uvw[0], vm = uvw[1], wm = uvw[2];
-    const_view<R> vrow = as_const(vis + 8 * (s.vis0 + (int64_t)t * a.nc_total));
-    V2 st[kPix], ph[kPix];
+    const V4* vrow = vlds + 2 * t * s.nc;
+    // Phasors along the channels of the row: ph_{j+1} = ph_j * step, kept in two
+    // ping-pong registers (pa for even offsets from the seed, pb for odd ones).
+    V2 st[kPix];
     {
       const double su = um * s.dfc, sv = vm * s.dfc, sw = wm * s.dfc;
 #pragma unroll
@@ -204,14 +229,13 @@ __global__ __launch_bounds__(kThreads) void grid_dft(const Group g) {
     for (int j0 = 0; j0 < s.nc; j0 += s.R) {
       const double fc = as_const(a.fc)[s.c0 + j0];
       const double cu = um * fc - u0, cv = vm * fc - v0, cw = wm * fc - s.w0;
+      V2 pa[kPix], pb[kPix];
 #pragma unroll
-      for (int p = 0; p < kPix; ++p) ph[p] = phasor(cu * px[p].l + cv * px[p].m + cw * px[p].n1, R());
+      for (int p = 0; p < kPix; ++p) pa[p] = phasor(cu * px[p].l + cv * px[p].m + cw * px[p].n1, R());
       const int jn = min(s.nc, j0 + s.R);
-      for (int j = j0; j < jn; ++j) {
-        const_view<R> v = vrow + 8 * j;
-        R vv[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) vv[i] = v[i];
+      auto mac = [&](int j, const V2 (&ph)[kPix]) {
+        const V4 va = vrow[2 * j], vb = vrow[2 * j + 1];
+        const R vv[8] = {va.x, va.y, va.z, va.w, vb.x, vb.y, vb.z, vb.w};
 #pragma unroll
         for (int p = 0; p < kPix; ++p) {
 #pragma unroll
@@ -221,9 +245,18 @@ __global__ __launch_bounds__(kThreads) void grid_dft(const Group g) {
             acc[p][2 * q + 1] = fma(vv[2 * q], ph[p].y, acc[p][2 * q + 1]);
             acc[p][2 * q + 1] = fma(vv[2 * q + 1], ph[p].x, acc[p][2 * q + 1]);
           }
-          ph[p] = cmul<R>(ph[p], st[p]);
         }
+      };
+      int j = j0;
+      for (; j + 1 < jn; j += 2) {
+        mac(j, pa);
+#pragma unroll
+        for (int p = 0; p < kPix; ++p) pb[p] = cmul<R>(pa[p], st[p]);
+        mac(j + 1, pb);
+#pragma unroll
+        for (int p = 0; p < kPix; ++p) pa[p] = cmul<R>(pb[p], st[p]);
       }
+      if (j < jn) mac(j, pa);
     }
   }
 
@@ -484,7 +517,11 @@ __device__ __forceinline__ R transpose_reduce32(R (&a)[32], int ln) {
 }
 
 template <int L, typename R>
-__global__ __launch_bounds__(kThreads) void degrid_dft(const Group g) {
+__global__ __launch_bounds__(kThreads)
+#if DEGRID_WAVES > 0
+__attribute__((amdgpu_waves_per_eu(DEGRID_WAVES, DEGRID_WAVES)))
+#endif
+void degrid_dft(const Group g) {
   using V2 = typename C2<R>::T;
   constexpr int P = DegridPix<L>::P, CH = kThreads * P;
   static_assert((L * L) % CH == 0, "pixel chunks must tile the subgrid");
@@ -606,7 +643,8 @@ int launch_one(KernelClass k, const Group& g, hipStream_t st, int max_nv) {
   const unsigned n = (unsigned)g.total;
   switch (k) {
     case kGridDft:
-      hipLaunchKernelGGL((grid_dft<L, R>), dim3((L * L) / kChunk, n), dim3(kThreads), 0, st, g);
+      hipLaunchKernelGGL((grid_dft<L, R>), dim3((L * L) / kChunk, n), dim3(kThreads),
+                         (size_t)max_nv * 8 * sizeof(R), st, g);
       break;
     case kFftAdd:
       hipLaunchKernelGGL((fft_add<L, R>), dim3(4, n), dim3(kThreads), 0, st, g);
