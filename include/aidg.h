@@ -61,7 +61,7 @@
 extern "C" {
 #endif
 
-#define AIDG_ABI_VERSION 1
+#define AIDG_ABI_VERSION 2
 
 typedef enum {
   AIDG_OK = 0,
@@ -93,6 +93,12 @@ typedef struct {
                               degrid writes 0); 1: plan creation fails with AIDG_E_RANGE */
   int32_t max_subgrid_vis; /* cap on visibilities per subgrid, 0 = 1024; larger caller
                               sub-tables are split in time */
+  int32_t center_lattice;  /* the library's partitioner puts subgrid centres on cells
+                              N/2 + k * center_lattice (Sec. 2.2: a centre snaps to a grid
+                              cell); 0 = automatic (largest power of two <= (L-K)/8), 1 = any cell.
+                              Subgrids with the same centre and w-layer share one subgrid FFT
+                              and one add to the grid (and one split + inverse FFT) */
+  int32_t reserved;        /* 0 */
   int64_t workspace_bytes; /* subgrid stack budget on the device; 0 = 2 GiB */
 } aidg_geometry;
 
@@ -123,6 +129,9 @@ typedef struct {
   int64_t vis_bytes;       /* size of one visibility array */
   int64_t n_batches;       /* kernel batches per aidg_grid / aidg_degrid call */
   int64_t max_subgrid_vis; /* largest sub-table */
+  int64_t n_groups;        /* runs of subgrids with one w-layer and centre that share one
+                              subgrid FFT; a centre holding more than 8x the mean
+                              visibilities per centre is split into several */
 } aidg_plan_info;
 
 typedef struct aidg_plan aidg_plan;

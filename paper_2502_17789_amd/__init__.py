@@ -40,7 +40,8 @@ class _Geometry(ctypes.Structure):
                 ("pixel_scale", ctypes.c_double), ("w_step", ctypes.c_double),
                 ("taper_beta", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("reseed_channels", ctypes.c_int32), ("strict_range", ctypes.c_int32),
-                ("max_subgrid_vis", ctypes.c_int32), ("workspace_bytes", ctypes.c_int64)]
+                ("max_subgrid_vis", ctypes.c_int32), ("center_lattice", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("workspace_bytes", ctypes.c_int64)]
 
 
 class _PlanInfo(ctypes.Structure):
@@ -49,7 +50,8 @@ class _PlanInfo(ctypes.Structure):
                 ("subgrid_size", ctypes.c_int32), ("w_step", ctypes.c_double),
                 ("device_bytes", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
                 ("grid_bytes", ctypes.c_int64), ("vis_bytes", ctypes.c_int64),
-                ("n_batches", ctypes.c_int64), ("max_subgrid_vis", ctypes.c_int64)]
+                ("n_batches", ctypes.c_int64), ("max_subgrid_vis", ctypes.c_int64),
+                ("n_groups", ctypes.c_int64)]
 
 
 KERNEL_CLASSES = ("grid_dft", "fft_add", "split_ifft", "degrid_dft", "zero_vis")
@@ -83,15 +85,17 @@ class Geometry:
     strict_range: int = 0
     max_subgrid_vis: int = 0
     workspace_bytes: int = 0
+    center_lattice: int = 0
 
     def to_c(self) -> _Geometry:
         return _Geometry(self.grid_size, self.subgrid_size, self.kernel_support, self.aterm_interval,
                          self.pixel_scale, self.w_step, self.taper_beta, self.precision,
                          self.reseed_channels, self.strict_range, self.max_subgrid_vis,
-                         self.workspace_bytes)
+                         self.center_lattice, 0, self.workspace_bytes)
 
 
 _lib = None
+ABI_VERSION = 2  # the structure layouts above follow include/aidg.h at this version
 
 
 def library() -> ctypes.CDLL:
@@ -125,6 +129,9 @@ def library() -> ctypes.CDLL:
         f = getattr(lib, name)
         f.restype = res
         f.argtypes = args
+    if lib.aidg_abi_version() != ABI_VERSION:
+        raise RuntimeError(f"{LIB_PATH} has ABI version {lib.aidg_abi_version()}, this binding "
+                           f"expects {ABI_VERSION}: rebuild with `python -m paper_2502_17789_amd.build`")
     _lib = lib
     return lib
 

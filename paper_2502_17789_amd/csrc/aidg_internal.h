@@ -13,12 +13,16 @@ constexpr double kSpeedOfLight = 299792458.0;
 constexpr int kMaxSubgridVisDefault = 1024;
 constexpr int kReseedDefault = 32;
 constexpr int64_t kWorkspaceDefault = int64_t(2) << 30;
+// A group of same-centre subgrids holds at most this many times the mean
+// visibilities per centre (and at least one subgrid).
+constexpr int64_t kGroupVisFactor = 8;
 
 // Per-subgrid record the kernels read (device copy of the partition).
 struct alignas(16) SubgridDev {
   int32_t t0, nt, c0, nc;      // sub-table
   int32_t U0, V0, wlayer, R;   // centre cell, layer, reseed interval (1: every channel)
-  int32_t ap, aq, bl, pad;     // A-term plane index (aint * n_st + station) of p and q
+  int32_t ap, aq, bl, group;   // A-term plane index (aint * n_st + station) of p and q;
+                               // baseline; (layer, centre) group in the plan's order
   int64_t vis0;                // flat visibility index of (bl, t0, c0)
   int64_t uvw0;                // flat uvw row index of (bl, t0)
   double dfc;                  // channel spacing / c (s/m * Hz ... i.e. 1/m) for the recurrence
@@ -28,7 +32,7 @@ static_assert(sizeof(SubgridDev) == 80, "SubgridDev layout");
 
 // Geometry after validation, with derived quantities.
 struct Geometry {
-  int N, L, K, aterm_interval, precision, R, strict, max_sg_vis;
+  int N, L, K, aterm_interval, precision, R, strict, max_sg_vis, lattice;
   double dl, fov, du, beta, w_step;
   int64_t workspace;
 };
@@ -60,27 +64,33 @@ struct KernelArgs {
   const void* aterms;       // device [n_int][n_st][L][L][4]
   const void* taper;        // device [L][L] taper times (-1)^(x+y)
   const void* twiddle;      // device [L] exp(-2 pi i k / L)
+  const int64_t* grp_begin; // device [n_groups + 1]: first subgrid of each (layer, centre) group
   int nt_total, nc_total, N, pad;
   double du;                // uv cell size, wavelengths
   double lstep;             // FOV / L, subgrid lattice spacing in direction cosines
 };
 
 // A grouped launch: consecutive ranges of subgrids from up to kMaxGroup plans
-// share one kernel launch.  Workgroup slot s belongs to the last job whose
-// slot_begin <= s; its subgrid is sg_begin + (s - slot_begin) of that plan, and
-// its subgrid image lives at scratch slot s.
+// share one kernel launch.  A plan's table is ordered so that subgrids with the
+// same w-layer and centre are consecutive (a "group"); the gridder, FFT/adder and
+// splitter/inverse FFT run one workgroup slot per group (slots gslot_begin..), the
+// degridder one slot per subgrid (slots slot_begin..).  Group g of a range owns
+// scratch slot gslot_begin + (g - g_first): its subgrid image sum, [4][L][L].
 constexpr int kMaxGroup = 16;
 struct JobRef {
   const KernelArgs* args;   // device copy of the plan's parameters
   const void* in;           // visibilities (gridder) or grid (splitter)
   void* out;                // grid (adder) or visibilities (degridder)
-  int64_t sg_begin;         // first subgrid of the range in the plan's table
-  int64_t slot_begin;       // first slot of the range in this launch
+  int64_t sg_begin, sg_end; // range of the plan's table
+  int64_t g_first;          // group of subgrid sg_begin
+  int64_t slot_begin;       // first per-subgrid slot of the range in this launch
+  int64_t gslot_begin;      // first per-group slot of the range in this launch
 };
 struct Group {
   int32_t n, pad;
-  int64_t total;            // slots (subgrids) in the launch
-  void* scratch;            // [total][4][L][L] subgrid images
+  int64_t total_sg;         // per-subgrid slots in the launch
+  int64_t total_grp;        // per-group slots (scratch images) in the launch
+  void* scratch;            // [total_grp][4][L][L] subgrid images
   JobRef job[kMaxGroup];
 };
 

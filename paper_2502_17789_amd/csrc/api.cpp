@@ -35,6 +35,12 @@ struct aidg_plan {
   std::vector<aidg_subgrid> table;
   std::vector<double> w0;
   int64_t n_excluded = 0;
+  // Subgrids sharing w-layer and centre are consecutive and form a group;
+  // group k holds subgrids [grp_begin[k], grp_begin[k+1]).  sg_group maps a
+  // subgrid to its group.  Batches are runs of whole groups: [batch_begin[b],
+  // batch_begin[b+1]) in subgrids, at most `batch` groups each.
+  std::vector<int64_t> grp_begin, batch_begin;
+  std::vector<int32_t> sg_group;
   int64_t batch = 1;
   size_t elem = 8, aterm_bytes = 0, device_bytes = 0, scratch_bytes = 0;
   SubgridDev* d_sg = nullptr;
@@ -45,6 +51,7 @@ struct aidg_plan {
   void* d_tw = nullptr;
   void* d_scratch = nullptr;
   int64_t* d_excl = nullptr;
+  int64_t* d_grp = nullptr;
   KernelArgs* d_args = nullptr;  // device copy of args()
   hipEvent_t last = nullptr;
   std::atomic<bool> busy{false};
@@ -68,6 +75,7 @@ struct aidg_plan {
     a.aterms = d_aterms;
     a.taper = d_taper;
     a.twiddle = d_tw;
+    a.grp_begin = d_grp;
     a.nt_total = nt;
     a.nc_total = nc;
     a.N = g.N;
@@ -78,7 +86,7 @@ struct aidg_plan {
   }
 
   void release() {
-    void* ptrs[] = {d_sg, d_uvw, d_fc, d_aterms, d_taper, d_tw, d_scratch, d_excl, d_args};
+    void* ptrs[] = {d_sg, d_uvw, d_fc, d_aterms, d_taper, d_tw, d_scratch, d_excl, d_grp, d_args};
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
     if (last) (void)hipEventDestroy(last);
@@ -89,6 +97,7 @@ struct aidg_plan {
     d_uvw = d_fc = nullptr;
     d_aterms = d_taper = d_tw = d_scratch = nullptr;
     d_excl = nullptr;
+    d_grp = nullptr;
     d_args = nullptr;
     last = nullptr;
   }
@@ -149,9 +158,10 @@ aidg_status run(aidg_plan* p, KernelClass k, int64_t b0, int64_t n, const void* 
     Group g;
     std::memset(&g, 0, sizeof(g));
     g.n = 1;
-    g.total = n;
+    g.total_sg = n;
+    g.total_grp = p->sg_group[b0 + n - 1] - p->sg_group[b0] + 1;
     g.scratch = p->d_scratch;
-    g.job[0] = {p->d_args, in, out, b0, 0};
+    g.job[0] = {p->d_args, in, out, b0, b0 + n, p->sg_group[b0], 0, 0};
     rc = launch_group(k, p->g.L, p->g.precision, g, stream, p->max_nv);
   }
   if (rc != 0) return hip_fail((hipError_t)rc, "kernel launch");
@@ -269,22 +279,62 @@ aidg_status aidg_plan_create(const aidg_geometry* geo, int32_t n_stations, int32
       plan->w0.resize(plan->W);
       for (int j = 0; j < plan->W; ++j) plan->w0[j] = pr.w_step > 0 ? (pr.jmin + j) * pr.w_step : 0.0;
     }
-    // Order: A-term interval first (a batch then touches one interval's A-terms),
-    // then baseline; inside each batch the largest sub-tables go first so that the
-    // longest workgroups start early (longest-processing-time-first).
+    // Order: subgrids with the same w-layer and centre are consecutive, so that a
+    // group shares one image sum, one FFT and one grid update (gridding) or one
+    // split and inverse FFT (degridding).  A group is capped at kGroupVisFactor
+    // times the mean group's visibilities (larger ones become several groups with
+    // the same centre) so that no gridder workgroup runs far longer than the rest.
+    // Groups go longest-first (longest-processing-time-first), and inside a group
+    // the largest sub-tables go first for the degridder.
     {
       auto& t = plan->table;
+      auto same_centre = [](const aidg_subgrid& x, const aidg_subgrid& y) {
+        return x.wlayer == y.wlayer && x.U0 == y.U0 && x.V0 == y.V0;
+      };
       std::stable_sort(t.begin(), t.end(), [](const aidg_subgrid& x, const aidg_subgrid& y) {
+        if (x.wlayer != y.wlayer) return x.wlayer < y.wlayer;
+        if (x.V0 != y.V0) return x.V0 < y.V0;
+        if (x.U0 != y.U0) return x.U0 < y.U0;
+        if (x.nt * x.nc != y.nt * y.nc) return x.nt * x.nc > y.nt * y.nc;
         return x.aint != y.aint ? x.aint < y.aint : x.bl < y.bl;
       });
-      const size_t per_sg = (size_t)4 * g.L * g.L * plan->elem;
-      const int64_t bsz = std::max<int64_t>(1, std::min<int64_t>(g.workspace / (int64_t)per_sg, 65535));
-      for (size_t b0 = 0; b0 < t.size(); b0 += (size_t)bsz) {
-        const size_t b1 = std::min(t.size(), b0 + (size_t)bsz);
-        std::stable_sort(t.begin() + b0, t.begin() + b1, [](const aidg_subgrid& x, const aidg_subgrid& y) {
-          return x.nt * x.nc > y.nt * y.nc;
-        });
+      struct Span {
+        size_t b, e;
+        int64_t nv;
+      };
+      std::vector<Span> spans;
+      int64_t total_nv = 0, n_centres = 0;
+      for (size_t i = 0; i < t.size(); ++i) {
+        total_nv += (int64_t)t[i].nt * t[i].nc;
+        if (i == 0 || !same_centre(t[i], t[i - 1])) ++n_centres;
       }
+      const int64_t cap_nv = n_centres ? std::max<int64_t>(
+          (int64_t)g.max_sg_vis, kGroupVisFactor * ((total_nv + n_centres - 1) / n_centres)) : 1;
+      for (size_t i = 0; i < t.size();) {
+        size_t j = i;
+        int64_t nv = 0;
+        while (j < t.size() && same_centre(t[j], t[i]) &&
+               (j == i || nv + (int64_t)t[j].nt * t[j].nc <= cap_nv)) {
+          nv += (int64_t)t[j].nt * t[j].nc;
+          ++j;
+        }
+        spans.push_back({i, j, nv});
+        i = j;
+      }
+      std::stable_sort(spans.begin(), spans.end(), [](const Span& x, const Span& y) { return x.nv > y.nv; });
+      std::vector<aidg_subgrid> ordered;
+      ordered.reserve(t.size());
+      plan->grp_begin.assign(1, 0);
+      plan->sg_group.clear();
+      plan->sg_group.reserve(t.size());
+      for (const Span& sp : spans) {
+        for (size_t k = sp.b; k < sp.e; ++k) {
+          ordered.push_back(t[k]);
+          plan->sg_group.push_back((int32_t)(plan->grp_begin.size() - 1));
+        }
+        plan->grp_begin.push_back((int64_t)ordered.size());
+      }
+      t.swap(ordered);
     }
     plan->max_nv = 1;
     plan->vp_prefix.assign(plan->table.size() + 1, 0);
@@ -314,6 +364,7 @@ aidg_status aidg_plan_create(const aidg_geometry* geo, int32_t n_stations, int32
       d.vis0 = s.vis_offset;
       d.uvw0 = (int64_t)s.bl * n_times + s.t0;
       d.w0 = s.w0;
+      d.group = plan->sg_group[i];
       const double df = s.nc > 1 ? freqs_hz[s.c0 + 1] - freqs_hz[s.c0] : 0.0;
       bool uniform = true;
       for (int c = s.c0 + 1; c < s.c0 + s.nc; ++c)
@@ -341,9 +392,13 @@ aidg_status aidg_plan_create(const aidg_geometry* geo, int32_t n_stations, int32
     plan->aterm_bytes = (size_t)plan->n_int * n_stations * L * L * 4 * plan->elem;
     const size_t per_sg = (size_t)4 * L * L * plan->elem;
     const int64_t nsg = (int64_t)plan->table.size();
+    const int64_t n_groups = (int64_t)plan->grp_begin.size() - 1;
     plan->batch = std::max<int64_t>(1, std::min<int64_t>(g.workspace / (int64_t)per_sg, 65535));
-    plan->batch = std::min<int64_t>(plan->batch, std::max<int64_t>(nsg, 1));
+    plan->batch = std::min<int64_t>(plan->batch, std::max<int64_t>(n_groups, 1));
     plan->scratch_bytes = (size_t)plan->batch * per_sg;
+    plan->batch_begin.clear();
+    for (int64_t k = 0; k < n_groups; k += plan->batch) plan->batch_begin.push_back(plan->grp_begin[k]);
+    plan->batch_begin.push_back(nsg);
 
     hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
     hipError_t e = hipGetDevice(&plan->device);
@@ -358,6 +413,7 @@ aidg_status aidg_plan_create(const aidg_geometry* geo, int32_t n_stations, int32
         (st = dalloc(&plan->d_taper, (size_t)L * L * (f32 ? 4 : 8), plan, "taper")) ||
         (st = dalloc(&plan->d_tw, (size_t)L * (f32 ? 8 : 16), plan, "twiddles")) ||
         (st = dalloc(&plan->d_excl, pr.excluded.size() * sizeof(int64_t), plan, "excluded list")) ||
+        (st = dalloc(&plan->d_grp, plan->grp_begin.size() * sizeof(int64_t), plan, "group index")) ||
         (st = dalloc(&plan->d_scratch, plan->scratch_bytes, plan, "subgrid workspace")) ||
         (st = dalloc(&plan->d_args, sizeof(KernelArgs), plan, "launch parameters"))) {
       plan->release();
@@ -380,6 +436,7 @@ aidg_status aidg_plan_create(const aidg_geometry* geo, int32_t n_stations, int32
         {plan->d_tw, f32 ? (const void*)twf.data() : (const void*)tw.data(), (size_t)L * (f32 ? 8 : 16),
          hipMemcpyHostToDevice},
         {plan->d_excl, pr.excluded.data(), pr.excluded.size() * sizeof(int64_t), hipMemcpyHostToDevice},
+        {plan->d_grp, plan->grp_begin.data(), plan->grp_begin.size() * sizeof(int64_t), hipMemcpyHostToDevice},
         {plan->d_args, &host_args, sizeof(KernelArgs), hipMemcpyHostToDevice},
     };
     for (const Copy& c : copies) {
@@ -422,8 +479,8 @@ aidg_status aidg_plan_info_get(const aidg_plan* plan, aidg_plan_info* info) {
   info->workspace_bytes = (int64_t)plan->scratch_bytes;
   info->grid_bytes = (int64_t)plan->W * 4 * plan->g.N * plan->g.N * (int64_t)plan->elem;
   info->vis_bytes = info->n_vis * 4 * (int64_t)plan->elem;
-  const int64_t n = info->n_subgrids;
-  info->n_batches = n ? (n + plan->batch - 1) / plan->batch : 0;
+  info->n_batches = plan->batch_begin.empty() ? 0 : (int64_t)plan->batch_begin.size() - 1;
+  info->n_groups = plan->grp_begin.empty() ? 0 : (int64_t)plan->grp_begin.size() - 1;
   info->max_subgrid_vis = plan->max_nv;
   return AIDG_OK;
 }
@@ -460,9 +517,8 @@ aidg_status aidg_grid(aidg_plan* plan, const void* vis, void* grid, void* hip_st
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   hipError_t e = hipStreamWaitEvent(st, plan->last, 0);
   if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
-  const int64_t n = (int64_t)plan->table.size();
-  for (int64_t b0 = 0; b0 < n; b0 += plan->batch) {
-    const int64_t nb = std::min(plan->batch, n - b0);
+  for (size_t b = 0; b + 1 < plan->batch_begin.size(); ++b) {
+    const int64_t b0 = plan->batch_begin[b], nb = plan->batch_begin[b + 1] - b0;
     aidg_status r = run(plan, kGridDft, b0, nb, vis, nullptr, hip_stream);
     if (r == AIDG_OK) r = run(plan, kFftAdd, b0, nb, nullptr, grid, hip_stream);
     if (r != AIDG_OK) return r;
@@ -481,9 +537,8 @@ aidg_status aidg_degrid(aidg_plan* plan, const void* grid, void* vis_out, void* 
   aidg_status r = AIDG_OK;
   if (plan->n_excluded > 0) r = run(plan, kZeroVis, 0, 0, nullptr, vis_out, hip_stream);
   if (r != AIDG_OK) return r;
-  const int64_t n = (int64_t)plan->table.size();
-  for (int64_t b0 = 0; b0 < n; b0 += plan->batch) {
-    const int64_t nb = std::min(plan->batch, n - b0);
+  for (size_t b = 0; b + 1 < plan->batch_begin.size(); ++b) {
+    const int64_t b0 = plan->batch_begin[b], nb = plan->batch_begin[b + 1] - b0;
     r = run(plan, kSplitIfft, b0, nb, grid, nullptr, hip_stream);
     if (r == AIDG_OK) r = run(plan, kDegridDft, b0, nb, nullptr, vis_out, hip_stream);
     if (r != AIDG_OK) return r;
@@ -607,7 +662,7 @@ aidg_status aidg_execute(aidg_executor* ex, const aidg_work* items, int32_t n_it
     g.scratch = ex->d_scratch;
     int max_nv = 1;
     auto flush = [&]() -> aidg_status {
-      if (g.total == 0) return AIDG_OK;
+      if (g.total_sg == 0) return AIDG_OK;
       const KernelClass k0 = dir == AIDG_DIR_GRID ? kGridDft : kSplitIfft;
       const KernelClass k1 = dir == AIDG_DIR_GRID ? kFftAdd : kDegridDft;
       int rc = launch_group(k0, L, prec, g, hip_stream, max_nv);
@@ -621,15 +676,20 @@ aidg_status aidg_execute(aidg_executor* ex, const aidg_work* items, int32_t n_it
       const aidg_work& w = items[i];
       if (done[i] || w.direction != dir || w.plan->g.L != L || w.plan->g.precision != prec) continue;
       done[i] = true;
+      // a launch takes whole or partial groups until `cap` group images
+      const aidg_plan* p = w.plan;
       for (int64_t b = w.sg_begin; b < w.sg_end && r == AIDG_OK;) {
-        if (g.n == kMaxGroup || g.total == cap) r = flush();
+        if (g.n == kMaxGroup || g.total_grp == cap) r = flush();
         if (r != AIDG_OK) break;
-        const int64_t take = std::min(w.sg_end - b, cap - g.total);
-        g.job[g.n] = {w.plan->d_args, w.in, w.out, b, g.total};
+        const int64_t g0 = p->sg_group[b], room = cap - g.total_grp;
+        const int64_t gn = (int64_t)p->grp_begin.size() - 1;
+        const int64_t e = g0 + room < gn ? std::min(w.sg_end, p->grp_begin[g0 + room]) : w.sg_end;
+        g.job[g.n] = {p->d_args, w.in, w.out, b, e, g0, g.total_sg, g.total_grp};
         g.n += 1;
-        g.total += take;
-        max_nv = std::max(max_nv, w.plan->max_nv);
-        b += take;
+        g.total_sg += e - b;
+        g.total_grp += p->sg_group[e - 1] - g0 + 1;
+        max_nv = std::max(max_nv, p->max_nv);
+        b = e;
       }
     }
     if (r == AIDG_OK) r = flush();

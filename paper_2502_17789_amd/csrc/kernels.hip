@@ -44,12 +44,18 @@ constexpr int kThreads = 256;
 #ifndef GRID_PIX
 #define GRID_PIX 4
 #endif
+#ifndef GRID_WAVES
+#define GRID_WAVES 0
+#endif
 #ifndef DEGRID_WAVES
 #define DEGRID_WAVES 0
 #endif
 constexpr int kPix = GRID_PIX;              // pixels per lane in the gridder
 constexpr int kChunk = kThreads * kPix;     // pixels per workgroup pass
-constexpr int kVisGroup = 4;                // channels per degridder reduction
+#ifndef DEGRID_GROUP
+#define DEGRID_GROUP 4
+#endif
+constexpr int kVisGroup = DEGRID_GROUP;     // channels per degridder reduction (2 or 4)
 
 // Degridder pixels per lane: more pixels per lane amortise the per-visibility
 // cross-lane reduction; 256 * P must divide L^2.
@@ -158,10 +164,34 @@ __device__ __forceinline__ T load_uniform(const T* p) {
   return r;
 }
 
-// The job of a workgroup slot in a grouped launch, its parameters and subgrid.
+// Group slot of a grouped launch: the plan's parameters and its subgrid range.
+struct GroupSlot {
+  KernelArgs a;
+  int64_t sb, se;  // subgrids [sb, se) of the group within the job's range
+  const void* in;
+  void* out;
+};
+__device__ __forceinline__ GroupSlot resolve_group(const Group& g, int64_t slot) {
+  int j = 0;
+  for (int i = 1; i < g.n; ++i)
+    if (slot >= g.job[i].gslot_begin) j = i;
+  GroupSlot r;
+  r.a = load_uniform(g.job[j].args);
+  const int64_t grp = g.job[j].g_first + (slot - g.job[j].gslot_begin);
+  const_view<int64_t> gb = as_const(r.a.grp_begin);
+  r.sb = max(gb[grp], g.job[j].sg_begin);
+  r.se = min(gb[grp + 1], g.job[j].sg_end);
+  r.in = uniform(g.job[j].in);
+  r.out = uniform(g.job[j].out);
+  return r;
+}
+
+// Subgrid slot of a grouped launch (degridder): parameters, subgrid and the
+// scratch slot holding its group's image.
 struct Slot {
   KernelArgs a;
   SubgridDev s;
+  int64_t img_slot;
   const void* in;
   void* out;
 };
@@ -172,6 +202,7 @@ __device__ __forceinline__ Slot resolve(const Group& g, int64_t slot) {
   Slot r;
   r.a = load_uniform(g.job[j].args);
   r.s = load_uniform(r.a.sg + g.job[j].sg_begin + (slot - g.job[j].slot_begin));
+  r.img_slot = g.job[j].gslot_begin + (r.s.group - g.job[j].g_first);
   r.in = uniform(g.job[j].in);
   r.out = uniform(g.job[j].out);
   return r;
@@ -180,110 +211,127 @@ __device__ __forceinline__ Slot resolve(const Group& g, int64_t slot) {
 // ------------------------------------------------------------------ gridder
 
 template <int L, typename R>
-__global__ __launch_bounds__(kThreads) void grid_dft(const Group g) {
+__global__ __launch_bounds__(kThreads)
+#if GRID_WAVES > 0
+__attribute__((amdgpu_waves_per_eu(GRID_WAVES, GRID_WAVES)))
+#endif
+void grid_dft(const Group g) {
   using V2 = typename C2<R>::T;
   using V4 = typename C4<R>::T;
   extern __shared__ unsigned char smem_raw[];
-  V4* vlds = reinterpret_cast<V4*>(smem_raw);  // the subgrid's visibilities, 8 values each
+  V4* vlds = reinterpret_cast<V4*>(smem_raw);  // one subgrid's visibilities, 8 values each
   const int64_t local = blockIdx.y;
-  const Slot sl = resolve(g, local);
-  const KernelArgs& a = sl.a;
-  const SubgridDev& s = sl.s;
-  const R* __restrict__ vis = reinterpret_cast<const R*>(sl.in);
+  const GroupSlot gs = resolve_group(g, local);
+  const KernelArgs& a = gs.a;
+  const R* __restrict__ vis = reinterpret_cast<const R*>(gs.in);
   R* __restrict__ scratch = reinterpret_cast<R*>(g.scratch);
-
-  // Stage the sub-table (rows of nc visibilities, coalesced) in LDS; every lane then
-  // reads each visibility by a broadcast LDS load into vector registers, so the
-  // accumulation FMAs take only VGPR operands and can dual-issue.
-  const int nv = s.nt * s.nc;
-  for (int i = threadIdx.x; i < 2 * nv; i += kThreads) {
-    const int k = i >> 1, row = k / s.nc, c = k - row * s.nc;
-    vlds[i] = reinterpret_cast<const V4*>(vis)[(s.vis0 + (int64_t)row * a.nc_total + c) * 2 + (i & 1)];
-  }
-
-  Pixel px[kPix];
-#pragma unroll
-  for (int p = 0; p < kPix; ++p)
-    px[p] = pixel_at<L>(blockIdx.x * kChunk + p * kThreads + threadIdx.x, a.lstep);
-
-  R acc[kPix][8];
-#pragma unroll
-  for (int p = 0; p < kPix; ++p)
-#pragma unroll
-    for (int i = 0; i < 8; ++i) acc[p][i] = 0;
-  __syncthreads();
-
-  const double u0 = (s.U0 - a.N / 2) * a.du, v0 = (s.V0 - a.N / 2) * a.du;
-  for (int t = 0; t < s.nt; ++t) {
-    const_view<double> uvw = as_const(a.uvw + 3 * (s.uvw0 + t));
-    const double um = uvw[0], vm = uvw[1], wm = uvw[2];
-    const V4* vrow = vlds + 2 * t * s.nc;
-    // Phasors along the channels of the row: ph_{j+1} = ph_j * step, kept in two
-    // ping-pong registers (pa for even offsets from the seed, pb for odd ones).
-    V2 st[kPix];
-    {
-      const double su = um * s.dfc, sv = vm * s.dfc, sw = wm * s.dfc;
-#pragma unroll
-      for (int p = 0; p < kPix; ++p) st[p] = phasor(su * px[p].l + sv * px[p].m + sw * px[p].n1, R());
-    }
-    for (int j0 = 0; j0 < s.nc; j0 += s.R) {
-      const double fc = as_const(a.fc)[s.c0 + j0];
-      const double cu = um * fc - u0, cv = vm * fc - v0, cw = wm * fc - s.w0;
-      V2 pa[kPix], pb[kPix];
-#pragma unroll
-      for (int p = 0; p < kPix; ++p) pa[p] = phasor(cu * px[p].l + cv * px[p].m + cw * px[p].n1, R());
-      const int jn = min(s.nc, j0 + s.R);
-      auto mac = [&](int j, const V2 (&ph)[kPix]) {
-        const V4 va = vrow[2 * j], vb = vrow[2 * j + 1];
-        const R vv[8] = {va.x, va.y, va.z, va.w, vb.x, vb.y, vb.z, vb.w};
-#pragma unroll
-        for (int p = 0; p < kPix; ++p) {
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            acc[p][2 * q] = fma(vv[2 * q], ph[p].x, acc[p][2 * q]);
-            acc[p][2 * q] = fma(-vv[2 * q + 1], ph[p].y, acc[p][2 * q]);
-            acc[p][2 * q + 1] = fma(vv[2 * q], ph[p].y, acc[p][2 * q + 1]);
-            acc[p][2 * q + 1] = fma(vv[2 * q + 1], ph[p].x, acc[p][2 * q + 1]);
-          }
-        }
-      };
-      int j = j0;
-      for (; j + 1 < jn; j += 2) {
-        mac(j, pa);
-#pragma unroll
-        for (int p = 0; p < kPix; ++p) pb[p] = cmul<R>(pa[p], st[p]);
-        mac(j + 1, pb);
-#pragma unroll
-        for (int p = 0; p < kPix; ++p) pa[p] = cmul<R>(pb[p], st[p]);
-      }
-      if (j < jn) mac(j, pa);
-    }
-  }
-
-  // epilogue: S' = T (-1)^(x+y) A_p^H S A_q, one plane per polarisation
   const V2* At = reinterpret_cast<const V2*>(a.aterms);
+
+  // The group's image, sum over its subgrids of T (-1)^(x+y) A_p^H S A_q, builds up
+  // in its scratch slot; each lane owns its pixels there, so it reads back only
+  // what it wrote itself (keeping the sum out of registers keeps occupancy).
   const R* taper = reinterpret_cast<const R*>(a.taper);
   V2* out = reinterpret_cast<V2*>(scratch) + local * 4 * L * L;
+
+  for (int64_t si = gs.sb; si < gs.se; ++si) {
+    const SubgridDev s = load_uniform(a.sg + si);
+    __syncthreads();  // the previous subgrid's visibilities are no longer read
+    // Pixel coordinates are recomputed per subgrid from an opaque copy of the lane
+    // index: cheaper than holding them (and what derives from them) in registers
+    // across the subgrid loop, which would cost occupancy.
+    int lane = threadIdx.x;
+    asm volatile("" : "+v"(lane));
+    Pixel px[kPix];
 #pragma unroll
-  for (int p = 0; p < kPix; ++p) {
-    const int pix = px[p].pix;
-    const V2* Ap = At + ((int64_t)s.ap * L * L + pix) * 4;
-    const V2* Aq = At + ((int64_t)s.aq * L * L + pix) * 4;
-    V2 a0 = Ap[0], a1 = Ap[1], a2 = Ap[2], a3 = Ap[3];
-    a0.y = -a0.y; a1.y = -a1.y; a2.y = -a2.y; a3.y = -a3.y;  // conj
-    const V2 b0 = Aq[0], b1 = Aq[1], b2 = Aq[2], b3 = Aq[3];
-    const V2 s0 = {acc[p][0], acc[p][1]}, s1 = {acc[p][2], acc[p][3]};
-    const V2 s2 = {acc[p][4], acc[p][5]}, s3 = {acc[p][6], acc[p][7]};
-    // A_p^H = [[conj a0, conj a2], [conj a1, conj a3]]
-    const V2 t0 = cmul<R>(a0, s0) + cmul<R>(a2, s2);
-    const V2 t1 = cmul<R>(a0, s1) + cmul<R>(a2, s3);
-    const V2 t2 = cmul<R>(a1, s0) + cmul<R>(a3, s2);
-    const V2 t3 = cmul<R>(a1, s1) + cmul<R>(a3, s3);
-    const R w = taper[pix];
-    out[0 * L * L + pix] = (cmul<R>(t0, b0) + cmul<R>(t1, b2)) * w;
-    out[1 * L * L + pix] = (cmul<R>(t0, b1) + cmul<R>(t1, b3)) * w;
-    out[2 * L * L + pix] = (cmul<R>(t2, b0) + cmul<R>(t3, b2)) * w;
-    out[3 * L * L + pix] = (cmul<R>(t2, b1) + cmul<R>(t3, b3)) * w;
+    for (int p = 0; p < kPix; ++p) px[p] = pixel_at<L>(blockIdx.x * kChunk + p * kThreads + lane, a.lstep);
+    // Stage the sub-table (rows of nc visibilities, coalesced) in LDS; every lane then
+    // reads each visibility by a broadcast LDS load into vector registers, so the
+    // accumulation FMAs take only VGPR operands and can dual-issue.
+    const int nv = s.nt * s.nc;
+    for (int i = threadIdx.x; i < 2 * nv; i += kThreads) {
+      const int k = i >> 1, row = k / s.nc, c = k - row * s.nc;
+      vlds[i] = reinterpret_cast<const V4*>(vis)[(s.vis0 + (int64_t)row * a.nc_total + c) * 2 + (i & 1)];
+    }
+    R acc[kPix][8];
+#pragma unroll
+    for (int p = 0; p < kPix; ++p)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) acc[p][i] = 0;
+    __syncthreads();
+
+    const double u0 = (s.U0 - a.N / 2) * a.du, v0 = (s.V0 - a.N / 2) * a.du;
+    for (int t = 0; t < s.nt; ++t) {
+      const_view<double> uvw = as_const(a.uvw + 3 * (s.uvw0 + t));
+      const double um = uvw[0], vm = uvw[1], wm = uvw[2];
+      const V4* vrow = vlds + 2 * t * s.nc;
+      // Phasors along the channels of the row: ph_{j+1} = ph_j * step, kept in two
+      // ping-pong registers (pa for even offsets from the seed, pb for odd ones).
+      V2 st[kPix];
+      {
+        const double su = um * s.dfc, sv = vm * s.dfc, sw = wm * s.dfc;
+#pragma unroll
+        for (int p = 0; p < kPix; ++p) st[p] = phasor(su * px[p].l + sv * px[p].m + sw * px[p].n1, R());
+      }
+      for (int j0 = 0; j0 < s.nc; j0 += s.R) {
+        const double fc = as_const(a.fc)[s.c0 + j0];
+        const double cu = um * fc - u0, cv = vm * fc - v0, cw = wm * fc - s.w0;
+        V2 pa[kPix], pb[kPix];
+#pragma unroll
+        for (int p = 0; p < kPix; ++p) pa[p] = phasor(cu * px[p].l + cv * px[p].m + cw * px[p].n1, R());
+        const int jn = min(s.nc, j0 + s.R);
+        auto mac = [&](int j, const V2 (&ph)[kPix]) {
+          const V4 va = vrow[2 * j], vb = vrow[2 * j + 1];
+          const R vv[8] = {va.x, va.y, va.z, va.w, vb.x, vb.y, vb.z, vb.w};
+#pragma unroll
+          for (int p = 0; p < kPix; ++p) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              acc[p][2 * q] = fma(vv[2 * q], ph[p].x, acc[p][2 * q]);
+              acc[p][2 * q] = fma(-vv[2 * q + 1], ph[p].y, acc[p][2 * q]);
+              acc[p][2 * q + 1] = fma(vv[2 * q], ph[p].y, acc[p][2 * q + 1]);
+              acc[p][2 * q + 1] = fma(vv[2 * q + 1], ph[p].x, acc[p][2 * q + 1]);
+            }
+          }
+        };
+        int j = j0;
+        for (; j + 1 < jn; j += 2) {
+          mac(j, pa);
+#pragma unroll
+          for (int p = 0; p < kPix; ++p) pb[p] = cmul<R>(pa[p], st[p]);
+          mac(j + 1, pb);
+#pragma unroll
+          for (int p = 0; p < kPix; ++p) pa[p] = cmul<R>(pb[p], st[p]);
+        }
+        if (j < jn) mac(j, pa);
+      }
+    }
+
+    // Jones correction of this subgrid, A_p^H S A_q, one plane per polarisation,
+    // tapered and added to the group's image
+#pragma unroll
+    for (int p = 0; p < kPix; ++p) {
+      const int pix = px[p].pix;
+      const V2* Ap = At + ((int64_t)s.ap * L * L + pix) * 4;
+      const V2* Aq = At + ((int64_t)s.aq * L * L + pix) * 4;
+      V2 a0 = Ap[0], a1 = Ap[1], a2 = Ap[2], a3 = Ap[3];
+      a0.y = -a0.y; a1.y = -a1.y; a2.y = -a2.y; a3.y = -a3.y;  // conj
+      const V2 b0 = Aq[0], b1 = Aq[1], b2 = Aq[2], b3 = Aq[3];
+      const V2 s0 = {acc[p][0], acc[p][1]}, s1 = {acc[p][2], acc[p][3]};
+      const V2 s2 = {acc[p][4], acc[p][5]}, s3 = {acc[p][6], acc[p][7]};
+      // A_p^H = [[conj a0, conj a2], [conj a1, conj a3]]
+      const V2 t0 = cmul<R>(a0, s0) + cmul<R>(a2, s2);
+      const V2 t1 = cmul<R>(a0, s1) + cmul<R>(a2, s3);
+      const V2 t2 = cmul<R>(a1, s0) + cmul<R>(a3, s2);
+      const V2 t3 = cmul<R>(a1, s1) + cmul<R>(a3, s3);
+      const R w = taper[pix];
+      V2 c[4] = {(cmul<R>(t0, b0) + cmul<R>(t1, b2)) * w, (cmul<R>(t0, b1) + cmul<R>(t1, b3)) * w,
+                 (cmul<R>(t2, b0) + cmul<R>(t3, b2)) * w, (cmul<R>(t2, b1) + cmul<R>(t3, b3)) * w};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (si != gs.sb) c[q] += out[q * L * L + pix];
+        out[q * L * L + pix] = c[q];
+      }
+    }
   }
 }
 
@@ -383,10 +431,10 @@ __global__ __launch_bounds__(kThreads) void fft_add(const Group g) {
   __shared__ V2 tw[L];
   const int pol = blockIdx.x;
   const int64_t local = blockIdx.y;
-  const Slot sl = resolve(g, local);
-  const KernelArgs& a = sl.a;
-  const SubgridDev& s = sl.s;
-  R* grid = reinterpret_cast<R*>(sl.out);
+  const GroupSlot gs = resolve_group(g, local);
+  const KernelArgs& a = gs.a;
+  const SubgridDev s = load_uniform(a.sg + gs.sb);  // centre and w-layer of the group
+  R* grid = reinterpret_cast<R*>(gs.out);
   const V2* in = reinterpret_cast<const V2*>(g.scratch) + (local * 4 + pol) * L * L;
   for (int e = threadIdx.x; e < L * L; e += kThreads) buf[(e / L) * pitch(L) + e % L] = in[e];
   for (int e = threadIdx.x; e < L; e += kThreads) tw[e] = reinterpret_cast<const V2*>(a.twiddle)[e];
@@ -411,10 +459,10 @@ __global__ __launch_bounds__(kThreads) void split_ifft(const Group g) {
   __shared__ V2 tw[L];
   const int pol = blockIdx.x;
   const int64_t local = blockIdx.y;
-  const Slot sl = resolve(g, local);
-  const KernelArgs& a = sl.a;
-  const SubgridDev& s = sl.s;
-  const R* __restrict__ grid = reinterpret_cast<const R*>(sl.in);
+  const GroupSlot gs = resolve_group(g, local);
+  const KernelArgs& a = gs.a;
+  const SubgridDev s = load_uniform(a.sg + gs.sb);  // centre and w-layer of the group
+  const R* __restrict__ grid = reinterpret_cast<const R*>(gs.in);
   R* __restrict__ scratch = reinterpret_cast<R*>(g.scratch);
   const V2* win = reinterpret_cast<const V2*>(grid) +
                   (((int64_t)s.wlayer * 4 + pol) * a.N + (s.V0 - L / 2)) * a.N + (s.U0 - L / 2);
@@ -516,6 +564,35 @@ __device__ __forceinline__ R transpose_reduce32(R (&a)[32], int ln) {
   return a[0] + dpp<kDppXor1>(a[0]);
 }
 
+// Sum 16 per-lane values over the 64 lanes of a wave.  On return lane `ln` holds
+// the full sum of value index (ln >> 2).
+template <typename R>
+__device__ __forceinline__ R transpose_reduce16(R (&a)[16], int ln) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    swap32(a[i], a[i + 8]);
+    a[i] = a[i] + a[i + 8];  // lanes 0-31: value i, lanes 32-63: value i+8
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    swap16(a[i], a[i + 4]);
+    a[i] = a[i] + a[i + 4];  // row r holds value i + 4r
+  }
+  const bool b3 = ln & 8, b2 = ln & 4;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const R keep = b3 ? a[i + 2] : a[i], send = b3 ? a[i] : a[i + 2];
+    a[i] = keep + dpp<kDppRowRor8>(send);  // value i + 2 b3 + 4 row
+  }
+  {
+    const R keep = b2 ? a[1] : a[0], send = b2 ? a[0] : a[1];
+    a[0] = keep + dpp<kDppHalfMirror>(send);  // value b2 + 2 b3 + 4 row = ln >> 2
+  }
+  // lanes ln, ln^2, ln^1 (and the mirror partner above) share the value index
+  a[0] = a[0] + dpp<kDppXor2>(a[0]);
+  return a[0] + dpp<kDppXor1>(a[0]);
+}
+
 template <int L, typename R>
 __global__ __launch_bounds__(kThreads)
 #if DEGRID_WAVES > 0
@@ -539,7 +616,7 @@ void degrid_dft(const Group g) {
   const int ln = threadIdx.x & 63;
   const V2* At = reinterpret_cast<const V2*>(a.aterms);
   const R* taper = reinterpret_cast<const R*>(a.taper);
-  const V2* img = reinterpret_cast<const V2*>(scratch) + local * 4 * L * L;
+  const V2* img = reinterpret_cast<const V2*>(scratch) + sl.img_slot * 4 * L * L;
   const double u0 = (s.U0 - a.N / 2) * a.du, v0 = (s.V0 - a.N / 2) * a.du;
 
   for (int chunk = 0; chunk < (L * L) / CH; ++chunk) {
@@ -585,7 +662,7 @@ void degrid_dft(const Group g) {
       }
       int since_seed = s.R;  // channels since the last FP64 re-seed
       for (int g0 = 0; g0 < s.nc; g0 += kVisGroup) {
-        R part[32];
+        R part[8 * kVisGroup];
 #pragma unroll
         for (int v = 0; v < kVisGroup; ++v) {
           const int j = g0 + v;
@@ -619,9 +696,19 @@ void degrid_dft(const Group g) {
             }
           }
         }
-        const R val = transpose_reduce32<R>(part, ln);
-        const int idx = ln >> 1, v = idx >> 3, comp = idx & 7;
-        if (!(ln & 1) && g0 + v < s.nc) atomicAdd(&accs[(t * s.nc + g0 + v) * 8 + comp], val);
+        R val;
+        int idx, lead;
+        if constexpr (kVisGroup == 4) {
+          val = transpose_reduce32<R>(part, ln);
+          idx = ln >> 1;
+          lead = !(ln & 1);
+        } else {
+          val = transpose_reduce16<R>(part, ln);
+          idx = ln >> 2;
+          lead = !(ln & 3);
+        }
+        const int v = idx >> 3, comp = idx & 7;
+        if (lead && g0 + v < s.nc) atomicAdd(&accs[(t * s.nc + g0 + v) * 8 + comp], val);
       }
     }
   }
@@ -640,7 +727,7 @@ __global__ void zero_vis(const int64_t* __restrict__ idx, int64_t n, R* vis) {
 
 template <int L, typename R>
 int launch_one(KernelClass k, const Group& g, hipStream_t st, int max_nv) {
-  const unsigned n = (unsigned)g.total;
+  const unsigned n = (unsigned)(k == kDegridDft ? g.total_sg : g.total_grp);
   switch (k) {
     case kGridDft:
       hipLaunchKernelGGL((grid_dft<L, R>), dim3((L * L) / kChunk, n), dim3(kThreads),
@@ -666,7 +753,9 @@ int launch_one(KernelClass k, const Group& g, hipStream_t st, int max_nv) {
 
 int launch_group(KernelClass k, int L, int precision, const Group& g, void* stream, int max_nv) {
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  if (g.total <= 0 || g.n < 1 || g.n > kMaxGroup) return g.total <= 0 ? 0 : (int)hipErrorInvalidValue;
+  if (g.total_sg <= 0) return 0;
+  if (g.n < 1 || g.n > kMaxGroup || g.total_grp < 1 || g.total_grp > 65535 || g.total_grp > g.total_sg)
+    return (int)hipErrorInvalidValue;
   if (precision == AIDG_FP32) {
     switch (L) {
       case 32: return launch_one<32, float>(k, g, st, max_nv);

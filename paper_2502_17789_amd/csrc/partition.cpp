@@ -62,6 +62,16 @@ aidg_status validate_geometry(const aidg_geometry* g, Geometry* o, std::string* 
   o->du = 1.0 / fov;
   o->beta = g->taper_beta > 0 ? g->taper_beta : M_PI * K / 4.0;
   o->workspace = g->workspace_bytes ? g->workspace_bytes : kWorkspaceDefault;
+  if (g->center_lattice < 0) {
+    *err = "center_lattice must be >= 0";
+    return AIDG_E_INVALID;
+  }
+  if (g->center_lattice > 0) {
+    o->lattice = g->center_lattice;
+  } else {
+    o->lattice = 1;
+    while (o->lattice * 2 <= (L - K) / 8) o->lattice *= 2;
+  }
   if (g->w_step > 0) o->w_step = g->w_step;
   else if (g->w_step < 0) o->w_step = 0.0;
   else o->w_step = auto_w_step(*o);
@@ -113,14 +123,32 @@ struct Box {
   }
 };
 
-// Integer centre for a span, clamped to keep the window on the grid; true if
-// every point of the span is within half of it.
-bool centre(double lo, double hi, double half, int L, int N, int* c) {
+// Centre cell for a span [lo, hi]: a cell of the lattice N/2 + k * lattice near the
+// middle of the span (clamped so that the L-cell window stays on the grid); true
+// if every point of the span is then within `half` cells of it.
+bool centre(double lo, double hi, double half, int L, int N, int lattice, int* c) {
   const double mid = 0.5 * (lo + hi);
+  const double k0 = std::floor((mid - N / 2) / lattice);
+  int best = 0;
+  double best_d = 1e300;
+  for (int dk = -1; dk <= 2; ++dk) {
+    int k = N / 2 + (int)(k0 + dk) * lattice;
+    k = std::min(std::max(k, L / 2), N - L / 2);
+    if (hi - k <= half && k - lo <= half) {
+      const double d = std::fabs(k - mid);
+      if (d < best_d) {
+        best_d = d;
+        best = k;
+      }
+    }
+  }
+  if (best_d < 1e300) {
+    *c = best;
+    return true;
+  }
   int k = (int)std::floor(mid + 0.5);
-  k = std::min(std::max(k, L / 2), N - L / 2);
-  *c = k;
-  return hi - k <= half && k - lo <= half;
+  *c = std::min(std::max(k, L / 2), N - L / 2);
+  return false;
 }
 
 // Add row t, channels [c0, c1), to box b; false if a visibility is unplaceable
@@ -161,7 +189,7 @@ void tile(const Ctx& x, int bl, int ts, int te, int c_lo, int c_hi, PartitionRes
       Box q = b;
       q.add(x.cell(bl, ts, e, 0), x.cell(bl, ts, e, 1));
       if (q.uhi - q.ulo > comfy || q.vhi - q.vlo > comfy) break;
-      if (!centre(q.ulo, q.uhi, half, g.L, g.N, &cu) || !centre(q.vlo, q.vhi, half, g.L, g.N, &cv))
+      if (!centre(q.ulo, q.uhi, half, g.L, g.N, g.lattice, &cu) || !centre(q.vlo, q.vhi, half, g.L, g.N, g.lattice, &cv))
         break;
       b = q;
       ++e;
@@ -170,14 +198,14 @@ void tile(const Ctx& x, int bl, int ts, int te, int c_lo, int c_hi, PartitionRes
     while (t1 < te && (int64_t)(t1 - ts + 1) * (e - c) <= g.max_sg_vis) {
       Box q = b;
       if (!add_row(x, bl, t1, c, e, lay, &q)) break;
-      if (!centre(q.ulo, q.uhi, half, g.L, g.N, &cu) || !centre(q.vlo, q.vhi, half, g.L, g.N, &cv))
+      if (!centre(q.ulo, q.uhi, half, g.L, g.N, g.lattice, &cu) || !centre(q.vlo, q.vhi, half, g.L, g.N, g.lattice, &cv))
         break;
       b = q;
       ++t1;
     }
     int U0, V0;
-    centre(b.ulo, b.uhi, half, g.L, g.N, &U0);
-    centre(b.vlo, b.vhi, half, g.L, g.N, &V0);
+    centre(b.ulo, b.uhi, half, g.L, g.N, g.lattice, &U0);
+    centre(b.vlo, b.vhi, half, g.L, g.N, g.lattice, &V0);
     aidg_subgrid s;
     std::memset(&s, 0, sizeof(s));
     s.bl = bl;

@@ -7,11 +7,15 @@ L = Re sum conj(R) V(G) with complex Gaussian R.  Central finite differences on
 the real and imaginary parts of 100 random grid cells (90 inside the footprint
 the subgrid windows cover, 10 outside, where the gradient must be exactly zero)
 are compared with autograd's gradient (PyTorch convention: dL/dRe + i dL/dIm).
-FP64 path: step h = 1e-3 rms(G), relative error <= 1e-6 per probe.  FP32 path:
-the loss sums 2.9M visibilities whose FP32 rounding (~3e-7 normwise) makes the
-loss uncertain by about as much as a 1e-3 rms(G) step changes it, so the step
-is h = 10 rms(G) (L is linear in G: the step size trades nothing else); gates
-median <= 1e-2 and max <= 5e-2.  The adjoint residual is checked through
+L is linear in G, so the central difference is exact up to the rounding of the
+two loss evaluations, an absolute error of about eps |L| / h per probe; it is
+therefore measured against the RMS gradient over the probes inside the footprint
+(a per-probe relative error would blow up at cells where the taper makes the
+gradient tiny).  FP64 path: step h = 1e-3 rms(G), error <= 1e-6 rms(grad) per
+probe.  FP32 path: the loss sums 2.9M visibilities whose FP32 rounding (~3e-7
+normwise) makes it uncertain by about as much as a 1e-3 rms(G) step changes it,
+so the step is h = 10 rms(G) (the step size trades nothing else); gates median
+<= 1e-2 and max <= 5e-2 of rms(grad).  The adjoint residual is checked through
 autograd as well.
 """
 import numpy as np
@@ -91,9 +95,10 @@ def test_degrid_backward_finite_differences(precision):
                     outside_fd.append(abs(fd))
                 else:
                     inside_g.append(abs(ref))
-                    errs.append(abs(fd - ref) / max(abs(ref), 1e-300))
-        assert max(outside_fd) <= (1e-8 if precision == 1 else 5e-2) * np.median(inside_g)
-        errs = np.array(errs)
+                    errs.append(abs(fd - ref))
+        scale = float(np.sqrt(np.mean(np.square(inside_g))))
+        assert max(outside_fd) <= (1e-8 if precision == 1 else 5e-2) * scale
+        errs = np.array(errs) / scale
         print(f"precision {precision}: FD vs autograd median {np.median(errs):.3e} max {errs.max():.3e}",
               flush=True)
         if precision == 1:
