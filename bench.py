@@ -67,6 +67,13 @@ def parse():
                     help="served mixed workload instead of the MWA-like job (separate JSON line)")
     ap.add_argument("--jobs", type=int, default=300)
     ap.add_argument("--rho", type=float, nargs="+", default=[0.8, 1.2])
+    ap.add_argument("--precision", action="store_true",
+                    help="precision study: FP32 path (reseed interval swept) against the FP64 path "
+                         "on the MWA-like workload, over screen rms and w-range (JSON line per case)")
+    ap.add_argument("--screens", type=float, nargs="+", default=[0.5, 2.0, 5.0])
+    ap.add_argument("--wmax", type=float, nargs="+", default=[0.0, 250.0, 500.0],
+                    help="largest |w| in wavelengths (0 = at transit)")
+    ap.add_argument("--reseed", type=int, nargs="+", default=[8, 16, 32, 96])
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device-to-device 3 times (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -204,6 +211,86 @@ def serve_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def precision_study(args):
+    """FP32 path (phasor recurrence re-seeded from FP64 every R channels) against the
+    full-FP64 path on the MWA-like workload.  Visibilities: 300 point sources
+    (0.01-30 Jy, log-uniform) plus unit noise, evaluated in FP64 on the device; the
+    degridding input is the FP64 grid of those visibilities.  Per result: normwise
+    relative error and max|d|/max|ref|; per visibility (|V_k|_F >= 1e-3 rms):
+    max, p99 and rms of |dV_k|_F / |V_k|_F."""
+    import torch
+
+    import paper_2502_17789_amd as aidg
+    import synth
+
+    torch.cuda.set_device(0)
+
+    def norm_err(x, ref):
+        num = den = 0.0
+        dmax = rmax = 0.0
+        for j in range(ref.shape[0]):           # layer by layer: bounded temporaries
+            d = x[j].to(torch.complex128) - ref[j]
+            num += float(torch.linalg.vector_norm(d)) ** 2
+            den += float(torch.linalg.vector_norm(ref[j])) ** 2
+            dmax = max(dmax, float(d.abs().max()))
+            rmax = max(rmax, float(ref[j].abs().max()))
+        return num ** 0.5 / max(den ** 0.5, 1e-300), dmax / max(rmax, 1e-300)
+
+    def vis_err(x, ref):
+        d = (x.to(torch.complex128) - ref)
+        nd = torch.linalg.vector_norm(d, dim=-1)
+        nr = torch.linalg.vector_norm(ref, dim=-1)
+        sel = nr >= 1e-3 * torch.sqrt((nr * nr).mean())
+        r = (nd[sel] / nr[sel]).flatten()
+        q = torch.quantile(r[torch.randperm(r.numel(), device=r.device)[:1 << 24]], 0.99)
+        return {"normwise": float(torch.linalg.vector_norm(d) / torch.linalg.vector_norm(ref)),
+                "per_vis_max": float(r.max()), "per_vis_p99": float(q),
+                "per_vis_rms": float(torch.sqrt((r * r).mean()))}
+
+    for wmax in args.wmax:
+        ha = synth.hour_angle_for_wmax(wmax) if wmax > 0 else 0.0
+        for rms in args.screens:
+            t0 = time.perf_counter()
+            wl = synth.config_mwa(seed=2, screen_rms=rms, ha0_rad=ha)
+            w_top = float(np.abs(wl.uvw[..., 2]).max() * wl.freqs.max() / 299792458.0)
+            base = dict(grid_size=wl.grid_size, subgrid_size=wl.subgrid_size,
+                        kernel_support=wl.kernel_support, pixel_scale=wl.pixel_scale,
+                        aterm_interval=wl.aterm_interval)
+            V64 = synth.device_point_source_vis(wl, 300, seed=3)
+            A64 = torch.from_numpy(wl.aterms).cuda()
+            with aidg.Plan(aidg.Geometry(precision=aidg.FP64, **base), wl.n_stations, wl.baselines,
+                           wl.uvw, wl.freqs, A64) as p64:
+                info = p64.info
+                G64 = p64.grid(V64)
+                Vd64 = p64.degrid(G64)
+                torch.cuda.synchronize()
+            del A64
+            G32in = torch.empty(G64.shape, dtype=torch.complex64, device="cuda")
+            for j in range(G64.shape[0]):
+                G32in[j] = G64[j].to(torch.complex64)
+            V32in = V64.to(torch.complex64)
+            A32 = torch.from_numpy(wl.aterms.astype(np.complex64)).cuda()
+            for R in args.reseed:
+                with aidg.Plan(aidg.Geometry(precision=aidg.FP32, reseed_channels=R, **base),
+                               wl.n_stations, wl.baselines, wl.uvw, wl.freqs, A32) as p32:
+                    assert p32.info["n_wlayers"] == info["n_wlayers"]
+                    G32 = p32.grid(V32in)
+                    Vd32 = p32.degrid(G32in)
+                    torch.cuda.synchronize()
+                g_norm, g_max = norm_err(G32, G64)
+                ve = vis_err(Vd32, Vd64)
+                del G32, Vd32
+                print(json.dumps({
+                    "precision_case": {"screen_rms_rad": rms, "max_abs_w_lambda": round(w_top, 1),
+                                       "hour_angle_rad": round(ha, 5), "n_wlayers": info["n_wlayers"],
+                                       "w_step": round(info["w_step"], 3), "reseed_channels": R},
+                    "grid_fp32_vs_fp64": {"normwise": g_norm, "max_over_max": g_max},
+                    "degrid_fp32_vs_fp64": ve,
+                    "elapsed_s": round(time.perf_counter() - t0, 1)}), flush=True)
+            del G64, Vd64, G32in, V32in, V64, A32
+            torch.cuda.empty_cache()
+
+
 def dataclasses_replace(obj, **kw):
     import dataclasses
     return dataclasses.replace(obj, **kw)
@@ -220,6 +307,9 @@ def main():
 
     if args.serve:
         serve_bench(args)
+        return
+    if args.precision:
+        precision_study(args)
         return
     if args.copy_probe:
         import torch

@@ -372,3 +372,55 @@ def device_phase_screen_aterms(n_st: int, L: int, rms: float, seed: int, coarse:
     A[0, :, :, :, 0] = e
     A[0, :, :, :, 3] = e
     return A
+
+
+def hour_angle_for_wmax(w_target: float, seed: int = 2, lo: float = 0.0, hi: float = 1.0) -> float:
+    """Phase-centre hour angle (rad) at which the MWA-like observation's largest
+    |w| at the top channel reaches w_target wavelengths (bisection on ha0)."""
+    c = 299792458.0
+
+    def wmax(ha):
+        _, uvw, f = observation(128, 5000.0, 60, 2.0, 140e6, 170e6, 96, np.random.default_rng(seed),
+                                ha0_rad=ha)
+        return float(np.abs(uvw[..., 2]).max() * f.max() / c)
+
+    if wmax(lo) >= w_target:
+        return lo
+    for _ in range(40):
+        mid = 0.5 * (lo + hi)
+        if wmax(mid) < w_target:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+def device_point_source_vis(wl: "Workload", n_src: int, seed: int, flux_lo: float = 0.01,
+                            flux_hi: float = 30.0, noise_rms: float = 1.0, chunk: int = 32):
+    """Visibilities of a point-source sky (identity Jones), evaluated in FP64 on the
+    GPU: V = sum_s B_s exp(-2 pi i (u l_s + v m_s + w n1_s)) plus complex Gaussian
+    noise of the given rms per component.  Returns complex128 [nbl, nt, nc, 4]."""
+    import torch
+    rng = np.random.default_rng(seed)
+    src = point_sources(n_src, wl.fov, flux_lo, flux_hi, rng)
+    l = torch.from_numpy(src["l"]).cuda()
+    m = torch.from_numpy(src["m"]).cuda()
+    n1 = -(l * l + m * m) / (1.0 + torch.sqrt(1.0 - l * l - m * m))
+    B = torch.from_numpy(src["B"]).cuda()                               # [S, 4]
+    fc = torch.from_numpy(wl.freqs / 299792458.0).cuda()               # [nc]
+    uvw = torch.from_numpy(wl.uvw).cuda()                              # [nbl, nt, 3] metres
+    out = torch.empty((wl.n_baselines, wl.n_times, wl.n_chans, 4), dtype=torch.complex128, device="cuda")
+    for b0 in range(0, wl.n_baselines, chunk):
+        u = uvw[b0:b0 + chunk]
+        # phase in turns per metre of baseline, then per channel: [b, t, S] x [c]
+        pm = u[..., 0:1] * l + u[..., 1:2] * m + u[..., 2:3] * n1
+        turns = pm[:, :, None, :] * fc[None, None, :, None]             # [b, t, c, S]
+        turns = turns - torch.round(turns)
+        ph = torch.polar(torch.ones_like(turns), -2.0 * math.pi * turns)
+        out[b0:b0 + chunk] = ph @ B
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    # torch draws complex normals with E|z|^2 = 1: scale to noise_rms per component
+    out += noise_rms * math.sqrt(2.0) * torch.randn(out.shape, dtype=torch.complex128, device="cuda",
+                                                    generator=g)
+    return out

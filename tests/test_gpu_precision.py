@@ -1,0 +1,99 @@
+"""Precision at the MWA-like geometry: FP32 path (phasor recurrence re-seeded from
+FP64 origins) and FP64 path against the FP64 oracle.
+
+Workload: 16 random baselines (seed 2) of the MWA-like observation at full
+60 x 96 sampling, grid 8000^2 at 15 arcsec, L = 96, K = 24, A-terms every 8
+timesteps (beam x Kolmogorov screen), with the screen rms swept over 0.5, 2 and
+5 rad at transit (|w| <= 18 wavelengths, one w-layer) and one case at 2 rad with
+the phase centre moved off transit so that the full observation's |w| reaches
+80 wavelengths (62 in the subset: three w-layers).  Visibilities: 300 point
+sources (0.01-30 Jy, log-uniform, identity Jones) plus unit noise, evaluated in
+FP64; the degridding input is the oracle's grid of them.  The library partitions; the oracle consumes the same table.
+
+Gates (normwise relative error per result): FP32 <= 1e-5, FP64 <= 1e-10.  The
+per-visibility error distribution (|V_k|_F >= 1e-3 rms) is printed beside it.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+C = 299792458.0
+
+
+def sky_vis(wl, n_src=300, seed=3):
+    rng = np.random.default_rng(seed)
+    src = synth.point_sources(n_src, wl.fov, 0.01, 30.0, rng)
+    l, m = src["l"], src["m"]
+    n1 = -(l * l + m * m) / (1.0 + np.sqrt(1.0 - l * l - m * m))
+    V = np.empty((wl.n_baselines, wl.n_times, wl.n_chans, 4), np.complex128)
+    fc = wl.freqs / C
+    for b in range(wl.n_baselines):
+        pm = wl.uvw[b, :, 0:1] * l + wl.uvw[b, :, 1:2] * m + wl.uvw[b, :, 2:3] * n1   # [t, S] metres
+        turns = pm[:, None, :] * fc[None, :, None]
+        turns -= np.round(turns)
+        V[b] = np.exp(-2j * np.pi * turns) @ src["B"]
+    V += (rng.standard_normal(V.shape) + 1j * rng.standard_normal(V.shape))
+    return V
+
+
+def per_vis(x, ref):
+    nd = np.linalg.norm(x - ref, axis=-1)
+    nr = np.linalg.norm(ref, axis=-1)
+    sel = nr >= 1e-3 * np.sqrt(np.mean(nr * nr))
+    r = nd[sel] / nr[sel]
+    return r.max(), np.percentile(r, 99), np.sqrt(np.mean(r * r))
+
+
+def rel(a, b):
+    """Normwise relative error, accumulated per leading index (bounded temporaries)."""
+    num = sum(float(np.linalg.norm((a[i] - b[i]).ravel())) ** 2 for i in range(b.shape[0]))
+    den = sum(float(np.linalg.norm(b[i].ravel())) ** 2 for i in range(b.shape[0]))
+    return math.sqrt(num / den)
+
+
+CASES = [(0.5, 0.0), (2.0, 0.0), (5.0, 0.0), (2.0, 80.0)]
+
+
+@pytest.mark.parametrize("rms,wmax", CASES)
+def test_mwa_subset_precision(orc, rms, wmax):
+    import paper_2502_17789_amd as aidg
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ha = synth.hour_angle_for_wmax(wmax) if wmax > 0 else 0.0
+    wl = synth.config_mwa(seed=2, n_bl_subset=16, screen_rms=rms, ha0_rad=ha)
+    V = sky_vis(wl)
+    results = {}
+    table = None
+    for prec, cdt in ((aidg.FP64, torch.complex128), (aidg.FP32, torch.complex64)):
+        geo = aidg.Geometry(wl.grid_size, wl.subgrid_size, wl.kernel_support, wl.pixel_scale,
+                            aterm_interval=wl.aterm_interval, precision=prec)
+        A = torch.from_numpy(wl.aterms).to(cdt).cuda()
+        with aidg.Plan(geo, wl.n_stations, wl.baselines, wl.uvw, wl.freqs, A) as p:
+            if table is None:
+                table = p.subgrids()
+                W = p.n_wlayers
+                Gref = orc.grid(wl, V, table, W=W)
+                Vref = orc.degrid(wl, Gref, table)
+            else:
+                assert np.array_equal(p.subgrids(), table)
+            Gg = p.grid(torch.from_numpy(V).to(cdt).cuda())
+            Vg = p.degrid(torch.from_numpy(Gref).to(cdt).cuda())
+            torch.cuda.synchronize()
+            results[prec] = (rel(Gg.cpu().numpy(), Gref), rel(Vg.cpu().numpy(), Vref),
+                             per_vis(Vg.cpu().numpy().astype(np.complex128), Vref))
+            del Gg, Vg, A
+    w_top = float(np.abs(wl.uvw[..., 2]).max() * wl.freqs.max() / C)
+    for prec, (eg, ev, (pmax, p99, prms)) in results.items():
+        print(f"screen {rms} rad, |w| <= {w_top:.0f} lambda, {W} layer(s), "
+              f"{'FP64' if prec else 'FP32'}: grid {eg:.3e} degrid {ev:.3e}; per-vis max {pmax:.2e} "
+              f"p99 {p99:.2e} rms {prms:.2e}", flush=True)
+    if wmax > 0:
+        assert W > 1
+    assert results[aidg.FP32][0] <= 1e-5 and results[aidg.FP32][1] <= 1e-5
+    assert results[aidg.FP64][0] <= 1e-10 and results[aidg.FP64][1] <= 1e-10
