@@ -390,7 +390,7 @@ def main():
     kernels = {name: {"ms_per_step": round(v["ms"] / args.steps, 3),
                       "launches_per_step": v["launches"] / args.steps,
                       **({"tflops": round(v["vis_pixels"] * FLOP_PER_VP / (v["ms"] * 1e-3) / 1e12, 3)}
-                         if v["vis_pixels"] and v["ms"] > 0 else {})}
+                         if name in ("grid_dft", "degrid_dft") and v["ms"] > 0 else {})}
                for name, v in kt.items()}
     out = {
         "metric": "Mvisibilities/sec gridded+degridded (with A-terms) at 1e-5 rel err; p50/p99 job latency",

@@ -33,10 +33,6 @@
 
 #include "aidg_internal.h"
 
-#ifndef DEGRID_PIX96
-#define DEGRID_PIX96 9
-#endif
-
 namespace aidg {
 namespace {
 
@@ -47,22 +43,20 @@ constexpr int kThreads = 256;
 #ifndef GRID_WAVES
 #define GRID_WAVES 0
 #endif
-#ifndef DEGRID_WAVES
-#define DEGRID_WAVES 0
-#endif
 constexpr int kPix = GRID_PIX;              // pixels per lane in the gridder
 constexpr int kChunk = kThreads * kPix;     // pixels per workgroup pass
 #ifndef DEGRID_GROUP
 #define DEGRID_GROUP 4
 #endif
 constexpr int kVisGroup = DEGRID_GROUP;     // channels per degridder reduction (2 or 4)
+static_assert(kVisGroup == 2 || kVisGroup == 4, "even group: phasor ping-pong restarts in the first set");
 
-// Degridder pixels per lane: more pixels per lane amortise the per-visibility
-// cross-lane reduction; 256 * P must divide L^2.
-template <int L> struct DegridPix;
-template <> struct DegridPix<32> { static constexpr int P = 4; };
-template <> struct DegridPix<64> { static constexpr int P = 8; };
-template <> struct DegridPix<96> { static constexpr int P = DEGRID_PIX96; };
+// Degridder tiling: P pixels per lane (more pixels amortise the per-visibility
+// cross-lane reduction; 256 * P must divide L^2) and the waves per SIMD the
+// register allocation aims at (W; 1 leaves it to the compiler).  At L = 96 in
+// FP32, P = 6 at 3 waves per SIMD measured faster than P = 9 at 2 and P = 4 at 4.
+template <int L, typename R> struct DegridTune { static constexpr int P = L == 32 ? 4 : L == 64 ? 8 : 6, W = 1; };
+template <> struct DegridTune<96, float> { static constexpr int P = 6, W = 3; };
 
 template <typename R> struct C2;
 template <> struct C2<float> { using T = float2; };
@@ -244,6 +238,7 @@ void grid_dft(const Group g) {
     Pixel px[kPix];
 #pragma unroll
     for (int p = 0; p < kPix; ++p) px[p] = pixel_at<L>(blockIdx.x * kChunk + p * kThreads + lane, a.lstep);
+
     // Stage the sub-table (rows of nc visibilities, coalesced) in LDS; every lane then
     // reads each visibility by a broadcast LDS load into vector registers, so the
     // accumulation FMAs take only VGPR operands and can dual-issue.
@@ -264,45 +259,64 @@ void grid_dft(const Group g) {
       const_view<double> uvw = as_const(a.uvw + 3 * (s.uvw0 + t));
       const double um = uvw[0], vm = uvw[1], wm = uvw[2];
       const V4* vrow = vlds + 2 * t * s.nc;
-      // Phasors along the channels of the row: ph_{j+1} = ph_j * step, kept in two
-      // ping-pong registers (pa for even offsets from the seed, pb for odd ones).
-      V2 st[kPix];
+      V2 st[kPix];  // per-channel step exp(2 pi i dfc (um l + vm m + wm n1))
       {
         const double su = um * s.dfc, sv = vm * s.dfc, sw = wm * s.dfc;
 #pragma unroll
         for (int p = 0; p < kPix; ++p) st[p] = phasor(su * px[p].l + sv * px[p].m + sw * px[p].n1, R());
       }
       for (int j0 = 0; j0 < s.nc; j0 += s.R) {
-        const double fc = as_const(a.fc)[s.c0 + j0];
-        const double cu = um * fc - u0, cv = vm * fc - v0, cw = wm * fc - s.w0;
-        V2 pa[kPix], pb[kPix];
-#pragma unroll
-        for (int p = 0; p < kPix; ++p) pa[p] = phasor(cu * px[p].l + cv * px[p].m + cw * px[p].n1, R());
         const int jn = min(s.nc, j0 + s.R);
-        auto mac = [&](int j, const V2 (&ph)[kPix]) {
+        // Channels j0..jn-1 of the row contribute ph_{j0} * H with
+        // H = sum_k V_{j0+k} st^k, evaluated by Horner's rule from the last channel
+        // back (h <- h st + V_j: 4 FMA per polarisation, no phasor update), in two
+        // ping-pong register sets; ph_{j0} is the FP64-seeded phasor of the block.
+        V2 ha[kPix][4];
+        {
+          const V4 va = vrow[2 * (jn - 1)], vb = vrow[2 * (jn - 1) + 1];
+          const R vv[8] = {va.x, va.y, va.z, va.w, vb.x, vb.y, vb.z, vb.w};
+#pragma unroll
+          for (int p = 0; p < kPix; ++p)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) ha[p][q] = V2{vv[2 * q], vv[2 * q + 1]};
+        }
+        auto step = [&](int j, V2 (&h)[kPix][4]) {
           const V4 va = vrow[2 * j], vb = vrow[2 * j + 1];
           const R vv[8] = {va.x, va.y, va.z, va.w, vb.x, vb.y, vb.z, vb.w};
 #pragma unroll
           for (int p = 0; p < kPix; ++p) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-              acc[p][2 * q] = fma(vv[2 * q], ph[p].x, acc[p][2 * q]);
-              acc[p][2 * q] = fma(-vv[2 * q + 1], ph[p].y, acc[p][2 * q]);
-              acc[p][2 * q + 1] = fma(vv[2 * q], ph[p].y, acc[p][2 * q + 1]);
-              acc[p][2 * q + 1] = fma(vv[2 * q + 1], ph[p].x, acc[p][2 * q + 1]);
+              R re = fma(h[p][q].x, st[p].x, vv[2 * q]);
+              re = fma(-h[p][q].y, st[p].y, re);
+              R im = fma(h[p][q].x, st[p].y, vv[2 * q + 1]);
+              im = fma(h[p][q].y, st[p].x, im);
+              h[p][q] = V2{re, im};
             }
           }
         };
-        int j = j0;
-        for (; j + 1 < jn; j += 2) {
-          mac(j, pa);
+        auto finish = [&](const V2 (&h)[kPix][4]) {
+          const double fc = as_const(a.fc)[s.c0 + j0];
+          const double cu = um * fc - u0, cv = vm * fc - v0, cw = wm * fc - s.w0;
 #pragma unroll
-          for (int p = 0; p < kPix; ++p) pb[p] = cmul<R>(pa[p], st[p]);
-          mac(j + 1, pb);
+          for (int p = 0; p < kPix; ++p) {
+            const V2 ph = phasor(cu * px[p].l + cv * px[p].m + cw * px[p].n1, R());
 #pragma unroll
-          for (int p = 0; p < kPix; ++p) pa[p] = cmul<R>(pb[p], st[p]);
+            for (int q = 0; q < 4; ++q) {
+              acc[p][2 * q] = fma(h[p][q].x, ph.x, acc[p][2 * q]);
+              acc[p][2 * q] = fma(-h[p][q].y, ph.y, acc[p][2 * q]);
+              acc[p][2 * q + 1] = fma(h[p][q].x, ph.y, acc[p][2 * q + 1]);
+              acc[p][2 * q + 1] = fma(h[p][q].y, ph.x, acc[p][2 * q + 1]);
+            }
+          }
+        };
+        int j = jn - 2;
+        for (; j > j0; j -= 2) {
+          step(j, ha);
+          step(j - 1, ha);
         }
-        if (j < jn) mac(j, pa);
+        if (j == j0) step(j, ha);
+        finish(ha);
       }
     }
 
@@ -595,12 +609,9 @@ __device__ __forceinline__ R transpose_reduce16(R (&a)[16], int ln) {
 
 template <int L, typename R>
 __global__ __launch_bounds__(kThreads)
-#if DEGRID_WAVES > 0
-__attribute__((amdgpu_waves_per_eu(DEGRID_WAVES, DEGRID_WAVES)))
-#endif
-void degrid_dft(const Group g) {
+__attribute__((amdgpu_waves_per_eu(DegridTune<L, R>::W))) void degrid_dft(const Group g) {
   using V2 = typename C2<R>::T;
-  constexpr int P = DegridPix<L>::P, CH = kThreads * P;
+  constexpr int P = DegridTune<L, R>::P, CH = kThreads * P;
   static_assert((L * L) % CH == 0, "pixel chunks must tile the subgrid");
   extern __shared__ unsigned char smem_raw[];
   R* accs = reinterpret_cast<R*>(smem_raw);
@@ -651,7 +662,9 @@ void degrid_dft(const Group g) {
     for (int t = 0; t < s.nt; ++t) {
       const_view<double> uvw = as_const(a.uvw + 3 * (s.uvw0 + t));
       const double um = uvw[0], vm = uvw[1], wm = uvw[2];
-      V2 st[P], ph[P];
+      // Phasors along the channels: ph_{j+1} = ph_j * step, in two ping-pong
+      // register sets (pa for even channel offsets inside a group, pb for odd).
+      V2 st[P], pa[P], pb[P];
       {
         const double su = um * s.dfc, sv = vm * s.dfc, sw = wm * s.dfc;
 #pragma unroll
@@ -666,6 +679,8 @@ void degrid_dft(const Group g) {
 #pragma unroll
         for (int v = 0; v < kVisGroup; ++v) {
           const int j = g0 + v;
+          V2 (&cur)[P] = (v & 1) ? pb : pa;
+          V2 (&nxt)[P] = (v & 1) ? pa : pb;
 #pragma unroll
           for (int i = 0; i < 8; ++i) part[8 * v + i] = 0;
           if (j < s.nc) {
@@ -676,7 +691,7 @@ void degrid_dft(const Group g) {
 #pragma unroll
               for (int p = 0; p < P; ++p) {
                 const double l = (pix[p] % L - L / 2) * a.lstep, m = (pix[p] / L - L / 2) * a.lstep;
-                ph[p] = phasor(-(cu * l + cv * m + cw * n1[p]), R());
+                cur[p] = phasor(-(cu * l + cv * m + cw * n1[p]), R());
               }
             }
             ++since_seed;
@@ -685,14 +700,14 @@ void degrid_dft(const Group g) {
 #pragma unroll
               for (int q = 0; q < 4; ++q) {
                 R re = part[8 * v + 2 * q], im = part[8 * v + 2 * q + 1];
-                re = fma(sp[p][q].x, ph[p].x, re);
-                re = fma(-sp[p][q].y, ph[p].y, re);
-                im = fma(sp[p][q].x, ph[p].y, im);
-                im = fma(sp[p][q].y, ph[p].x, im);
+                re = fma(sp[p][q].x, cur[p].x, re);
+                re = fma(-sp[p][q].y, cur[p].y, re);
+                im = fma(sp[p][q].x, cur[p].y, im);
+                im = fma(sp[p][q].y, cur[p].x, im);
                 part[8 * v + 2 * q] = re;
                 part[8 * v + 2 * q + 1] = im;
               }
-              ph[p] = cmul<R>(ph[p], st[p]);
+              nxt[p] = cmul<R>(cur[p], st[p]);
             }
           }
         }
