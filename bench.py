@@ -66,7 +66,11 @@ def parse():
     ap.add_argument("--serve", action="store_true",
                     help="served mixed workload instead of the MWA-like job (separate JSON line)")
     ap.add_argument("--jobs", type=int, default=300)
-    ap.add_argument("--rho", type=float, nargs="+", default=[0.8, 1.2])
+    ap.add_argument("--rho", type=float, nargs="+", default=[0.8, 1.2, 2.0])
+    ap.add_argument("--rounds-in-flight", type=int, default=2)
+    ap.add_argument("--range-subgrids", type=int, default=4096)
+    ap.add_argument("--prepare-workers", type=int, default=4)
+    ap.add_argument("--max-active", type=int, default=32)
     ap.add_argument("--precision", action="store_true",
                     help="precision study: FP32 path (reseed interval swept) against the FP64 path "
                          "on the MWA-like workload, over screen rms and w-range (JSON line per case)")
@@ -171,19 +175,33 @@ def serve_bench(args):
         return np.array(lat), np.array(service), time.perf_counter() - t0
 
     def run_served(arrivals):
-        srv = Server(GpuBackend(workspace_bytes=1 << 30), range_subgrids=4096, prepare_workers=4)
+        srv = Server(GpuBackend(workspace_bytes=1 << 30), range_subgrids=args.range_subgrids,
+                     rounds_in_flight=args.rounds_in_flight, prepare_workers=args.prepare_workers,
+                     max_active=args.max_active)
         futs = []
+
+        def consume(f):
+            # the client takes its result and releases the device output, as the
+            # sequential client does after each job
+            f.result().output = None   # the job's work is complete when its future resolves
+
         with srv:
             t0 = time.perf_counter()
             for i, (d, arr) in enumerate(zip(mix, arrivals)):
                 now = time.perf_counter() - t0
                 if now < arr:
                     time.sleep(arr - now)
-                futs.append(srv.submit(make_job(d, i)))
+                f = srv.submit(make_job(d, i))
+                f.add_done_callback(consume)
+                futs.append(f)
             res = [f.result() for f in futs]
         lat = np.array([r.latency for r in res])
         span = max(r.finished for r in res) - min(r.arrival for r in res)
-        return lat, span, srv.stats()
+        stats = srv.stats()
+        del res, futs, srv
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()   # the next run starts from the same free memory
+        return lat, span, stats
 
     total = sum(n_vis(d) for d in mix)
     run_sequential([0.0] * 6)   # warm-up: kernels of each subgrid size, allocator
@@ -191,6 +209,8 @@ def serve_bench(args):
     es = float(service.mean())
     out = {"metric": "served mixed grid/degrid jobs: Mvis/s and p50/p99 job latency",
            "jobs": len(mix), "total_vis": int(total), "mean_sequential_service_ms": round(es * 1e3, 3),
+           "server": {"rounds_in_flight": args.rounds_in_flight, "range_subgrids": args.range_subgrids,
+                      "prepare_workers": args.prepare_workers, "max_active": args.max_active},
            "sequential_back_to_back": {"mvis_s": round(total / span0 / 1e6, 3)}, "loads": []}
     rng = np.random.default_rng(6)
     for rho in args.rho:
@@ -203,7 +223,9 @@ def serve_bench(args):
             "served": {"p50_ms": round(float(np.percentile(ls, 50)) * 1e3, 3),
                        "p99_ms": round(float(np.percentile(ls, 99)) * 1e3, 3),
                        "mvis_s": round(total / span_s / 1e6, 3), "rounds": st["rounds"],
-                       "peak_admitted_bytes": st["peak_bytes"]},
+                       "ranges_per_round": round(st["ranges_per_round"], 2),
+                       "loop_wait_s": round(st["wait_s"], 3), "prepare_s": round(st["prepare_s"], 3),
+                       "makespan_s": round(span_s, 3), "peak_admitted_bytes": st["peak_bytes"]},
             "sequential": {"p50_ms": round(float(np.percentile(lq, 50)) * 1e3, 3),
                            "p99_ms": round(float(np.percentile(lq, 99)) * 1e3, 3),
                            "mvis_s": round(total / span_q / 1e6, 3)}})

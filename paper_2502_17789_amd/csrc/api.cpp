@@ -6,6 +6,8 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -25,6 +27,28 @@ aidg_status fail(aidg_status st, const std::string& msg) {
 
 aidg_status hip_fail(hipError_t e, const char* what) {
   return fail(AIDG_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// One library stream per device on which plan memory is returned to the device's
+// stream-ordered pool (null if it cannot be created: memory is then freed
+// synchronously).  Default priority, non-blocking.
+hipStream_t release_stream(int device) {
+  static std::mutex mu;
+  static std::map<int, hipStream_t> streams;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = streams.find(device);
+  if (it != streams.end()) return it->second;
+  int cur = 0;
+  hipStream_t s = nullptr;
+  if (hipGetDevice(&cur) == hipSuccess && (cur == device || hipSetDevice(device) == hipSuccess)) {
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+      (void)hipGetLastError();
+      s = nullptr;
+    }
+    if (cur != device) (void)hipSetDevice(cur);
+  }
+  streams[device] = s;
+  return s;
 }
 
 }  // namespace
@@ -85,10 +109,29 @@ struct aidg_plan {
     return a;
   }
 
+  // Device memory comes from the device's stream-ordered pool (hipMallocAsync on
+  // the creation stream) where the device supports it.  It goes back on a library
+  // stream after the plan's last recorded work, so destroying a plan never
+  // synchronises the device: a serving loop retires plans while other jobs run.
+  bool async_mem = false;
+
   void release() {
     void* ptrs[] = {d_sg, d_uvw, d_fc, d_aterms, d_taper, d_tw, d_scratch, d_excl, d_grp, d_args};
-    for (void* p : ptrs)
-      if (p) (void)hipFree(p);
+    hipStream_t fs = async_mem ? release_stream(device) : nullptr;
+    int cur = device;
+    if (fs) {
+      (void)hipGetDevice(&cur);
+      if (cur != device) (void)hipSetDevice(device);
+      if (last) (void)hipStreamWaitEvent(fs, last, 0);
+    }
+    for (void* p : ptrs) {
+      if (!p) continue;
+      if (!fs)
+        (void)hipFree(p);
+      else if (hipFreeAsync(p, fs) != hipSuccess)
+        (void)hipGetLastError();
+    }
+    if (fs && cur != device) (void)hipSetDevice(cur);
     if (last) (void)hipEventDestroy(last);
     for (hipEvent_t e : pool) (void)hipEventDestroy(e);
     pool.clear();
@@ -170,16 +213,17 @@ aidg_status run(aidg_plan* p, KernelClass k, int64_t b0, int64_t n, const void* 
 }
 
 template <typename T>
-aidg_status dalloc(T** p, size_t bytes, aidg_plan* plan, const char* what) {
+aidg_status dalloc(T** p, size_t bytes, aidg_plan* plan, const char* what, hipStream_t stream) {
   void* q = nullptr;
-  const hipError_t e = hipMalloc(&q, std::max<size_t>(bytes, 256));
+  const size_t n = std::max<size_t>(bytes, 256);
+  const hipError_t e = plan->async_mem ? hipMallocAsync(&q, n, stream) : hipMalloc(&q, n);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return fail(AIDG_E_NOMEM, std::string("device allocation of ") + what + " failed: " +
                                   hipGetErrorString(e));
   }
   *p = reinterpret_cast<T*>(q);
-  plan->device_bytes += std::max<size_t>(bytes, 256);
+  plan->device_bytes += n;
   return AIDG_OK;
 }
 
@@ -406,18 +450,28 @@ aidg_status aidg_plan_create(const aidg_geometry* geo, int32_t n_stations, int32
       delete plan;
       return hip_fail(e, "hipGetDevice");
     }
-    if ((st = dalloc(&plan->d_sg, dev.size() * sizeof(SubgridDev), plan, "subgrid table")) ||
-        (st = dalloc(&plan->d_uvw, (size_t)n_baselines * n_times * 3 * sizeof(double), plan, "uvw")) ||
-        (st = dalloc(&plan->d_fc, fc.size() * sizeof(double), plan, "frequencies")) ||
-        (st = dalloc(&plan->d_aterms, plan->aterm_bytes, plan, "A-terms")) ||
-        (st = dalloc(&plan->d_taper, (size_t)L * L * (f32 ? 4 : 8), plan, "taper")) ||
-        (st = dalloc(&plan->d_tw, (size_t)L * (f32 ? 8 : 16), plan, "twiddles")) ||
-        (st = dalloc(&plan->d_excl, pr.excluded.size() * sizeof(int64_t), plan, "excluded list")) ||
-        (st = dalloc(&plan->d_grp, plan->grp_begin.size() * sizeof(int64_t), plan, "group index")) ||
-        (st = dalloc(&plan->d_scratch, plan->scratch_bytes, plan, "subgrid workspace")) ||
-        (st = dalloc(&plan->d_args, sizeof(KernelArgs), plan, "launch parameters"))) {
+    int pools = 0;
+    plan->async_mem = hipDeviceGetAttribute(&pools, hipDeviceAttributeMemoryPoolsSupported, plan->device) ==
+                          hipSuccess && pools != 0 && release_stream(plan->device) != nullptr;
+    (void)hipGetLastError();
+    // on failure after the first allocation: let the creation stream finish, then free
+    auto abandon = [&]() {
+      (void)hipStreamSynchronize(stream);
+      (void)hipGetLastError();
       plan->release();
       delete plan;
+    };
+    if ((st = dalloc(&plan->d_sg, dev.size() * sizeof(SubgridDev), plan, "subgrid table", stream)) ||
+        (st = dalloc(&plan->d_uvw, (size_t)n_baselines * n_times * 3 * sizeof(double), plan, "uvw", stream)) ||
+        (st = dalloc(&plan->d_fc, fc.size() * sizeof(double), plan, "frequencies", stream)) ||
+        (st = dalloc(&plan->d_aterms, plan->aterm_bytes, plan, "A-terms", stream)) ||
+        (st = dalloc(&plan->d_taper, (size_t)L * L * (f32 ? 4 : 8), plan, "taper", stream)) ||
+        (st = dalloc(&plan->d_tw, (size_t)L * (f32 ? 8 : 16), plan, "twiddles", stream)) ||
+        (st = dalloc(&plan->d_excl, pr.excluded.size() * sizeof(int64_t), plan, "excluded list", stream)) ||
+        (st = dalloc(&plan->d_grp, plan->grp_begin.size() * sizeof(int64_t), plan, "group index", stream)) ||
+        (st = dalloc(&plan->d_scratch, plan->scratch_bytes, plan, "subgrid workspace", stream)) ||
+        (st = dalloc(&plan->d_args, sizeof(KernelArgs), plan, "launch parameters", stream))) {
+      abandon();
       return st;
     }
     const KernelArgs host_args = plan->args();
@@ -443,22 +497,21 @@ aidg_status aidg_plan_create(const aidg_geometry* geo, int32_t n_stations, int32
       if (!c.n) continue;
       e = hipMemcpyAsync(c.dst, c.src, c.n, c.kind, stream);
       if (e != hipSuccess) {
-        plan->release();
-        delete plan;
+        abandon();
         return hip_fail(e, "hipMemcpyAsync (plan upload)");
       }
     }
     if ((e = hipEventCreateWithFlags(&plan->last, hipEventDisableTiming)) != hipSuccess ||
         (e = hipEventRecord(plan->last, stream)) != hipSuccess ||
         (e = hipStreamSynchronize(stream)) != hipSuccess) {
-      plan->release();
-      delete plan;
+      abandon();
       return hip_fail(e, "plan upload");
     }
     *out = plan;
     return AIDG_OK;
   } catch (const std::bad_alloc&) {
     if (plan) {
+      if (plan->async_mem && plan->d_sg) (void)hipDeviceSynchronize();  // allocations in flight
       plan->release();
       delete plan;
     }

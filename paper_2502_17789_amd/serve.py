@@ -186,7 +186,8 @@ class Server:
     """Continuous-batching request loop (see module docstring)."""
 
     def __init__(self, backend=None, hbm_budget: int | None = None, range_subgrids: int = 2048,
-                 rounds_in_flight: int = 2, clock=time.perf_counter, prepare_workers: int = 0):
+                 rounds_in_flight: int = 2, clock=time.perf_counter, prepare_workers: int = 0,
+                 max_active: int = 32):
         self.backend = backend if backend is not None else GpuBackend()
         if hbm_budget is None:
             import torch
@@ -195,6 +196,9 @@ class Server:
         self.hbm_budget = int(hbm_budget)
         self.range_subgrids = int(range_subgrids)
         self.rounds_in_flight = int(rounds_in_flight)
+        # Jobs admitted (preparing or active) at once.  More than a few rounds' worth
+        # only adds device allocations and preparation contention, not throughput.
+        self.max_active = max(1, int(max_active))
         self.clock = clock
         self._queue: collections.deque[_Active] = collections.deque()
         self._active: list[_Active] = []
@@ -209,6 +213,9 @@ class Server:
         self.completed: list[JobResult] = []
         self.peak_in_use = 0
         self.rounds = 0
+        self.ranges = 0                 # subgrid ranges launched, over all rounds
+        self.t_wait = 0.0               # loop time blocked on the oldest round (device-bound)
+        self.t_prepare = 0.0            # time inside backend.prepare, summed over jobs
 
     # ------------------------------------------------------------ client side
     def submit(self, job: Job) -> concurrent.futures.Future:
@@ -261,7 +268,9 @@ class Server:
                     return
             if not self.step():
                 if self._rounds:
+                    t0 = self.clock()
                     self.backend.wait(self._rounds[0][0])
+                    self.t_wait += self.clock() - t0
                 elif self._preparing:
                     concurrent.futures.wait([f for _, f in self._preparing], timeout=0.05,
                                             return_when=concurrent.futures.FIRST_COMPLETED)
@@ -290,8 +299,9 @@ class Server:
                 st.future.set_exception(MemoryError(
                     f"job needs {fp} device bytes, more than the server's budget {self.hbm_budget}"))
                 continue
-            if self._in_use + fp > self.hbm_budget:
-                return admitted     # first-in first-out: wait for memory to free up
+            if (self._in_use + fp > self.hbm_budget or
+                    len(self._active) + len(self._preparing) >= self.max_active):
+                return admitted     # first-in first-out: wait for memory or a slot to free up
             with self._cv:
                 self._queue.popleft()
             st.footprint = fp
@@ -299,13 +309,20 @@ class Server:
             self.peak_in_use = max(self.peak_in_use, self._in_use)
             admitted = True
             if self._pool is not None:
-                self._preparing.append((st, self._pool.submit(self.backend.prepare, st.job)))
+                self._preparing.append((st, self._pool.submit(self._timed_prepare, st.job)))
                 continue
             try:
-                self._activate(st, self.backend.prepare(st.job))
+                self._activate(st, self._timed_prepare(st.job))
             except Exception as e:
                 self._in_use -= fp
                 st.future.set_exception(e)
+
+    def _timed_prepare(self, job):
+        t0 = self.clock()
+        try:
+            return self.backend.prepare(job)
+        finally:
+            self.t_prepare += self.clock() - t0   # float add under the GIL: no lost updates
 
     def _activate(self, st, handle):
         st.handle = handle
@@ -343,6 +360,7 @@ class Server:
         if not ranges:
             return False
         token = self.backend.execute(ranges)
+        self.ranges += len(ranges)
         retiring = []
         for st in owners:
             if st.next_sg >= st.n_sg:
@@ -379,4 +397,5 @@ class Server:
         return {"jobs": int(lat.size), "p50_ms": float(np.percentile(lat, 50) * 1e3),
                 "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
                 "makespan_s": float(t1 - t0), "mvis_per_s": float(nvis / (t1 - t0) / 1e6),
-                "rounds": self.rounds, "peak_bytes": int(self.peak_in_use)}
+                "rounds": self.rounds, "ranges_per_round": self.ranges / max(self.rounds, 1),
+                "wait_s": self.t_wait, "prepare_s": self.t_prepare, "peak_bytes": int(self.peak_in_use)}

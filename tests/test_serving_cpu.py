@@ -199,3 +199,25 @@ def test_parallel_prepare_matches():
         ref = oracle.grid(wl, job.data, table) if job.direction == "grid" else oracle.degrid(wl, job.data, table)
         assert np.abs(f.result().output - ref).max() <= 1e-12 * np.abs(ref).max()
     srv.stop()
+
+
+def test_active_jobs_bounded():
+    """At most max_active jobs are admitted at once, whatever the memory budget;
+    the rest wait in arrival order and every job still completes."""
+    clock = FakeClock()
+    be = OracleBackend(clock)
+    srv = Server(be, hbm_budget=1 << 40, range_subgrids=2, clock=clock, max_active=2)
+    jobs = [make_job(60 + i, "grid" if i % 2 else "degrid", n_c=3) for i in range(5)]
+    futs = [srv.submit(j) for j, _ in jobs]
+    peak = 0
+    for _ in range(10000):
+        if srv.idle():
+            break
+        progressed = srv.step()
+        peak = max(peak, len(srv._active) + len(srv._preparing))
+        if not progressed:
+            be.wait(srv._rounds[0][0])
+    assert srv.idle() and peak == 2
+    res = [f.result() for f in futs]
+    adm = [r.admitted for r in res]
+    assert adm == sorted(adm) and len(set(adm)) >= 3
