@@ -78,6 +78,9 @@ def parse():
     ap.add_argument("--wmax", type=float, nargs="+", default=[0.0, 250.0, 500.0],
                     help="largest |w| in wavelengths (0 = at transit)")
     ap.add_argument("--reseed", type=int, nargs="+", default=[8, 16, 32, 96])
+    ap.add_argument("--kernel-sweep", action="store_true",
+                    help="kernel-only grid/degrid throughput at subgrid sizes 32/64/96 (K = L/4), "
+                         "FP32 and FP64, on the MWA-like observation (JSON line per case)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device-to-device 3 times (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -313,6 +316,61 @@ def precision_study(args):
             torch.cuda.empty_cache()
 
 
+def kernel_sweep(args):
+    """Throughput against subgrid size, kernels only (HIP events around every launch):
+    the MWA-like observation partitioned at L = 32, 64, 96 with K = L/4, in FP32
+    and FP64.  grid = grid_dft + fft_add, degrid = split_ifft + degrid_dft."""
+    import torch
+
+    import paper_2502_17789_amd as aidg
+    import synth
+
+    torch.cuda.set_device(0)
+    wl = synth.config_mwa(seed=2)
+    gen = torch.Generator(device="cuda")
+    for prec in (aidg.FP32, aidg.FP64):
+        cdt = torch.complex64 if prec == aidg.FP32 else torch.complex128
+        for L in (32, 64, 96):
+            A = synth.device_phase_screen_aterms(wl.n_stations, L, 2.0, seed=7)
+            n_int = (wl.n_times + wl.aterm_interval - 1) // wl.aterm_interval
+            A = A.expand(n_int, -1, -1, -1, -1).contiguous().to(cdt)
+            geo = aidg.Geometry(wl.grid_size, L, L // 4, wl.pixel_scale, aterm_interval=wl.aterm_interval,
+                                precision=prec)
+            with aidg.Plan(geo, wl.n_stations, wl.baselines, wl.uvw, wl.freqs, A) as plan:
+                del A
+                gen.manual_seed(2)
+                V = torch.randn(plan.vis_shape(), dtype=cdt, device="cuda", generator=gen)
+                G = torch.zeros(plan.grid_shape(), dtype=cdt, device="cuda")
+                Vo = torch.empty_like(V)
+                plan.grid(V, G)
+                plan.degrid(G, Vo)
+                torch.cuda.synchronize()
+                plan.set_profiling(True)
+                reps = 2
+                for _ in range(reps):
+                    plan.grid(V, G)
+                    plan.degrid(G, Vo)
+                torch.cuda.synchronize()
+                kt = plan.kernel_times()
+                info = plan.info
+                del V, G, Vo
+            ms = {k: v["ms"] / reps for k, v in kt.items()}
+            n = wl.n_vis
+            t_grid = ms["grid_dft"] + ms["fft_add"]
+            t_degrid = ms["split_ifft"] + ms["degrid_dft"]
+            print(json.dumps({
+                "kernel_sweep": {"subgrid_size": L, "kernel_support": L // 4,
+                                 "precision": "fp32" if prec == aidg.FP32 else "fp64",
+                                 "n_vis": n, "n_subgrids": info["n_subgrids"], "n_groups": info["n_groups"],
+                                 "mean_vis_per_subgrid": round(n / max(info["n_subgrids"], 1), 1)},
+                "grid_mvis_s": round(n / (t_grid * 1e-3) / 1e6, 1),
+                "degrid_mvis_s": round(n / (t_degrid * 1e-3) / 1e6, 1),
+                "ms": {k: round(v, 3) for k, v in ms.items() if v > 0},
+                "dft_tflops": {k: round(kt[k]["vis_pixels"] * FLOP_PER_VP / (ms[k] * reps * 1e-3) / 1e12, 2)
+                               for k in ("grid_dft", "degrid_dft")}}), flush=True)
+            torch.cuda.empty_cache()
+
+
 def dataclasses_replace(obj, **kw):
     import dataclasses
     return dataclasses.replace(obj, **kw)
@@ -332,6 +390,9 @@ def main():
         return
     if args.precision:
         precision_study(args)
+        return
+    if args.kernel_sweep:
+        kernel_sweep(args)
         return
     if args.copy_probe:
         import torch
