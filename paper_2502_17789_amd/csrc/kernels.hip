@@ -89,10 +89,12 @@ __device__ __forceinline__ float2 phasor(double theta, float) {
   c = fmaf(t2, c, 64.93939402266828f);
   c = fmaf(t2, c, -19.739208802178716f);
   c = fmaf(t2, c, 1.0f);
-  // rotate by qi quarter turns
-  const bool odd = qi & 1, neg_c = (qi + 1) & 2, neg_s = qi & 2;
+  // rotate by qi quarter turns: swap for odd qi, then flip the sign bits (cos is
+  // negative for qi = 1, 2 mod 4 and sin for qi = 2, 3: bit 1 of qi + 1 and of qi)
+  const bool odd = qi & 1;
   const float cc = odd ? s : c, ss = odd ? c : s;
-  return {neg_c ? -cc : cc, neg_s ? -ss : ss};
+  const unsigned sign_c = ((unsigned)(qi + 1) << 30) & 0x80000000u, sign_s = ((unsigned)qi << 30) & 0x80000000u;
+  return {__uint_as_float(__float_as_uint(cc) ^ sign_c), __uint_as_float(__float_as_uint(ss) ^ sign_s)};
 }
 
 // FP64 variant: reduction to [-1/2, 1/2] and the device library's sincospi.
@@ -631,28 +633,35 @@ __attribute__((amdgpu_waves_per_eu(DegridTune<L, R>::W))) void degrid_dft(const 
   const double u0 = (s.U0 - a.N / 2) * a.du, v0 = (s.V0 - a.N / 2) * a.du;
 
   for (int chunk = 0; chunk < (L * L) / CH; ++chunk) {
-    int pix[P];
+    // Pixel offsets from the centre, (x - L/2) in the low and (y - L/2) in the high
+    // half-word: (l, m) are rebuilt from them at every phasor seed without a division.
+    int xy[P];
     double n1[P];
     V2 sp[P][4];
+    auto lm = [&](int p) {
+      const int dx = (int)(short)(xy[p] & 0xffff), dy = xy[p] >> 16;
+      return double2{dx * a.lstep, dy * a.lstep};
+    };
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-      pix[p] = chunk * CH + p * kThreads + threadIdx.x;
-      const double l = (pix[p] % L - L / 2) * a.lstep, m = (pix[p] / L - L / 2) * a.lstep;
+      const int pix = chunk * CH + p * kThreads + threadIdx.x;
+      xy[p] = ((pix % L - L / 2) & 0xffff) | ((pix / L - L / 2) * 65536);
+      const double l = lm(p).x, m = lm(p).y;
       const double r2 = l * l + m * m;
       n1[p] = -r2 / (1.0 + sqrt(1.0 - r2));
       // prologue: S' = T (-1)^(x+y) A_p S A_q^H
-      const V2* Ap = At + ((int64_t)s.ap * L * L + pix[p]) * 4;
-      const V2* Aq = At + ((int64_t)s.aq * L * L + pix[p]) * 4;
+      const V2* Ap = At + ((int64_t)s.ap * L * L + pix) * 4;
+      const V2* Aq = At + ((int64_t)s.aq * L * L + pix) * 4;
       const V2 a0 = Ap[0], a1 = Ap[1], a2 = Ap[2], a3 = Ap[3];
       V2 b0 = Aq[0], b1 = Aq[1], b2 = Aq[2], b3 = Aq[3];
       b0.y = -b0.y; b1.y = -b1.y; b2.y = -b2.y; b3.y = -b3.y;  // conj
-      const V2 s0 = img[0 * L * L + pix[p]], s1 = img[1 * L * L + pix[p]];
-      const V2 s2 = img[2 * L * L + pix[p]], s3 = img[3 * L * L + pix[p]];
+      const V2 s0 = img[0 * L * L + pix], s1 = img[1 * L * L + pix];
+      const V2 s2 = img[2 * L * L + pix], s3 = img[3 * L * L + pix];
       const V2 t0 = cmul<R>(a0, s0) + cmul<R>(a1, s2);
       const V2 t1 = cmul<R>(a0, s1) + cmul<R>(a1, s3);
       const V2 t2 = cmul<R>(a2, s0) + cmul<R>(a3, s2);
       const V2 t3 = cmul<R>(a2, s1) + cmul<R>(a3, s3);
-      const R w = taper[pix[p]];
+      const R w = taper[pix];
       // A_q^H = [[conj b0, conj b2], [conj b1, conj b3]]
       sp[p][0] = (cmul<R>(t0, b0) + cmul<R>(t1, b1)) * w;
       sp[p][1] = (cmul<R>(t0, b2) + cmul<R>(t1, b3)) * w;
@@ -669,7 +678,7 @@ __attribute__((amdgpu_waves_per_eu(DegridTune<L, R>::W))) void degrid_dft(const 
         const double su = um * s.dfc, sv = vm * s.dfc, sw = wm * s.dfc;
 #pragma unroll
         for (int p = 0; p < P; ++p) {
-          const double l = (pix[p] % L - L / 2) * a.lstep, m = (pix[p] / L - L / 2) * a.lstep;
+          const double l = lm(p).x, m = lm(p).y;
           st[p] = phasor(-(su * l + sv * m + sw * n1[p]), R());
         }
       }
@@ -690,7 +699,7 @@ __attribute__((amdgpu_waves_per_eu(DegridTune<L, R>::W))) void degrid_dft(const 
               const double cu = um * fc - u0, cv = vm * fc - v0, cw = wm * fc - s.w0;
 #pragma unroll
               for (int p = 0; p < P; ++p) {
-                const double l = (pix[p] % L - L / 2) * a.lstep, m = (pix[p] / L - L / 2) * a.lstep;
+                const double l = lm(p).x, m = lm(p).y;
                 cur[p] = phasor(-(cu * l + cv * m + cw * n1[p]), R());
               }
             }
