@@ -37,6 +37,28 @@ namespace aidg {
 namespace {
 
 constexpr int kThreads = 256;
+// Workgroups are dispatched to the 8 XCDs (each with its own L2) round-robin by
+// linear workgroup index, so index b runs on XCD b % 8.
+constexpr int kXcds = 8;
+
+// Gridder work item of linear workgroup index b: (group slot, pixel chunk) such
+// that all chunks of a slot share one XCD (its visibilities are fetched into one
+// L2) while consecutive slots, longest first, spread over the XCDs.  The launch
+// has ceil(slots / 8) * 8 * chunks workgroups; indices past the last slot exit.
+template <int Chunks>
+__device__ __forceinline__ void grid_work(int64_t b, int64_t* slot, int* chunk) {
+  const int64_t k = b / kXcds;
+  *chunk = (int)(k % Chunks);
+  *slot = (k / Chunks) * kXcds + b % kXcds;
+}
+
+// Degridder subgrid slot of linear workgroup index b < n: within every full tile
+// of 64, XCD x takes the 8 consecutive slots 8x..8x+7 (subgrids of one
+// same-centre group then mostly share their image in one L2); a last partial
+// tile maps one to one.
+__device__ __forceinline__ int64_t degrid_slot(int64_t b, int64_t n) {
+  return b < (n & ~int64_t(63)) ? ((b & ~int64_t(63)) | ((b & 7) << 3) | ((b >> 3) & 7)) : b;
+}
 #ifndef GRID_PIX
 #define GRID_PIX 4
 #endif
@@ -216,7 +238,10 @@ void grid_dft(const Group g) {
   using V4 = typename C4<R>::T;
   extern __shared__ unsigned char smem_raw[];
   V4* vlds = reinterpret_cast<V4*>(smem_raw);  // one subgrid's visibilities, 8 values each
-  const int64_t local = blockIdx.y;
+  int64_t local;
+  int chunk;
+  grid_work<(L * L) / kChunk>(blockIdx.x, &local, &chunk);
+  if (local >= g.total_grp) return;  // padding of the last XCD round (whole workgroup)
   const GroupSlot gs = resolve_group(g, local);
   const KernelArgs& a = gs.a;
   const R* __restrict__ vis = reinterpret_cast<const R*>(gs.in);
@@ -239,7 +264,7 @@ void grid_dft(const Group g) {
     asm volatile("" : "+v"(lane));
     Pixel px[kPix];
 #pragma unroll
-    for (int p = 0; p < kPix; ++p) px[p] = pixel_at<L>(blockIdx.x * kChunk + p * kThreads + lane, a.lstep);
+    for (int p = 0; p < kPix; ++p) px[p] = pixel_at<L>(chunk * kChunk + p * kThreads + lane, a.lstep);
 
     // Stage the sub-table (rows of nc visibilities, coalesced) in LDS; every lane then
     // reads each visibility by a broadcast LDS load into vector registers, so the
@@ -617,7 +642,7 @@ __attribute__((amdgpu_waves_per_eu(DegridTune<L, R>::W))) void degrid_dft(const 
   static_assert((L * L) % CH == 0, "pixel chunks must tile the subgrid");
   extern __shared__ unsigned char smem_raw[];
   R* accs = reinterpret_cast<R*>(smem_raw);
-  const int64_t local = blockIdx.x;
+  const int64_t local = degrid_slot(blockIdx.x, g.total_sg);
   const Slot sl = resolve(g, local);
   const KernelArgs& a = sl.a;
   const SubgridDev& s = sl.s;
@@ -754,8 +779,8 @@ int launch_one(KernelClass k, const Group& g, hipStream_t st, int max_nv) {
   const unsigned n = (unsigned)(k == kDegridDft ? g.total_sg : g.total_grp);
   switch (k) {
     case kGridDft:
-      hipLaunchKernelGGL((grid_dft<L, R>), dim3((L * L) / kChunk, n), dim3(kThreads),
-                         (size_t)max_nv * 8 * sizeof(R), st, g);
+      hipLaunchKernelGGL((grid_dft<L, R>), dim3((n + kXcds - 1) / kXcds * kXcds * ((L * L) / kChunk)),
+                         dim3(kThreads), (size_t)max_nv * 8 * sizeof(R), st, g);
       break;
     case kFftAdd:
       hipLaunchKernelGGL((fft_add<L, R>), dim3(4, n), dim3(kThreads), 0, st, g);
