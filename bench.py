@@ -41,16 +41,28 @@ PEAK_FP32_SINGLE_ISSUE_TFLOPS = PEAK_FP32_TFLOPS / 2
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_mwa.json")
 
 
+def library_source_hash() -> str:
+    """SHA-256 over the library's sources (kernels, partitioner, plan and launches):
+    what decides the kernels and how the workload is cut into launches."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2502_17789_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".cpp", ".h")):
+            h.update(name.encode())
+            h.update(open(os.path.join(csrc, name), "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic(kernel: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE summary, or None once the kernel source has changed since."""
-    import hashlib
+    WRITE_SIZE summary, or None once the library source has changed since."""
     try:
         rec = json.load(open(TRAFFIC_FILE))
-        src = open(os.path.join(ROOT, "paper_2502_17789_amd", "csrc", "kernels.hip"), "rb").read()
+        digest = library_source_hash()
     except OSError:
         return None
-    if hashlib.sha256(src).hexdigest() != rec.get("kernels_hip_sha256"):
+    if digest != rec.get("library_sha256"):
         return None
     k = rec["kernels"].get(kernel)
     return None if k is None else round(k["bytes_per_launch"])
@@ -81,6 +93,9 @@ def parse():
     ap.add_argument("--kernel-sweep", action="store_true",
                     help="kernel-only grid/degrid throughput at subgrid sizes 32/64/96 (K = L/4), "
                          "FP32 and FP64, on the MWA-like observation (JSON line per case)")
+    ap.add_argument("--lattice-cases", type=lambda t: tuple(int(x) for x in t.split(":")), nargs="*",
+                    default=[], help="extra FP32 kernel-sweep cases L:lattice (centre lattice step)")
+    ap.add_argument("--lattice-only", action="store_true", help="kernel sweep: only the --lattice-cases")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device-to-device 3 times (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -328,14 +343,16 @@ def kernel_sweep(args):
     torch.cuda.set_device(0)
     wl = synth.config_mwa(seed=2)
     gen = torch.Generator(device="cuda")
-    for prec in (aidg.FP32, aidg.FP64):
+    cases = [] if args.lattice_only else [(prec, L, 0) for prec in (aidg.FP32, aidg.FP64) for L in (32, 64, 96)]
+    cases += [(aidg.FP32, L, lat) for L, lat in args.lattice_cases]
+    for prec, L, lattice in cases:
         cdt = torch.complex64 if prec == aidg.FP32 else torch.complex128
-        for L in (32, 64, 96):
+        if True:
             A = synth.device_phase_screen_aterms(wl.n_stations, L, 2.0, seed=7)
             n_int = (wl.n_times + wl.aterm_interval - 1) // wl.aterm_interval
             A = A.expand(n_int, -1, -1, -1, -1).contiguous().to(cdt)
             geo = aidg.Geometry(wl.grid_size, L, L // 4, wl.pixel_scale, aterm_interval=wl.aterm_interval,
-                                precision=prec)
+                                precision=prec, center_lattice=lattice)
             with aidg.Plan(geo, wl.n_stations, wl.baselines, wl.uvw, wl.freqs, A) as plan:
                 del A
                 gen.manual_seed(2)
@@ -359,7 +376,7 @@ def kernel_sweep(args):
             t_grid = ms["grid_dft"] + ms["fft_add"]
             t_degrid = ms["split_ifft"] + ms["degrid_dft"]
             print(json.dumps({
-                "kernel_sweep": {"subgrid_size": L, "kernel_support": L // 4,
+                "kernel_sweep": {"subgrid_size": L, "kernel_support": L // 4, "center_lattice": lattice or "auto",
                                  "precision": "fp32" if prec == aidg.FP32 else "fp64",
                                  "n_vis": n, "n_subgrids": info["n_subgrids"], "n_groups": info["n_groups"],
                                  "mean_vis_per_subgrid": round(n / max(info["n_subgrids"], 1), 1)},

@@ -95,7 +95,7 @@ typedef struct {
                               sub-tables are split in time */
   int32_t center_lattice;  /* the library's partitioner puts subgrid centres on cells
                               N/2 + k * center_lattice (Sec. 2.2: a centre snaps to a grid
-                              cell); 0 = automatic (largest power of two <= (L-K)/8), 1 = any cell.
+                              cell); 0 = automatic (largest power of two <= 2(L-K)/3), 1 = any cell.
                               Subgrids with the same centre and w-layer share one subgrid FFT
                               and one add to the grid (and one split + inverse FFT) */
   int32_t reserved;        /* 0 */
