@@ -42,15 +42,20 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_mwa.json")
 
 
 def library_source_hash() -> str:
-    """SHA-256 over the library's sources (kernels, partitioner, plan and launches):
-    what decides the kernels and how the workload is cut into launches."""
+    """SHA-256 over the library's sources (kernels, partitioner, plan and launches),
+    what decides the kernels and how the workload is cut into launches, with
+    comments and whitespace removed so that documentation edits keep it."""
     import hashlib
+    import re
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2502_17789_amd", "csrc")
     for name in sorted(os.listdir(csrc)):
         if name.endswith((".hip", ".cpp", ".h")):
+            text = open(os.path.join(csrc, name), encoding="utf-8").read()
+            text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+            text = re.sub(r"//[^\n]*", " ", text)
             h.update(name.encode())
-            h.update(open(os.path.join(csrc, name), "rb").read())
+            h.update(" ".join(text.split()).encode())
     return h.hexdigest()
 
 

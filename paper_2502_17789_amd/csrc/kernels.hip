@@ -1,27 +1,33 @@
 // HIP kernels for A-term image-domain gridding on gfx950 (CDNA4).
 //
-// Gridding of one batch of subgrids (Sec. 2.5 imaging, steps 2a-2c):
-//   grid_dft   one workgroup per (1024-pixel chunk, subgrid); each lane owns 4
-//              subgrid pixels and sums every visibility of the subgrid onto them
-//              (Eq. withw).  Visibilities and uvw rows are wave-uniform loads
-//              (scalar unit), so each visibility costs 16 FMA for the 2x2 complex
-//              accumulation plus 4 for the phasor step per pixel.  Phasors come
-//              from a per-channel recurrence: an FP64 phase origin per (row,
-//              pixel) reduced to a quarter turn, an accurate FP32 sin/cos, then
-//              ph <- ph * step, re-seeded from FP64 every R channels.  The
-//              epilogue applies T (-1)^(x+y) A_p^H S A_q (Sec. 3.3).
-//   fft_add    one workgroup per (polarisation, subgrid): Stockham FFT of the
-//              L x L plane in LDS (radix 4/2/3), then (-1)^(a+b) and an atomic
-//              add onto the subgrid's window of its w-layer (Eq. shiftback).
+// A plan orders its subgrids so that those with the same w-layer and centre form
+// consecutive groups; a grouped launch covers subgrid ranges of up to 16 plans,
+// with one scratch image slot per group.
+//
+// Gridding of a batch (Sec. 2.5 imaging, steps 2a-2c):
+//   grid_dft   one workgroup per (1024-pixel chunk, group); each lane owns 4
+//              subgrid pixels.  For every subgrid of the group the visibilities
+//              are staged in LDS and read by wave broadcast; per row and block of
+//              R channels, H = sum_k V_{j0+k} step^k is evaluated by Horner's rule
+//              (4 FMA per polarisation per visibility and pixel) and multiplied by
+//              the block's phasor, seeded from an FP64 phase origin reduced to a
+//              quarter turn and an FP32 polynomial sin/cos (Eq. withw).  The
+//              subgrid's T (-1)^(x+y) A_p^H S A_q (Sec. 3.3) is added into the
+//              group's image slot.
+//   fft_add    one workgroup per (polarisation, group): Stockham FFT of the L x L
+//              plane in LDS (radix 4/2/3), then (-1)^(a+b) and an atomic add onto
+//              the group's window of its w-layer (Eq. shiftback).
 // Degridding (prediction, step 3), the adjoint chain:
-//   split_ifft one workgroup per (polarisation, subgrid): copy the window times
-//              (-1)^(a+b) into LDS (splitter), inverse FFT, store the plane.
-//   degrid_dft one workgroup per subgrid; lanes own pixels and apply
-//              T (-1)^(x+y) A_p S A_q^H once; for each group of 4 channels every
-//              lane forms its 4 pixels' partial sums (32 floats), a wave-wide
-//              transpose-reduction (permlane32/permlane16 swaps, then DPP) leaves
-//              each lane with one reduced value, and waves combine through LDS
-//              atomics; the finished visibilities are written once (Eq. degridder).
+//   split_ifft one workgroup per (polarisation, group): copy the window times
+//              (-1)^(a+b) into LDS (splitter), inverse FFT, store the group image.
+//   degrid_dft one workgroup per subgrid; lanes own P pixels each and apply
+//              T (-1)^(x+y) A_p S A_q^H to the group image once per pixel chunk;
+//              phasors follow ph <- ph * step along the channels (re-seeded from
+//              FP64 every R), and for each group of 4 channels every lane forms its
+//              pixels' partial sums (32 floats); a wave-wide transpose-reduction
+//              (permlane32/permlane16 swaps, then DPP) leaves each lane pair with
+//              one reduced value, and waves combine through LDS atomics; the
+//              finished visibilities are written once (Eq. degridder).
 //
 // The centred DFT of Sec. 2.3 relates to a plain FFT by a checkerboard:
 //   sum_{x,y} s(x,y) e^{-2 pi i [(a-L/2)(x-L/2) + (b-L/2)(y-L/2)]/L}
@@ -60,15 +66,12 @@ __device__ __forceinline__ int64_t degrid_slot(int64_t b, int64_t n) {
   return b < (n & ~int64_t(63)) ? ((b & ~int64_t(63)) | ((b & 7) << 3) | ((b >> 3) & 7)) : b;
 }
 #ifndef GRID_PIX
-#define GRID_PIX 4
-#endif
-#ifndef GRID_WAVES
-#define GRID_WAVES 0
+#define GRID_PIX 4  // compile-time tile parameter; 4 measured best (2 within noise)
 #endif
 constexpr int kPix = GRID_PIX;              // pixels per lane in the gridder
 constexpr int kChunk = kThreads * kPix;     // pixels per workgroup pass
 #ifndef DEGRID_GROUP
-#define DEGRID_GROUP 4
+#define DEGRID_GROUP 4  // compile-time tile parameter; 4 measured faster than 2
 #endif
 constexpr int kVisGroup = DEGRID_GROUP;     // channels per degridder reduction (2 or 4)
 static_assert(kVisGroup == 2 || kVisGroup == 4, "even group: phasor ping-pong restarts in the first set");
@@ -229,11 +232,7 @@ __device__ __forceinline__ Slot resolve(const Group& g, int64_t slot) {
 // ------------------------------------------------------------------ gridder
 
 template <int L, typename R>
-__global__ __launch_bounds__(kThreads)
-#if GRID_WAVES > 0
-__attribute__((amdgpu_waves_per_eu(GRID_WAVES, GRID_WAVES)))
-#endif
-void grid_dft(const Group g) {
+__global__ __launch_bounds__(kThreads) void grid_dft(const Group g) {
   using V2 = typename C2<R>::T;
   using V4 = typename C4<R>::T;
   extern __shared__ unsigned char smem_raw[];
