@@ -99,7 +99,8 @@ typedef struct {
                               Subgrids with the same centre and w-layer share one subgrid FFT
                               and one add to the grid (and one split + inverse FFT) */
   int32_t reserved;        /* 0 */
-  int64_t workspace_bytes; /* subgrid stack budget on the device; 0 = 2 GiB */
+  int64_t workspace_bytes; /* device budget for the group images of one batch
+                              (4 L^2 complex each); 0 = 2 GiB */
 } aidg_geometry;
 
 /* One subgrid: the rectangular sub-table [t0, t0+nt) x [c0, c0+nc) of one
@@ -124,10 +125,11 @@ typedef struct {
   int32_t subgrid_size;    /* L */
   double w_step;           /* layer spacing used (0 for a single layer) */
   int64_t device_bytes;    /* everything the plan holds on the device */
-  int64_t workspace_bytes; /* subgrid stack */
+  int64_t workspace_bytes; /* group image stack of one batch */
   int64_t grid_bytes;      /* size of one grid for this plan, W * 4 * N * N * complex */
   int64_t vis_bytes;       /* size of one visibility array */
-  int64_t n_batches;       /* kernel batches per aidg_grid / aidg_degrid call */
+  int64_t n_batches;       /* kernel batches per aidg_grid / aidg_degrid call: runs of
+                              whole groups, as many as the workspace holds images */
   int64_t max_subgrid_vis; /* largest sub-table */
   int64_t n_groups;        /* runs of subgrids with one w-layer and centre that share one
                               subgrid FFT; a centre holding more than 8x the mean
@@ -140,7 +142,8 @@ typedef struct aidg_plan aidg_plan;
  * Sec. 3.1.  Each baseline's rows of one A-term interval are split at their first
  * timestep into channel runs whose uv span comfortably fits (3/4 of L - K), and
  * each run is then extended in time while every visibility stays within
- * (L - K)/2 cells of an integer centre, in one w-layer, and under max_subgrid_vis.
+ * (L - K)/2 cells of a centre cell (on the centre lattice where one fits), in one
+ * w-layer, and under max_subgrid_vis.
  * Writes up to cap records to out (may be NULL with cap 0), the count to *n_out
  * and the layer spacing used to *w_step_out.  AIDG_E_INVALID if cap is too small
  * (*n_out still receives the count). */
