@@ -91,7 +91,8 @@ typedef struct {
   int32_t reseed_channels; /* FP32 phasor recurrence re-seeded from FP64 every R channels; 0 = 32 */
   int32_t strict_range;    /* 0: unplaceable visibilities are excluded (grid ignores them,
                               degrid writes 0); 1: plan creation fails with AIDG_E_RANGE */
-  int32_t max_subgrid_vis; /* cap on visibilities per subgrid, 0 = 1024; larger caller
+  int32_t max_subgrid_vis; /* cap on visibilities per subgrid, 0 = 1024, at most 2048
+                              (they are staged in LDS: AIDG_E_INVALID above); larger caller
                               sub-tables are split in time */
   int32_t center_lattice;  /* the library's partitioner puts subgrid centres on cells
                               N/2 + k * center_lattice (Sec. 2.2: a centre snaps to a grid

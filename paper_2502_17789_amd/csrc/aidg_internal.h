@@ -11,6 +11,9 @@ namespace aidg {
 
 constexpr double kSpeedOfLight = 299792458.0;
 constexpr int kMaxSubgridVisDefault = 1024;
+// The (de)gridder stages one subgrid's visibilities (8 values each) in LDS:
+// 2048 of them take 64 KB in FP32 and 128 KB in FP64, within the 160 KB of a CU.
+constexpr int kMaxSubgridVisLimit = 2048;
 constexpr int kReseedDefault = 32;
 constexpr int64_t kWorkspaceDefault = int64_t(2) << 30;
 // A group of same-centre subgrids holds at most this many times the mean

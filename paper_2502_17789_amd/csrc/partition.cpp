@@ -44,6 +44,11 @@ aidg_status validate_geometry(const aidg_geometry* g, Geometry* o, std::string* 
     *err = "precision must be AIDG_FP32 or AIDG_FP64";
     return AIDG_E_INVALID;
   }
+  if (g->max_subgrid_vis > kMaxSubgridVisLimit) {
+    *err = "max_subgrid_vis must be <= " + std::to_string(kMaxSubgridVisLimit) +
+           " (a subgrid's visibilities are staged in LDS)";
+    return AIDG_E_INVALID;
+  }
   if (g->reseed_channels < 0 || g->max_subgrid_vis < 0 || g->workspace_bytes < 0 ||
       !std::isfinite(g->w_step) || !std::isfinite(g->taper_beta) || g->taper_beta < 0) {
     *err = "negative or non-finite numeric parameter";

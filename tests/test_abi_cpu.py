@@ -78,7 +78,8 @@ def test_auto_w_step_formula():
 
 @pytest.mark.parametrize("bad", [dict(subgrid_size=33), dict(kernel_support=32), dict(grid_size=30),
                                  dict(pixel_scale=-1.0), dict(aterm_interval=0),
-                                 dict(pixel_scale=math.radians(120) / 512)])
+                                 dict(pixel_scale=math.radians(120) / 512), dict(max_subgrid_vis=2049),
+                                 dict(max_subgrid_vis=-1), dict(center_lattice=-2)])
 def test_invalid_geometry_rejected(bad):
     kw = dict(grid_size=512, subgrid_size=32, kernel_support=8, pixel_scale=math.radians(10) / 512)
     kw.update(bad)
