@@ -37,6 +37,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "aidg_internal.h"
 
 namespace aidg {
@@ -70,6 +72,9 @@ __device__ __forceinline__ int64_t degrid_slot(int64_t b, int64_t n) {
 #endif
 constexpr int kPix = GRID_PIX;              // pixels per lane in the gridder
 constexpr int kChunk = kThreads * kPix;     // pixels per workgroup pass
+#ifndef DEGRID_LDS_REDUCE
+#define DEGRID_LDS_REDUCE 1
+#endif
 #ifndef DEGRID_GROUP
 #define DEGRID_GROUP 4  // compile-time tile parameter; 4 measured faster than 2
 #endif
@@ -633,6 +638,36 @@ __device__ __forceinline__ R transpose_reduce16(R (&a)[16], int ln) {
   return a[0] + dpp<kDppXor1>(a[0]);
 }
 
+// Per-wave LDS area of the staged reduction below: 32 values x 16 partials at a
+// pitch of 18 floats, which puts the 4 rows of 16 lanes on disjoint banks.
+constexpr int kStagePitch = 18, kStageFloats = 32 * kStagePitch;
+constexpr int kStageBytes = (kThreads / 64) * kStageFloats * 4;
+
+// FP32 variant of transpose_reduce32: the two permlane levels in registers leave
+// lane ln with partials of values i + 8 (ln >> 4) over 4 lanes; the 16 partials
+// of each value then meet in the wave's LDS area (8 stores, 8 loads, 8 adds per
+// lane instead of 22 select/DPP instructions).  On return lane ln holds the full
+// sum of value (ln >> 1) (both lanes of a pair).  The area is private to the
+// wave, whose LDS accesses complete in order, so no barrier is needed.
+__device__ __forceinline__ float transpose_reduce32_lds(float (&a)[32], int ln, float* st) {
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    swap32(a[i], a[i + 16]);
+    a[i] = a[i] + a[i + 16];
+  }
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    swap16(a[i], a[i + 8]);
+    a[i] = a[i] + a[i + 8];
+  }
+  const int row = ln >> 4, c = ln & 15;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) st[(i + 8 * row) * kStagePitch + c] = a[i];
+  const float* src = st + (ln >> 1) * kStagePitch + 8 * (ln & 1);
+  float s = ((src[0] + src[1]) + (src[2] + src[3])) + ((src[4] + src[5]) + (src[6] + src[7]));
+  return s + dpp<kDppXor1>(s);
+}
+
 template <int L, typename R>
 __global__ __launch_bounds__(kThreads)
 __attribute__((amdgpu_waves_per_eu(DegridTune<L, R>::W))) void degrid_dft(const Group g) {
@@ -640,7 +675,8 @@ __attribute__((amdgpu_waves_per_eu(DegridTune<L, R>::W))) void degrid_dft(const 
   constexpr int P = DegridTune<L, R>::P, CH = kThreads * P;
   static_assert((L * L) % CH == 0, "pixel chunks must tile the subgrid");
   extern __shared__ unsigned char smem_raw[];
-  R* accs = reinterpret_cast<R*>(smem_raw);
+  float* stage = reinterpret_cast<float*>(smem_raw) + (threadIdx.x >> 6) * kStageFloats;
+  R* accs = reinterpret_cast<R*>(smem_raw + kStageBytes);
   const int64_t local = degrid_slot(blockIdx.x, g.total_sg);
   const Slot sl = resolve(g, local);
   const KernelArgs& a = sl.a;
@@ -747,7 +783,10 @@ __attribute__((amdgpu_waves_per_eu(DegridTune<L, R>::W))) void degrid_dft(const 
         R val;
         int idx, lead;
         if constexpr (kVisGroup == 4) {
-          val = transpose_reduce32<R>(part, ln);
+          if constexpr (DEGRID_LDS_REDUCE && std::is_same_v<R, float>)
+            val = transpose_reduce32_lds(part, ln, stage);
+          else
+            val = transpose_reduce32<R>(part, ln);
           idx = ln >> 1;
           lead = !(ln & 1);
         } else {
@@ -788,8 +827,8 @@ int launch_one(KernelClass k, const Group& g, hipStream_t st, int max_nv) {
       hipLaunchKernelGGL((split_ifft<L, R>), dim3(4, n), dim3(kThreads), 0, st, g);
       break;
     case kDegridDft:
-      hipLaunchKernelGGL((degrid_dft<L, R>), dim3(n), dim3(kThreads), (size_t)max_nv * 8 * sizeof(R),
-                         st, g);
+      hipLaunchKernelGGL((degrid_dft<L, R>), dim3(n), dim3(kThreads),
+                         (size_t)kStageBytes + (size_t)max_nv * 8 * sizeof(R), st, g);
       break;
     default:
       return (int)hipErrorInvalidValue;
