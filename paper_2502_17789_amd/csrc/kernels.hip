@@ -25,9 +25,10 @@
 //              phasors follow ph <- ph * step along the channels (re-seeded from
 //              FP64 every R), and for each group of 4 channels every lane forms its
 //              pixels' partial sums (32 floats); a wave-wide transpose-reduction
-//              (permlane32/permlane16 swaps, then DPP) leaves each lane pair with
-//              one reduced value, and waves combine through LDS atomics; the
-//              finished visibilities are written once (Eq. degridder).
+//              (permlane32/permlane16 swaps, then in FP32 a per-wave LDS area, in
+//              FP64 DPP) leaves each lane pair with one reduced value, and waves
+//              combine through LDS atomics; the finished visibilities are written
+//              once (Eq. degridder).
 //
 // The centred DFT of Sec. 2.3 relates to a plain FFT by a checkerboard:
 //   sum_{x,y} s(x,y) e^{-2 pi i [(a-L/2)(x-L/2) + (b-L/2)(y-L/2)]/L}
@@ -661,8 +662,13 @@ __device__ __forceinline__ float transpose_reduce32_lds(float (&a)[32], int ln, 
     a[i] = a[i] + a[i + 8];
   }
   const int row = ln >> 4, c = ln & 15;
+  // The area is private to this wave, whose LDS operations complete in issue order;
+  // the wave barriers keep the compiler from moving this call's stores above the
+  // previous call's loads, or its loads above its stores.
+  __builtin_amdgcn_wave_barrier();
 #pragma unroll
   for (int i = 0; i < 8; ++i) st[(i + 8 * row) * kStagePitch + c] = a[i];
+  __builtin_amdgcn_wave_barrier();
   const float* src = st + (ln >> 1) * kStagePitch + 8 * (ln & 1);
   float s = ((src[0] + src[1]) + (src[2] + src[3])) + ((src[4] + src[5]) + (src[6] + src[7]));
   return s + dpp<kDppXor1>(s);
