@@ -398,6 +398,17 @@ def dataclasses_replace(obj, **kw):
     return dataclasses.replace(obj, **kw)
 
 
+def path_roofline(kt, wall_s):
+    """Sustained rate of the whole timed step: both DFT kernels' algorithmic FLOP
+    (40 per vp) over the wall time, which also covers the FFTs, the adder, the
+    splitter and the zeroing kernels."""
+    vp = sum(kt[k]["vis_pixels"] for k in ("grid_dft", "degrid_dft"))
+    achieved = vp * FLOP_PER_VP / wall_s / 1e12
+    return {"achieved": round(achieved, 3), "peak": round(PEAK_FP32_TFLOPS, 1), "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+            "scope": "grid_dft + degrid_dft FLOP over the wall time of the timed steps"}
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -513,6 +524,7 @@ def main():
                        "job": "one grid job + one degrid job of the whole observation"},
         "plan_build_s": round(plan_s, 3),
         "roofline": roof,
+        "path_roofline": path_roofline(kt, wall),
         "kernels": kernels,
     }
     plan.close()
