@@ -9,10 +9,15 @@ Pins (tests/test_oracle_*.py) tie every function here to something other than
 itself: lattice identities against the brute-force direct DFT, a Dirichlet
 closed form, numpy FFTs and scipy's Bessel function for special cases, and the
 adjoint identity between gridding and degridding.
+
+The image-level step (w-stacking, ``invert`` / ``predict``) is plain numpy in
+FP64 on top of numpy's FFT; it is pinned by a brute-force DFT matrix, the adjoint
+identity, and the direct imaging and prediction equations at the subgrid lattice.
 """
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -229,3 +234,62 @@ def lattice_dirs(wl, xs, ys):
     xs = np.asarray(xs, np.int32)
     ys = np.asarray(ys, np.int32)
     return (xs - L // 2) * step, (ys - L // 2) * step
+
+
+# ------------------------------------------------------------------ image level (w-stacking)
+
+
+def image_taper(N: int, K: int, beta: float = 0.0) -> np.ndarray:
+    """The Kaiser-Bessel taper of Sec. 4.2 at image resolution, one axis:
+    t[X] = I0(beta sqrt(1 - (2 f)^2)) / I0(beta), f = (X - N/2) / N, beta = pi K / 4
+    unless given.  The subgrid taper samples the same function at L points."""
+    beta = beta if beta > 0 else math.pi * K / 4
+    f = (np.arange(N) - N // 2) / N
+    return np.i0(beta * np.sqrt(1.0 - (2.0 * f) ** 2)) / np.i0(beta)
+
+
+def image_n1(N: int, dl: float) -> np.ndarray:
+    """n - 1 = sqrt(1 - l^2 - m^2) - 1 at image pixel [Y][X], l = (X - N/2) dl,
+    m = (Y - N/2) dl, in the cancellation-free form -r^2 / (1 + sqrt(1 - r^2))."""
+    x = (np.arange(N) - N // 2) * dl
+    r2 = x[None, :] ** 2 + x[:, None] ** 2
+    return -r2 / (1.0 + np.sqrt(1.0 - r2))
+
+
+def centred_dft2(a: np.ndarray, sign: int) -> np.ndarray:
+    """Unnormalised centred DFT over the last two axes (Sec. 2.3):
+    out[k1, k2] = sum_{x1, x2} a[x1, x2] exp(sign 2 pi i [(k1 - N/2)(x1 - N/2)
+    + (k2 - N/2)(x2 - N/2)] / N), by numpy's FFT with the centre moved to index 0."""
+    N = a.shape[-1]
+    s = np.fft.ifftshift(a, axes=(-2, -1))
+    t = np.fft.ifft2(s) * (N * N) if sign > 0 else np.fft.fft2(s)
+    return np.fft.fftshift(t, axes=(-2, -1))
+
+
+def invert(G: np.ndarray, w0, L: int, K: int, dl: float, beta: float = 0.0) -> np.ndarray:
+    """Imaging by w-stacking (Sec. 2.4, Eq. wstack; Sec. 2.5 imaging step 3):
+    I[p][Y][X] = 1 / (L^2 T(X, Y)) sum_w exp(+2 pi i w0_w n1(X, Y)) F+{G_w[p]}(Y, X),
+    F+ the centred transform with exp(+2 pi i (u l + v m)) over (gv, gu).  The 1/L^2
+    undoes the unnormalised subgrid transforms, so that at subgrid-lattice pixels the
+    image of gridded visibilities is the direct A-term image.  G: [W][P][N][N]."""
+    G = np.asarray(G)
+    N = G.shape[-1]
+    t = image_taper(N, K, beta)
+    n1 = image_n1(N, dl)
+    out = np.zeros(G.shape[1:], np.complex128)
+    for j in range(G.shape[0]):
+        out += centred_dft2(G[j].astype(np.complex128), +1) * np.exp(2j * np.pi * w0[j] * n1)
+    return out / (L * L * np.outer(t, t))
+
+
+def predict(I: np.ndarray, w0, L: int, K: int, dl: float, beta: float = 0.0) -> np.ndarray:
+    """Inverse w-stacking for prediction (Sec. 2.5 prediction step 2, Eq. wunstack),
+    taken as the exact adjoint of ``invert`` (the degridder multiplies by T, so the
+    image is divided by it here): G_w[p] = F-{ I[p] exp(-2 pi i w0_w n1) / (L^2 T) }.
+    I: [P][N][N]; returns [W][P][N][N]."""
+    I = np.asarray(I, np.complex128)
+    N = I.shape[-1]
+    t = image_taper(N, K, beta)
+    n1 = image_n1(N, dl)
+    base = I / (L * L * np.outer(t, t))
+    return np.stack([centred_dft2(base * np.exp(-2j * np.pi * w * n1), -1) for w in w0])

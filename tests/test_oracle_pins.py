@@ -400,3 +400,101 @@ def test_excluded_visibilities_are_outside(orc):
     G = synth.random_grid(1, wl.grid_size, np.random.default_rng(1))
     V = orc.degrid(wl, G, t)
     assert np.abs(V[mask == 0]).max() == 0.0
+
+
+# ------------------------------------------------------------------ image level (w-stacking)
+
+
+def dft_matrix(N, sign):
+    """Brute-force centred DFT matrix E[k][x] = exp(sign 2 pi i (k - N/2)(x - N/2) / N)."""
+    k = np.arange(N) - N // 2
+    return np.array([[np.exp(sign * 2j * np.pi * kk * xx / N) for xx in k] for kk in k])
+
+
+@pytest.mark.parametrize("N,sign", [(12, +1), (12, -1), (10, +1), (16, -1)])
+def test_centred_dft2_is_the_dft_matrix(orc, N, sign):
+    rng = np.random.default_rng(N + sign)
+    a = rng.standard_normal((3, N, N)) + 1j * rng.standard_normal((3, N, N))
+    E = dft_matrix(N, sign)
+    ref = np.stack([E @ a[i] @ E.T for i in range(3)])
+    assert rel(orc.centred_dft2(a, sign), ref) < 1e-13
+
+
+def test_image_taper_is_the_subgrid_taper_at_lattice_pixels(orc):
+    """At X - N/2 = (x - L/2) N / L the image taper equals the subgrid taper T[x]."""
+    N, L, K = 128, 32, 8
+    t = orc.image_taper(N, K)
+    T = orc.taper(L, K)
+    x = np.arange(L)
+    assert np.allclose(t[N // 2 + (x - L // 2) * (N // L)], np.sqrt(np.diag(T)), rtol=1e-13, atol=0)
+
+
+def test_invert_of_one_cell_is_a_plane_wave(orc):
+    """One grid cell (gu, gv) of layer j images to exp(2 pi i [u l + v m + w0_j n1]) / (L^2 T)."""
+    N, L, K, dl = 24, 8, 2, 0.02
+    w0 = [0.0, 7.5]
+    gu, gv = 5, 17
+    G = np.zeros((2, 1, N, N), np.complex128)
+    G[1, 0, gv, gu] = 2.0 - 1.0j
+    I = orc.invert(G, w0, L, K, dl)[0]
+    x = (np.arange(N) - N // 2) * dl
+    du = 1.0 / (N * dl)
+    t = orc.image_taper(N, K)
+    n1 = -(x[None, :] ** 2 + x[:, None] ** 2) / (1 + np.sqrt(1 - x[None, :] ** 2 - x[:, None] ** 2))
+    ref = (2.0 - 1.0j) * np.exp(2j * np.pi * ((gu - N // 2) * du * x[None, :] + (gv - N // 2) * du * x[:, None]
+                                              + w0[1] * n1)) / (L * L * np.outer(t, t))
+    assert rel(I, ref) < 1e-13
+
+
+@pytest.mark.parametrize("N", [24, 30])
+def test_invert_predict_adjoint(orc, N):
+    rng = np.random.default_rng(N)
+    w0 = [-12.0, 0.0, 9.0]
+    G = rng.standard_normal((3, 4, N, N)) + 1j * rng.standard_normal((3, 4, N, N))
+    I = rng.standard_normal((4, N, N)) + 1j * rng.standard_normal((4, N, N))
+    lhs = inner(orc.invert(G, w0, 8, 2, 0.015), I)
+    rhs = inner(G, orc.predict(I, w0, 8, 2, 0.015))
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+@pytest.mark.parametrize("seed,w_step", [(41, 0.0), (42, 12.0)])
+def test_invert_of_gridded_visibilities_is_the_direct_image(orc, seed, w_step):
+    """At subgrid-lattice pixels, invert(grid(V)) is the direct A-term image (Sec. 2.4:
+    gridding, the FFTs and w-stacking are exact at the lattice directions)."""
+    wl = synth.config_tiny(seed)
+    N, L, K = wl.grid_size, wl.subgrid_size, wl.kernel_support
+    rng = np.random.default_rng(seed)
+    V = synth.random_vis((wl.n_baselines, wl.n_times, wl.n_chans), rng)
+    table = orc.partition(wl, w_step)
+    if w_step > 0:
+        assert orc.n_layers(table) >= 2
+    I = orc.invert(orc.grid(wl, V, table), orc.layer_w(table), L, K, wl.pixel_scale)
+    xs, ys = lattice_all(L)
+    sel = rng.choice(xs.shape[0], 100, replace=False)
+    xs, ys = xs[sel], ys[sel]
+    X, Y = N // 2 + (xs - L // 2) * (N // L), N // 2 + (ys - L // 2) * (N // L)
+    l, m = orc.lattice_dirs(wl, xs, ys)
+    ref = orc.direct_image(wl, V, l, m, xs, ys, mask=orc.coverage_mask(wl, table))
+    assert rel(I[:, Y, X].T, ref) < 1e-11
+
+
+@pytest.mark.parametrize("seed,w_step", [(43, 0.0), (44, 12.0)])
+def test_degrid_of_predicted_lattice_sources_is_the_direct_prediction(orc, seed, w_step):
+    """Point sources on image pixels that are subgrid-lattice pixels: degrid(predict(I))
+    is the direct prediction of Eq. 1 for every covered visibility."""
+    wl = synth.config_tiny(seed)
+    N, L, K = wl.grid_size, wl.subgrid_size, wl.kernel_support
+    rng = np.random.default_rng(seed)
+    src = synth.point_sources(4, wl.fov, 0.5, 5.0, rng, L=L, on_lattice=True)
+    I = np.zeros((4, N, N), np.complex128)
+    for s in range(4):
+        X = N // 2 + (src["xs"][s] - L // 2) * (N // L)
+        Y = N // 2 + (src["ys"][s] - L // 2) * (N // L)
+        I[:, Y, X] += src["B"][s]
+    table = orc.partition(wl, w_step)
+    G = orc.predict(I, orc.layer_w(table), L, K, wl.pixel_scale)
+    V = orc.degrid(wl, G, table)
+    Vd = orc.direct_predict(wl, src["l"], src["m"], src["B"], src["xs"], src["ys"])
+    mask = orc.coverage_mask(wl, table).astype(bool)
+    assert mask.sum() > 0.8 * mask.size
+    assert rel(V[mask], Vd[mask]) < 1e-11
