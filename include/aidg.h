@@ -61,7 +61,7 @@
 extern "C" {
 #endif
 
-#define AIDG_ABI_VERSION 2
+#define AIDG_ABI_VERSION 3
 
 typedef enum {
   AIDG_OK = 0,
@@ -186,8 +186,9 @@ aidg_status aidg_degrid(aidg_plan* plan, const void* grid, void* vis_out, void* 
 /* Per-kernel device timing (the paper's per-subroutine breakdown, Sec. 5.4).
  * Kernel classes: 0 gridder DFT + Jones/taper epilogue, 1 FFT + adder,
  * 2 splitter + inverse FFT, 3 degridder DFT with Jones/taper prologue,
- * 4 zeroing of excluded visibilities. */
-#define AIDG_KERNEL_CLASSES 5
+ * 4 zeroing of excluded visibilities, 5 image-level row FFTs (aidg_invert /
+ * aidg_predict), 6 image-level transposes and w-stacking passes. */
+#define AIDG_KERNEL_CLASSES 7
 typedef struct {
   double ms[AIDG_KERNEL_CLASSES];            /* summed device time of the class */
   int64_t launches[AIDG_KERNEL_CLASSES];     /* kernel launches timed */
@@ -205,6 +206,36 @@ aidg_status aidg_plan_set_profiling(aidg_plan* plan, int32_t enable);
 aidg_status aidg_plan_kernel_times(aidg_plan* plan, aidg_kernel_times* out);
 
 void aidg_plan_destroy(aidg_plan* plan);
+
+/* ---- Image level: w-stacking (Sec. 2.4, Eq. wstack; Sec. 2.5 imaging step 3) and
+ * its inverse for prediction (Eq. wunstack, prediction step 2).
+ * Image pixel (X, Y), 0 <= X, Y < N, sits at l = (X - N/2) dl, m = (Y - N/2) dl,
+ * with n1 = sqrt(1 - l^2 - m^2) - 1.  Image layout: device [4][N][N] (pol, Y, X), X
+ * fastest, c64 / c128 as the plan's precision.
+ *   aidg_invert:  I[p](X, Y) = 1 / (L^2 T(X, Y)) sum_w exp(+2 pi i w0_w n1)
+ *                              sum_{gu, gv} G_w[p][gv][gu] exp(+2 pi i (u l + v m))
+ *   aidg_predict: G_w[p][gv][gu] = sum_{X, Y} I[p](X, Y) exp(-2 pi i w0_w n1)
+ *                              exp(-2 pi i (u l + v m)) / (L^2 T(X, Y))
+ * with u l + v m = [(gu - N/2)(X - N/2) + (gv - N/2)(Y - N/2)] / N, w0_w the plan's
+ * layers and T(X, Y) = t(X) t(Y) the plan's Kaiser-Bessel taper sampled at image
+ * resolution, t(X) = I0(beta sqrt(1 - (2 (X - N/2)/N)^2)) / I0(beta).  The 1/L^2
+ * undoes the unnormalised subgrid transforms: at image pixels on the subgrid lattice
+ * (X - N/2 = (x - L/2) N / L) invert of gridded visibilities is the direct A-term
+ * image of those visibilities, and prediction of point sources at such pixels
+ * degrids to their direct visibilities.  aidg_predict is the exact adjoint of
+ * aidg_invert; the taper divides in both (the degridder multiplies by T, unlike
+ * the paper's Eq. degridder, which divides by it).
+ * Both OVERWRITE their output (the whole image / every layer of the grid).
+ * Supported: N = 2^a 3^b 5^c, N <= 8192 with a row of N complex values within 64 KB
+ * (N <= 8192 in FP32, N <= 4096 in FP64); otherwise AIDG_E_UNSUPPORTED.  The
+ * workspace is caller-owned device memory of aidg_image_workspace_bytes (two N x N
+ * planes), AIDG_E_INVALID when smaller.  Neither call allocates or synchronises the
+ * host; both queue kernels on hip_stream after the plan's earlier work. */
+aidg_status aidg_image_workspace_bytes(const aidg_plan* plan, int64_t* bytes);
+aidg_status aidg_invert(aidg_plan* plan, const void* grid, void* image, void* workspace,
+                        int64_t workspace_bytes, void* hip_stream);
+aidg_status aidg_predict(aidg_plan* plan, const void* image, void* grid, void* workspace,
+                         int64_t workspace_bytes, void* hip_stream);
 
 /* ---- Serving: grouped execution of work from many plans (continuous batching).
  * Gridding and degridding decompose into independent subgrids (Sec. 2.2: the

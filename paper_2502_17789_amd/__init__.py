@@ -54,7 +54,8 @@ class _PlanInfo(ctypes.Structure):
                 ("n_groups", ctypes.c_int64)]
 
 
-KERNEL_CLASSES = ("grid_dft", "fft_add", "split_ifft", "degrid_dft", "zero_vis")
+KERNEL_CLASSES = ("grid_dft", "fft_add", "split_ifft", "degrid_dft", "zero_vis", "image_fft",
+                  "image_wstack")
 DIR_GRID, DIR_DEGRID = 0, 1
 
 
@@ -65,8 +66,8 @@ class _Work(ctypes.Structure):
 
 
 class _KernelTimes(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 5), ("launches", ctypes.c_int64 * 5),
-                ("vis_pixels", ctypes.c_int64 * 5), ("subgrids", ctypes.c_int64 * 5)]
+    _fields_ = [("ms", ctypes.c_double * 7), ("launches", ctypes.c_int64 * 7),
+                ("vis_pixels", ctypes.c_int64 * 7), ("subgrids", ctypes.c_int64 * 7)]
 
 
 @dataclasses.dataclass
@@ -95,7 +96,7 @@ class Geometry:
 
 
 _lib = None
-ABI_VERSION = 2  # the structure layouts above follow include/aidg.h at this version
+ABI_VERSION = 3  # the structure layouts above follow include/aidg.h at this version
 
 
 def library() -> ctypes.CDLL:
@@ -124,6 +125,9 @@ def library() -> ctypes.CDLL:
         "aidg_executor_create": (I32, [I64, P]),
         "aidg_execute": (I32, [P, P, I32, P]),
         "aidg_executor_destroy": (None, [P]),
+        "aidg_image_workspace_bytes": (I32, [P, P]),
+        "aidg_invert": (I32, [P, P, P, P, I64, P]),
+        "aidg_predict": (I32, [P, P, P, P, I64, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -256,6 +260,43 @@ class Plan:
             out = torch.empty(self.vis_shape(), dtype=self._cdtype, device=grid.device)
         self._check_tensor(out, self.vis_shape(), "vis")
         _check(library().aidg_degrid(self._h, _dptr(grid), _dptr(out), _stream_handle(stream)))
+        return out
+
+    def image_shape(self):
+        N = self.geometry.grid_size
+        return (4, N, N)
+
+    def _image_workspace(self, device):
+        import torch
+        n = ctypes.c_int64()
+        _check(library().aidg_image_workspace_bytes(self._h, ctypes.byref(n)))
+        ws = getattr(self, "_img_ws", None)
+        if ws is None or ws.numel() < n.value or ws.device != device:
+            ws = self._img_ws = torch.empty(n.value, dtype=torch.uint8, device=device)
+        return ws
+
+    def invert(self, grid, out=None, stream=None):
+        """Image ``grid`` [W, 4, N, N] by w-stacking into ``out`` [4, N, N] (overwritten)."""
+        import torch
+        self._check_tensor(grid, self.grid_shape(), "grid")
+        if out is None:
+            out = torch.empty(self.image_shape(), dtype=self._cdtype, device=grid.device)
+        self._check_tensor(out, self.image_shape(), "image")
+        ws = self._image_workspace(grid.device)
+        _check(library().aidg_invert(self._h, _dptr(grid), _dptr(out), _dptr(ws), ws.numel(),
+                                     _stream_handle(stream)))
+        return out
+
+    def predict(self, image, out=None, stream=None):
+        """Grid layers [W, 4, N, N] (``out``, overwritten) predicted from ``image`` [4, N, N]."""
+        import torch
+        self._check_tensor(image, self.image_shape(), "image")
+        if out is None:
+            out = torch.empty(self.grid_shape(), dtype=self._cdtype, device=image.device)
+        self._check_tensor(out, self.grid_shape(), "grid")
+        ws = self._image_workspace(image.device)
+        _check(library().aidg_predict(self._h, _dptr(image), _dptr(out), _dptr(ws), ws.numel(),
+                                      _stream_handle(stream)))
         return out
 
     def set_profiling(self, enable: bool = True):

@@ -98,11 +98,34 @@ struct Group {
 };
 
 // Kernel classes, in the order of aidg_kernel_times.
-enum KernelClass { kGridDft = 0, kFftAdd = 1, kSplitIfft = 2, kDegridDft = 3, kZeroVis = 4 };
+enum KernelClass {
+  kGridDft = 0, kFftAdd = 1, kSplitIfft = 2, kDegridDft = 3, kZeroVis = 4,
+  kImageFft = 5,      // image-level row FFTs (invert / predict)
+  kImageWstack = 6    // image-level transposes and w-stacking passes
+};
 
 // Launch one kernel class over a group (kernels.hip).  max_nv: the largest
 // sub-table of the group (degridder LDS).  Returns a hipError_t as int.
 int launch_group(KernelClass k, int L, int precision, const Group& g, void* stream, int max_nv);
 int launch_zero_vis(int precision, const int64_t* idx, int64_t n, void* vis, void* stream);
+
+// Image level (image.hip).  A row of N complex values is transformed in LDS: N must
+// factor into radices 4, 2, 3 and 5 and a row must fit in 64 KB.
+constexpr int kMaxImageN = 8192;
+constexpr int kMaxImageRowBytes = 65536;
+constexpr int kMaxImageRadices = 16;
+struct ImageRadices {
+  int32_t n;                     // number of Stockham passes
+  int32_t r[kMaxImageRadices];   // radix of each pass
+};
+// Factorisation of N in pass order (4s first); false when N is not supported.
+bool image_radices(int N, int elem_bytes, ImageRadices* out);
+void kaiser_bessel_axis(int n, double beta, std::vector<double>* t);
+int launch_image_fft_rows(int precision, int dir, bool predict, const void* src, void* dst, int N,
+                          const ImageRadices& fr, const void* tw, const double* taper, double dl,
+                          double w0, double inv_l2, void* stream);
+int launch_image_transpose(int precision, const void* src, void* dst, int N, void* stream);
+int launch_image_wstack(int precision, const void* B, void* img, int N, const double* taper, double dl,
+                        double w0, double inv_l2, int assign, void* stream);
 
 }  // namespace aidg

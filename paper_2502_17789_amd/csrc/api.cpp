@@ -77,6 +77,12 @@ struct aidg_plan {
   int64_t* d_excl = nullptr;
   int64_t* d_grp = nullptr;
   KernelArgs* d_args = nullptr;  // device copy of args()
+  // image level (invert / predict): Stockham radices of N, twiddles exp(-2 pi i k / N)
+  // and the taper's axis at image resolution (FP64); absent when N is not supported
+  ImageRadices img_fr{};
+  bool img_ok = false;
+  void* d_img_tw = nullptr;
+  double* d_img_taper = nullptr;
   hipEvent_t last = nullptr;
   std::atomic<bool> busy{false};
   // profiling: events around each kernel launch
@@ -116,7 +122,8 @@ struct aidg_plan {
   bool async_mem = false;
 
   void release() {
-    void* ptrs[] = {d_sg, d_uvw, d_fc, d_aterms, d_taper, d_tw, d_scratch, d_excl, d_grp, d_args};
+    void* ptrs[] = {d_sg,      d_uvw,  d_fc,   d_aterms, d_taper,  d_tw,
+                    d_scratch, d_excl, d_grp,  d_args,   d_img_tw, d_img_taper};
     hipStream_t fs = async_mem ? release_stream(device) : nullptr;
     int cur = device;
     if (fs) {
@@ -142,6 +149,8 @@ struct aidg_plan {
     d_excl = nullptr;
     d_grp = nullptr;
     d_args = nullptr;
+    d_img_tw = nullptr;
+    d_img_taper = nullptr;
     last = nullptr;
   }
 };
@@ -224,6 +233,32 @@ aidg_status dalloc(T** p, size_t bytes, aidg_plan* plan, const char* what, hipSt
   }
   *p = reinterpret_cast<T*>(q);
   plan->device_bytes += n;
+  return AIDG_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// Shared checks of aidg_invert / aidg_predict.
+aidg_status image_args(aidg_plan* plan, const void* a, const void* b, const void* ws, int64_t ws_bytes) {
+  if (!plan || !a || !b || !ws) return fail(AIDG_E_INVALID, "NULL plan, grid, image or workspace");
+  if (!plan->img_ok)
+    return fail(AIDG_E_UNSUPPORTED, "image-level transforms need N = 2^a 3^b 5^c <= 8192 with a row of N "
+                                    "complex values within 64 KB");
+  const int64_t N = plan->g.N;
+  if (ws_bytes < 2 * N * N * (int64_t)plan->elem)
+    return fail(AIDG_E_INVALID, "workspace smaller than aidg_image_workspace_bytes");
+  return AIDG_OK;
+}
+
+// Run one image-level launcher, timed as class k when the plan is profiling.
+template <typename F>
+aidg_status image_step(aidg_plan* p, hipStream_t st, KernelClass k, F&& launch) {
+  TimedLaunch tl(p, st);
+  const int rc = launch();
+  if (rc != 0) return hip_fail((hipError_t)rc, "image kernel launch");
+  tl.done(k, 0, 0);
   return AIDG_OK;
 }
 
@@ -432,6 +467,19 @@ aidg_status aidg_plan_create(const aidg_geometry* geo, int32_t n_stations, int32
     }
     const bool f32 = g.precision == AIDG_FP32;
     std::vector<float> Tf(T.begin(), T.end()), twf(tw.begin(), tw.end());
+    // image level: twiddles exp(-2 pi i k / N) and the taper axis t[X] at image resolution
+    std::vector<double> img_t, img_tw;
+    plan->img_ok = image_radices(g.N, (int)plan->elem, &plan->img_fr);
+    if (plan->img_ok) {
+      kaiser_bessel_axis(g.N, g.beta, &img_t);
+      img_tw.resize(2 * (size_t)g.N);
+      for (int k = 0; k < g.N; ++k) {
+        const double ang = -2.0 * M_PI * k / g.N;
+        img_tw[2 * (size_t)k] = std::cos(ang);
+        img_tw[2 * (size_t)k + 1] = std::sin(ang);
+      }
+    }
+    std::vector<float> img_twf(img_tw.begin(), img_tw.end());
 
     plan->aterm_bytes = (size_t)plan->n_int * n_stations * L * L * 4 * plan->elem;
     const size_t per_sg = (size_t)4 * L * L * plan->elem;
@@ -470,7 +518,10 @@ aidg_status aidg_plan_create(const aidg_geometry* geo, int32_t n_stations, int32
         (st = dalloc(&plan->d_excl, pr.excluded.size() * sizeof(int64_t), plan, "excluded list", stream)) ||
         (st = dalloc(&plan->d_grp, plan->grp_begin.size() * sizeof(int64_t), plan, "group index", stream)) ||
         (st = dalloc(&plan->d_scratch, plan->scratch_bytes, plan, "subgrid workspace", stream)) ||
-        (st = dalloc(&plan->d_args, sizeof(KernelArgs), plan, "launch parameters", stream))) {
+        (st = dalloc(&plan->d_args, sizeof(KernelArgs), plan, "launch parameters", stream)) ||
+        (plan->img_ok &&
+         ((st = dalloc(&plan->d_img_tw, (size_t)g.N * plan->elem, plan, "image twiddles", stream)) ||
+          (st = dalloc(&plan->d_img_taper, (size_t)g.N * sizeof(double), plan, "image taper", stream))))) {
       abandon();
       return st;
     }
@@ -492,6 +543,10 @@ aidg_status aidg_plan_create(const aidg_geometry* geo, int32_t n_stations, int32
         {plan->d_excl, pr.excluded.data(), pr.excluded.size() * sizeof(int64_t), hipMemcpyHostToDevice},
         {plan->d_grp, plan->grp_begin.data(), plan->grp_begin.size() * sizeof(int64_t), hipMemcpyHostToDevice},
         {plan->d_args, &host_args, sizeof(KernelArgs), hipMemcpyHostToDevice},
+        {plan->d_img_tw, f32 ? (const void*)img_twf.data() : (const void*)img_tw.data(),
+         plan->img_ok ? (size_t)g.N * plan->elem : 0, hipMemcpyHostToDevice},
+        {plan->d_img_taper, img_t.data(), plan->img_ok ? (size_t)g.N * sizeof(double) : 0,
+         hipMemcpyHostToDevice},
     };
     for (const Copy& c : copies) {
       if (!c.n) continue;
@@ -596,6 +651,96 @@ aidg_status aidg_degrid(aidg_plan* plan, const void* grid, void* vis_out, void* 
     if (r == AIDG_OK) r = run(plan, kDegridDft, b0, nb, nullptr, vis_out, hip_stream);
     if (r != AIDG_OK) return r;
   }
+  e = hipEventRecord(plan->last, st);
+  return e == hipSuccess ? AIDG_OK : hip_fail(e, "hipEventRecord");
+}
+
+aidg_status aidg_image_workspace_bytes(const aidg_plan* plan, int64_t* bytes) {
+  if (!plan || !bytes) return fail(AIDG_E_INVALID, "NULL plan or output");
+  if (!plan->img_ok)
+    return fail(AIDG_E_UNSUPPORTED, "image-level transforms need N = 2^a 3^b 5^c <= 8192 with a row of N "
+                                    "complex values within 64 KB");
+  *bytes = 2 * (int64_t)plan->g.N * plan->g.N * (int64_t)plan->elem;
+  return AIDG_OK;
+}
+
+aidg_status aidg_invert(aidg_plan* plan, const void* grid, void* image, void* workspace,
+                        int64_t workspace_bytes, void* hip_stream) {
+  aidg_status r = image_args(plan, grid, image, workspace, workspace_bytes);
+  if (r != AIDG_OK) return r;
+  BusyGuard guard(plan);
+  if (!guard.ok) return fail(AIDG_E_BUSY, "plan in use by another thread");
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  hipError_t e = hipStreamWaitEvent(st, plan->last, 0);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
+  const int N = plan->g.N, prec = plan->g.precision;
+  const size_t plane = (size_t)N * N * plan->elem;
+  char* A = static_cast<char*>(workspace);
+  char* B = A + plane;
+  const double dl = plan->g.dl, inv_l2 = 1.0 / ((double)plan->g.L * plan->g.L);
+  for (int pol = 0; pol < 4 && r == AIDG_OK; ++pol) {
+    char* img = static_cast<char*>(image) + pol * plane;
+    for (int w = 0; w < plan->W && r == AIDG_OK; ++w) {
+      const char* G = static_cast<const char*>(grid) + ((size_t)w * 4 + pol) * plane;
+      // rows: G[gv][gu] -> A[gv][X]; transpose -> B[X][gv]; rows -> B[X][Y]; add into img[Y][X]
+      r = image_step(plan, st, kImageFft, [&] {
+        return launch_image_fft_rows(prec, +1, false, G, A, N, plan->img_fr, plan->d_img_tw,
+                                     plan->d_img_taper, dl, 0.0, inv_l2, st);
+      });
+      if (r == AIDG_OK)
+        r = image_step(plan, st, kImageWstack, [&] { return launch_image_transpose(prec, A, B, N, st); });
+      if (r == AIDG_OK)
+        r = image_step(plan, st, kImageFft, [&] {
+          return launch_image_fft_rows(prec, +1, false, B, B, N, plan->img_fr, plan->d_img_tw,
+                                       plan->d_img_taper, dl, 0.0, inv_l2, st);
+        });
+      if (r == AIDG_OK)
+        r = image_step(plan, st, kImageWstack, [&] {
+          return launch_image_wstack(prec, B, img, N, plan->d_img_taper, dl, plan->w0[w], inv_l2, w == 0, st);
+        });
+    }
+  }
+  if (r != AIDG_OK) return r;
+  e = hipEventRecord(plan->last, st);
+  return e == hipSuccess ? AIDG_OK : hip_fail(e, "hipEventRecord");
+}
+
+aidg_status aidg_predict(aidg_plan* plan, const void* image, void* grid, void* workspace,
+                         int64_t workspace_bytes, void* hip_stream) {
+  aidg_status r = image_args(plan, image, grid, workspace, workspace_bytes);
+  if (r != AIDG_OK) return r;
+  BusyGuard guard(plan);
+  if (!guard.ok) return fail(AIDG_E_BUSY, "plan in use by another thread");
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  hipError_t e = hipStreamWaitEvent(st, plan->last, 0);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
+  const int N = plan->g.N, prec = plan->g.precision;
+  const size_t plane = (size_t)N * N * plan->elem;
+  char* A = static_cast<char*>(workspace);
+  char* B = A + plane;
+  const double dl = plan->g.dl, inv_l2 = 1.0 / ((double)plan->g.L * plan->g.L);
+  for (int w = 0; w < plan->W && r == AIDG_OK; ++w) {
+    for (int pol = 0; pol < 4 && r == AIDG_OK; ++pol) {
+      const char* img = static_cast<const char*>(image) + pol * plane;
+      char* G = static_cast<char*>(grid) + ((size_t)w * 4 + pol) * plane;
+      // rows of img[Y][X] times the w-term -> A[Y][gu]; transpose -> B[gu][Y];
+      // rows -> B[gu][gv]; transpose -> G[gv][gu]
+      r = image_step(plan, st, kImageFft, [&] {
+        return launch_image_fft_rows(prec, -1, true, img, A, N, plan->img_fr, plan->d_img_tw,
+                                     plan->d_img_taper, dl, plan->w0[w], inv_l2, st);
+      });
+      if (r == AIDG_OK)
+        r = image_step(plan, st, kImageWstack, [&] { return launch_image_transpose(prec, A, B, N, st); });
+      if (r == AIDG_OK)
+        r = image_step(plan, st, kImageFft, [&] {
+          return launch_image_fft_rows(prec, -1, false, B, B, N, plan->img_fr, plan->d_img_tw,
+                                       plan->d_img_taper, dl, 0.0, inv_l2, st);
+        });
+      if (r == AIDG_OK)
+        r = image_step(plan, st, kImageWstack, [&] { return launch_image_transpose(prec, B, G, N, st); });
+    }
+  }
+  if (r != AIDG_OK) return r;
   e = hipEventRecord(plan->last, st);
   return e == hipSuccess ? AIDG_OK : hip_fail(e, "hipEventRecord");
 }

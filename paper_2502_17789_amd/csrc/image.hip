@@ -1,0 +1,227 @@
+// HIP kernels of the image-level step: w-stacking for imaging (Sec. 2.4, Eq. wstack;
+// Sec. 2.5 imaging step 3) and its adjoint for prediction (Eq. wunstack, prediction
+// step 2).  A centred N x N transform is two passes of one-dimensional FFTs along
+// rows with a tiled transpose between them:
+//   image_fft_rows  one workgroup per row: the row is read into LDS times (-1)^x,
+//                   transformed by mixed-radix Stockham passes (radix 4/2/3/5,
+//                   twiddles from a table), and written back times (-1)^k.  The
+//                   prediction variant first multiplies each image value by
+//                   exp(-2 pi i w0 n1) / (L^2 T).
+//   image_transpose 32 x 32 tiles through LDS.
+//   image_wstack    a transposing tile pass that adds one layer's transform times
+//                   exp(+2 pi i w0 n1) / (L^2 T) into the image (or stores it, for
+//                   the first layer).
+// For even N, (-1)^k FFT[(-1)^x a](k) is the centred transform times (-1)^(N/2); the
+// sign cancels between the two passes of a plane.
+#include <hip/hip_runtime.h>
+
+#include "aidg_internal.h"
+#include "device_common.h"
+
+namespace aidg {
+namespace {
+
+constexpr int kFftThreads = 1024;
+constexpr int kTile = 32;
+
+// One Stockham pass of radix R over the row held in LDS (Ls = product of the
+// earlier radices): butterfly j < N/R reads buf[j + i N/R], multiplies input i by
+// exp(DIR 2 pi i k i / (Ls R)) with k = j mod Ls, and writes its outputs to
+// buf[(j / Ls) Ls R + k + i Ls].  In place: every read, a barrier, every write.
+template <int R, int DIR, typename V2>
+__device__ __forceinline__ void row_pass(V2* buf, int N, int Ls, const V2* __restrict__ tw) {
+  using Rt = decltype(V2{}.x);
+  constexpr int MAXB = (kMaxImageN / R + kFftThreads - 1) / kFftThreads;
+  const int m = N / R, tstep = N / (Ls * R);
+  V2 y[MAXB][R];
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    const int j = threadIdx.x + b * kFftThreads;
+    if (j < m) {
+      const int k = j % Ls;
+#pragma unroll
+      for (int i = 0; i < R; ++i) y[b][i] = buf[j + i * m];
+#pragma unroll
+      for (int i = 1; i < R; ++i) {
+        V2 w = tw[k * i * tstep];  // exp(-2 pi i k i / (Ls R))
+        if (DIR > 0) w.y = -w.y;
+        y[b][i] = cmul<Rt>(y[b][i], w);
+      }
+      butterfly<V2, R, DIR>(y[b]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    const int j = threadIdx.x + b * kFftThreads;
+    if (j < m) {
+      const int k = j % Ls, base = (j / Ls) * Ls * R + k;
+#pragma unroll
+      for (int i = 0; i < R; ++i) buf[base + i * Ls] = y[b][i];
+    }
+  }
+  __syncthreads();
+}
+
+template <int DIR, typename V2>
+__device__ __forceinline__ void row_fft(V2* buf, const ImageRadices& fr, int N, const V2* tw) {
+  int Ls = 1;
+  for (int p = 0; p < fr.n; ++p) {
+    const int r = fr.r[p];
+    if (r == 4) row_pass<4, DIR>(buf, N, Ls, tw);
+    else if (r == 2) row_pass<2, DIR>(buf, N, Ls, tw);
+    else if (r == 3) row_pass<3, DIR>(buf, N, Ls, tw);
+    else row_pass<5, DIR>(buf, N, Ls, tw);
+    Ls *= r;
+  }
+}
+
+// exp(sign 2 pi i w0 n1(X, Y)) / (L^2 T(X, Y)) at image pixel (X, Y):
+// l = (X - N/2) dl, m = (Y - N/2) dl, n1 = -r^2 / (1 + sqrt(1 - r^2)).
+template <typename R>
+__device__ __forceinline__ typename C2<R>::T wterm(int X, int Y, int N, double dl, double w0,
+                                                   const double* __restrict__ taper, double inv_l2,
+                                                   double sign) {
+  const double l = (X - N / 2) * dl, m = (Y - N / 2) * dl, r2 = l * l + m * m;
+  const double n1 = -r2 / (1.0 + sqrt(1.0 - r2));
+  const auto ph = phasor(sign * w0 * n1, R());
+  const R sc = (R)(inv_l2 / (taper[X] * taper[Y]));
+  return {ph.x * sc, ph.y * sc};
+}
+
+// Row transforms of an N x N plane, src and dst may be the same buffer (each
+// workgroup reads its whole row before it writes).  PREDICT: src is an image plane
+// [Y][X] and each value is first multiplied by wterm(X, Y) with sign -1.
+template <typename R, int DIR, bool PREDICT>
+__global__ __launch_bounds__(kFftThreads) void image_fft_rows(const typename C2<R>::T* src,
+                                                              typename C2<R>::T* dst, int N,
+                                                              ImageRadices fr,
+                                                              const typename C2<R>::T* __restrict__ tw,
+                                                              const double* __restrict__ taper,
+                                                              double dl, double w0, double inv_l2) {
+  using V2 = typename C2<R>::T;
+  extern __shared__ unsigned char smem_raw[];
+  V2* buf = reinterpret_cast<V2*>(smem_raw);
+  const int row = blockIdx.x;
+  const V2* s = src + (size_t)row * N;
+  for (int x = threadIdx.x; x < N; x += kFftThreads) {
+    V2 v = s[x];
+    if constexpr (PREDICT) v = cmul<R>(v, wterm<R>(x, row, N, dl, w0, taper, inv_l2, -1.0));
+    if (x & 1) v = V2{-v.x, -v.y};
+    buf[x] = v;
+  }
+  __syncthreads();
+  row_fft<DIR>(buf, fr, N, tw);
+  V2* d = dst + (size_t)row * N;
+  for (int k = threadIdx.x; k < N; k += kFftThreads) {
+    V2 v = buf[k];
+    if (k & 1) v = V2{-v.x, -v.y};
+    d[k] = v;
+  }
+}
+
+// dst[x][y] = src[y][x] over 32 x 32 tiles (grid ceil(N/32) x ceil(N/32), 256 threads).
+template <typename V2>
+__global__ __launch_bounds__(256) void image_transpose(const V2* __restrict__ src, V2* __restrict__ dst,
+                                                       int N) {
+  __shared__ V2 tile[kTile][kTile + 1];
+  const int bx = blockIdx.x * kTile, by = blockIdx.y * kTile;
+  const int tx = threadIdx.x % kTile, ty = threadIdx.x / kTile;
+  for (int j = ty; j < kTile; j += 256 / kTile) {
+    const int y = by + j, x = bx + tx;
+    if (y < N && x < N) tile[j][tx] = src[(size_t)y * N + x];
+  }
+  __syncthreads();
+  for (int j = ty; j < kTile; j += 256 / kTile) {
+    const int y = bx + j, x = by + tx;
+    if (y < N && x < N) dst[(size_t)y * N + x] = tile[tx][j];
+  }
+}
+
+// One layer of Eq. wstack: img[Y][X] (+)= B[X][Y] * wterm(X, Y) with sign +1.  B is
+// the layer's transform with rows X (the second row pass ran along v); tiles are
+// read along Y and written along X.
+template <typename R>
+__global__ __launch_bounds__(256) void image_wstack(const typename C2<R>::T* __restrict__ B,
+                                                    typename C2<R>::T* __restrict__ img, int N,
+                                                    const double* __restrict__ taper, double dl,
+                                                    double w0, double inv_l2, int assign) {
+  using V2 = typename C2<R>::T;
+  __shared__ V2 tile[kTile][kTile + 1];
+  const int bx = blockIdx.x * kTile, by = blockIdx.y * kTile;  // X and Y ranges
+  const int tx = threadIdx.x % kTile, ty = threadIdx.x / kTile;
+  for (int j = ty; j < kTile; j += 256 / kTile) {
+    const int X = bx + j, Y = by + tx;
+    if (X < N && Y < N) tile[j][tx] = B[(size_t)X * N + Y];
+  }
+  __syncthreads();
+  for (int j = ty; j < kTile; j += 256 / kTile) {
+    const int Y = by + j, X = bx + tx;
+    if (X < N && Y < N) {
+      const V2 v = cmul<R>(tile[tx][j], wterm<R>(X, Y, N, dl, w0, taper, inv_l2, 1.0));
+      V2* o = img + (size_t)Y * N + X;
+      *o = assign ? v : V2{o->x + v.x, o->y + v.y};
+    }
+  }
+}
+
+template <typename R>
+int fft_rows_t(int dir, bool predict, const void* src, void* dst, int N, const ImageRadices& fr,
+               const void* tw, const double* taper, double dl, double w0, double inv_l2,
+               hipStream_t st) {
+  using V2 = typename C2<R>::T;
+  const size_t lds = (size_t)N * sizeof(V2);
+  const V2* s = reinterpret_cast<const V2*>(src);
+  V2* d = reinterpret_cast<V2*>(dst);
+  const V2* t = reinterpret_cast<const V2*>(tw);
+  if (predict)
+    hipLaunchKernelGGL((image_fft_rows<R, -1, true>), dim3(N), dim3(kFftThreads), lds, st, s, d, N, fr,
+                       t, taper, dl, w0, inv_l2);
+  else if (dir > 0)
+    hipLaunchKernelGGL((image_fft_rows<R, 1, false>), dim3(N), dim3(kFftThreads), lds, st, s, d, N, fr,
+                       t, taper, dl, w0, inv_l2);
+  else
+    hipLaunchKernelGGL((image_fft_rows<R, -1, false>), dim3(N), dim3(kFftThreads), lds, st, s, d, N, fr,
+                       t, taper, dl, w0, inv_l2);
+  return (int)hipGetLastError();
+}
+
+}  // namespace
+
+int launch_image_fft_rows(int precision, int dir, bool predict, const void* src, void* dst, int N,
+                          const ImageRadices& fr, const void* tw, const double* taper, double dl,
+                          double w0, double inv_l2, void* stream) {
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  return precision == AIDG_FP64
+             ? fft_rows_t<double>(dir, predict, src, dst, N, fr, tw, taper, dl, w0, inv_l2, st)
+             : fft_rows_t<float>(dir, predict, src, dst, N, fr, tw, taper, dl, w0, inv_l2, st);
+}
+
+int launch_image_transpose(int precision, const void* src, void* dst, int N, void* stream) {
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const dim3 grid((N + kTile - 1) / kTile, (N + kTile - 1) / kTile);
+  if (precision == AIDG_FP64)
+    hipLaunchKernelGGL((image_transpose<double2>), grid, dim3(256), 0, st,
+                       reinterpret_cast<const double2*>(src), reinterpret_cast<double2*>(dst), N);
+  else
+    hipLaunchKernelGGL((image_transpose<float2>), grid, dim3(256), 0, st,
+                       reinterpret_cast<const float2*>(src), reinterpret_cast<float2*>(dst), N);
+  return (int)hipGetLastError();
+}
+
+int launch_image_wstack(int precision, const void* B, void* img, int N, const double* taper, double dl,
+                        double w0, double inv_l2, int assign, void* stream) {
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const dim3 grid((N + kTile - 1) / kTile, (N + kTile - 1) / kTile);
+  if (precision == AIDG_FP64)
+    hipLaunchKernelGGL((image_wstack<double>), grid, dim3(256), 0, st,
+                       reinterpret_cast<const double2*>(B), reinterpret_cast<double2*>(img), N, taper,
+                       dl, w0, inv_l2, assign);
+  else
+    hipLaunchKernelGGL((image_wstack<float>), grid, dim3(256), 0, st,
+                       reinterpret_cast<const float2*>(B), reinterpret_cast<float2*>(img), N, taper,
+                       dl, w0, inv_l2, assign);
+  return (int)hipGetLastError();
+}
+
+}  // namespace aidg

@@ -41,6 +41,7 @@
 #include <type_traits>
 
 #include "aidg_internal.h"
+#include "device_common.h"
 
 namespace aidg {
 namespace {
@@ -88,53 +89,6 @@ static_assert(kVisGroup == 2 || kVisGroup == 4, "even group: phasor ping-pong re
 // FP32, P = 6 at 3 waves per SIMD measured faster than P = 9 at 2 and P = 4 at 4.
 template <int L, typename R> struct DegridTune { static constexpr int P = L == 32 ? 4 : L == 64 ? 8 : 6, W = 1; };
 template <> struct DegridTune<96, float> { static constexpr int P = 6, W = 3; };
-
-template <typename R> struct C2;
-template <> struct C2<float> { using T = float2; };
-template <> struct C2<double> { using T = double2; };
-template <typename R> struct C4;
-template <> struct C4<float> { using T = float4; };
-template <> struct C4<double> { using T = double4; };
-
-template <typename R>
-__device__ __forceinline__ typename C2<R>::T cmul(typename C2<R>::T a, typename C2<R>::T b) {
-  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
-}
-
-// exp(2 pi i theta) for a phase theta in turns, FP32 result.  The quarter-turn
-// reduction happens in FP64 (theta = q/4 + t, |t| <= 1/8, exact), t is rounded
-// once to FP32, and sin/cos(2 pi t) come from their Taylor series to degree 9
-// and 10 (truncation < 2e-9 for |2 pi t| <= pi/4), evaluated by Horner in FP32.
-__device__ __forceinline__ float2 phasor(double theta, float) {
-  const double q = rint(4.0 * theta);
-  const float t = (float)fma(q, -0.25, theta);
-  const int qi = (int)q;  // |theta| is bounded by the grid size in turns
-  const float t2 = t * t;
-  float s = fmaf(t2, 42.058693944897634f, -76.70585975306136f);
-  s = fmaf(t2, s, 81.60524927607504f);
-  s = fmaf(t2, s, -41.341702240399755f);
-  s = fmaf(t2, s, 6.283185307179586f);
-  s = s * t;
-  float c = fmaf(t2, -26.426256783374388f, 60.24464137187664f);
-  c = fmaf(t2, c, -85.45681720669371f);
-  c = fmaf(t2, c, 64.93939402266828f);
-  c = fmaf(t2, c, -19.739208802178716f);
-  c = fmaf(t2, c, 1.0f);
-  // rotate by qi quarter turns: swap for odd qi, then flip the sign bits (cos is
-  // negative for qi = 1, 2 mod 4 and sin for qi = 2, 3: bit 1 of qi + 1 and of qi)
-  const bool odd = qi & 1;
-  const float cc = odd ? s : c, ss = odd ? c : s;
-  const unsigned sign_c = ((unsigned)(qi + 1) << 30) & 0x80000000u, sign_s = ((unsigned)qi << 30) & 0x80000000u;
-  return {__uint_as_float(__float_as_uint(cc) ^ sign_c), __uint_as_float(__float_as_uint(ss) ^ sign_s)};
-}
-
-// FP64 variant: reduction to [-1/2, 1/2] and the device library's sincospi.
-__device__ __forceinline__ double2 phasor(double theta, double) {
-  const double r = theta - rint(theta);
-  double s, c;
-  sincospi(2.0 * r, &s, &c);
-  return {c, s};
-}
 
 struct Pixel {
   int pix, x, y;
@@ -387,32 +341,6 @@ template <int L> struct Radices;
 template <> struct Radices<32> { static constexpr int n = 3, r[4] = {4, 4, 2, 1}; };
 template <> struct Radices<64> { static constexpr int n = 3, r[4] = {4, 4, 4, 1}; };
 template <> struct Radices<96> { static constexpr int n = 4, r[4] = {4, 4, 2, 3}; };
-
-template <typename V2, int R, int DIR>
-__device__ __forceinline__ void butterfly(V2* v) {
-  using Rt = decltype(v[0].x);
-  if constexpr (R == 2) {
-    const V2 a = v[0], b = v[1];
-    v[0] = a + b;
-    v[1] = a - b;
-  } else if constexpr (R == 4) {
-    const V2 t0 = v[0] + v[2], t1 = v[0] - v[2], t2 = v[1] + v[3];
-    const V2 d = v[1] - v[3];
-    const V2 t3 = {Rt(-DIR) * d.y, Rt(DIR) * d.x};  // (DIR i) d
-    v[0] = t0 + t2;
-    v[1] = t1 + t3;
-    v[2] = t0 - t2;
-    v[3] = t1 - t3;
-  } else if constexpr (R == 3) {
-    const Rt c = Rt(-0.5), dd = Rt(DIR) * Rt(0.86602540378443864676);
-    const V2 t1 = v[1] + v[2], t2 = v[1] - v[2];
-    const V2 m = v[0] + t1 * c;
-    const V2 n = {-dd * t2.y, dd * t2.x};
-    v[0] = v[0] + t1;
-    v[1] = m + n;
-    v[2] = m - n;
-  }
-}
 
 constexpr int pitch(int L) { return L + 1; }
 

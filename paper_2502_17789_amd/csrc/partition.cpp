@@ -386,13 +386,37 @@ std::vector<aidg_subgrid> split_large(const std::vector<aidg_subgrid>& t, int ma
   return out;
 }
 
-void kaiser_bessel_taper(int L, double beta, std::vector<double>* T) {
-  std::vector<double> t(L);
+// One axis of the Kaiser-Bessel taper sampled at n points: f = (x - n/2) / n,
+// t[x] = I0(beta sqrt(1 - (2 f)^2)) / I0(beta).  The subgrid taper takes n = L,
+// the image-level correction n = N (the same function at a finer sampling).
+void kaiser_bessel_axis(int n, double beta, std::vector<double>* t) {
+  t->resize(n);
   const double i0b = std::cyl_bessel_i(0.0, beta);
-  for (int x = 0; x < L; ++x) {
-    const double f = double(x - L / 2) / L;
-    t[x] = std::cyl_bessel_i(0.0, beta * std::sqrt(std::max(0.0, 1.0 - 4.0 * f * f))) / i0b;
+  for (int x = 0; x < n; ++x) {
+    const double f = double(x - n / 2) / n;
+    (*t)[x] = std::cyl_bessel_i(0.0, beta * std::sqrt(std::max(0.0, 1.0 - 4.0 * f * f))) / i0b;
   }
+}
+
+bool image_radices(int N, int elem_bytes, ImageRadices* out) {
+  if (N < 2 || N > kMaxImageN || (int64_t)N * elem_bytes > kMaxImageRowBytes) return false;
+  ImageRadices r{};
+  int n = N;
+  for (int radix : {4, 2, 3, 5}) {
+    while (n % radix == 0) {
+      if (r.n == kMaxImageRadices) return false;
+      r.r[r.n++] = radix;
+      n /= radix;
+    }
+  }
+  if (n != 1) return false;
+  *out = r;
+  return true;
+}
+
+void kaiser_bessel_taper(int L, double beta, std::vector<double>* T) {
+  std::vector<double> t;
+  kaiser_bessel_axis(L, beta, &t);
   T->resize((size_t)L * L);
   for (int y = 0; y < L; ++y)
     for (int x = 0; x < L; ++x) (*T)[(size_t)y * L + x] = t[x] * t[y];

@@ -1,0 +1,158 @@
+"""GPU parity of the image-level step (w-stacking, Eq. wstack; its inverse for
+prediction, Eq. wunstack) through the C ABI, against the FP64 oracle.
+
+Bar (normwise relative error per result): FP32 <= 1e-5, FP64 <= 1e-10.
+  * aidg_invert / aidg_predict against oracle.invert / oracle.predict on random
+    grids and images, over N whose FFTs take every radix (4, 2, 3, 5) and several
+    w-layers;
+  * the adjoint identity <invert(G), I> = <G, predict(I)> on GPU outputs;
+  * end to end through the library's own partition: invert(grid(V)) at subgrid-
+    lattice pixels equals the direct A-term image of the gridded visibilities, and
+    degrid(predict(I)) of point sources on lattice pixels equals their direct
+    prediction (Eq. 1);
+  * an N whose row FFT the library does not implement is refused.
+"""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def aidg():
+    import paper_2502_17789_amd as m
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    m.library()
+    return m
+
+
+def rel(a, b):
+    a = np.asarray(a, np.complex128)
+    b = np.asarray(b, np.complex128)
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def dev(x, prec):
+    dt = np.complex64 if prec == 0 else np.complex128
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=dt)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().astype(np.complex128)
+
+
+def plan_for(aidg, wl, precision=0, w_step=0.0):
+    geo = aidg.Geometry(wl.grid_size, wl.subgrid_size, wl.kernel_support, wl.pixel_scale,
+                        aterm_interval=wl.aterm_interval, precision=precision, w_step=w_step)
+    return aidg.Plan(geo, wl.n_stations, wl.baselines, wl.uvw, wl.freqs, dev(wl.aterms, precision))
+
+
+# N = 128: radices 4 4 4 2; N = 480: 4 4 2 3 5; N = 250: 2 5 5 5; N = 384: 4 4 4 2 3
+CASES = {
+    "N128": dict(seed=201, N=128, L=32, K=8, w_step=12.0),
+    "N480": dict(seed=202, N=480, L=32, K=8, w_step=15.0),
+    "N250": dict(seed=203, N=250, L=32, K=8, fov_deg=12.0, w_step=6.0),
+    "N384": dict(seed=204, N=384, L=96, K=24, n_c=12, fov_deg=12.0, diameter_m=1500.0, w_step=0.0),
+}
+TOL = {0: 1e-5, 1: 1e-10}
+
+
+def case(name):
+    c = dict(CASES[name])
+    w_step = c.pop("w_step")
+    return synth.config_tiny(**c), w_step
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_invert_and_predict_match_oracle(aidg, orc, name, precision):
+    wl, w_step = case(name)
+    with plan_for(aidg, wl, precision, w_step) as p:
+        w0 = p.wlayers()
+        rng = np.random.default_rng(7)
+        N, L, K = wl.grid_size, wl.subgrid_size, wl.kernel_support
+        G = synth.random_grid(p.n_wlayers, N, rng)
+        I = rng.standard_normal((4, N, N)) + 1j * rng.standard_normal((4, N, N))
+        Ig = host(p.invert(dev(G, precision)))
+        Gg = host(p.predict(dev(I, precision)))
+        ei = rel(Ig, orc.invert(G, w0, L, K, wl.pixel_scale))
+        ep = rel(Gg, orc.predict(I, w0, L, K, wl.pixel_scale))
+        print(f"{name} {'FP64' if precision else 'FP32'} W={p.n_wlayers}: invert {ei:.2e} predict {ep:.2e}",
+              flush=True)
+        assert ei <= TOL[precision] and ep <= TOL[precision]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_image_adjoint_identity_on_gpu(aidg, precision):
+    wl, w_step = case("N480")
+    with plan_for(aidg, wl, precision, w_step) as p:
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(3)
+        dt = torch.complex64 if precision == 0 else torch.complex128
+        G = torch.randn(p.grid_shape(), dtype=dt, device="cuda", generator=gen)
+        I = torch.randn(p.image_shape(), dtype=dt, device="cuda", generator=gen)
+        IG = p.invert(G)
+        GI = p.predict(I)
+        torch.cuda.synchronize()
+        c = torch.complex128
+        lhs = torch.vdot(IG.flatten().to(c), I.flatten().to(c)).item()
+        rhs = torch.vdot(G.flatten().to(c), GI.flatten().to(c)).item()
+        scale = (IG.to(c).norm() * I.to(c).norm() + G.to(c).norm() * GI.to(c).norm()).item()
+        assert abs(lhs - rhs) <= TOL[precision] * scale
+
+
+def lattice_pixels(wl, rng, n):
+    N, L = wl.grid_size, wl.subgrid_size
+    xs = rng.integers(1, L, n).astype(np.int32)
+    ys = rng.integers(1, L, n).astype(np.int32)
+    return xs, ys, N // 2 + (xs - L // 2) * (N // L), N // 2 + (ys - L // 2) * (N // L)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_invert_of_gridded_visibilities_is_the_direct_image(aidg, orc, precision):
+    wl, w_step = case("N480")
+    rng = np.random.default_rng(11)
+    V = synth.random_vis((wl.n_baselines, wl.n_times, wl.n_chans), rng)
+    with plan_for(aidg, wl, precision, w_step) as p:
+        assert p.n_wlayers >= 2
+        I = host(p.invert(p.grid(dev(V, precision))))
+        table = p.subgrids()
+    xs, ys, X, Y = lattice_pixels(wl, rng, 80)
+    l, m = orc.lattice_dirs(wl, xs, ys)
+    ref = orc.direct_image(wl, V, l, m, xs, ys, mask=orc.coverage_mask(wl, table))
+    err = rel(I[:, Y, X].T, ref)
+    print(f"invert(grid(V)) at lattice pixels vs direct image: {err:.2e}", flush=True)
+    assert err <= TOL[precision]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_degrid_of_predicted_lattice_sources_is_the_direct_prediction(aidg, orc, precision):
+    wl, w_step = case("N480")
+    N, L = wl.grid_size, wl.subgrid_size
+    rng = np.random.default_rng(12)
+    src = synth.point_sources(5, wl.fov, 0.5, 5.0, rng, L=L, on_lattice=True)
+    I = np.zeros((4, N, N), np.complex128)
+    for s in range(5):
+        I[:, N // 2 + (src["ys"][s] - L // 2) * (N // L), N // 2 + (src["xs"][s] - L // 2) * (N // L)] += src["B"][s]
+    with plan_for(aidg, wl, precision, w_step) as p:
+        V = host(p.degrid(p.predict(dev(I, precision))))
+        table = p.subgrids()
+    Vd = orc.direct_predict(wl, src["l"], src["m"], src["B"], src["xs"], src["ys"])
+    mask = orc.coverage_mask(wl, table).astype(bool)
+    assert mask.sum() > 0.8 * mask.size
+    err = rel(V[mask], Vd[mask])
+    print(f"degrid(predict(I)) vs direct prediction: {err:.2e}", flush=True)
+    assert err <= TOL[precision]
+
+
+def test_unsupported_image_size_is_refused(aidg):
+    wl = synth.config_tiny(205, N=126, L=32, K=8)  # 126 = 2 x 3^2 x 7
+    with plan_for(aidg, wl) as p:
+        G = torch.zeros(p.grid_shape(), dtype=torch.complex64, device="cuda")
+        with pytest.raises(RuntimeError, match="2\\^a 3\\^b 5\\^c"):
+            p.invert(G)
