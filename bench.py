@@ -101,6 +101,10 @@ def parse():
     ap.add_argument("--lattice-cases", type=lambda t: tuple(int(x) for x in t.split(":")), nargs="*",
                     default=[], help="extra FP32 kernel-sweep cases L:lattice (centre lattice step)")
     ap.add_argument("--lattice-only", action="store_true", help="kernel sweep: only the --lattice-cases")
+    ap.add_argument("--image", action="store_true",
+                    help="image-level w-stacking (invert and predict) at the MWA-like size, FP32, at "
+                         "max |w| of --image-wmax wavelengths (JSON line per case)")
+    ap.add_argument("--image-wmax", type=float, nargs="+", default=[0.0, 250.0])
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device-to-device 3 times (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -393,6 +397,69 @@ def kernel_sweep(args):
             torch.cuda.empty_cache()
 
 
+def image_bench(args):
+    """Image-level w-stacking (Eq. wstack) and its inverse (Eq. wunstack) on the
+    MWA-like grid (N = 8000, the plan's w-layers), FP32: aidg_invert and aidg_predict
+    timed with HIP events around every launch.  Each kernel class's effective
+    bandwidth is the bytes its launches read and write (one N x N plane in and one
+    out per row-FFT pass or transpose; the w-stacking pass also reads the image it
+    adds to) over their time."""
+    import torch
+
+    import paper_2502_17789_amd as aidg
+    import synth
+
+    torch.cuda.set_device(0)
+    for wmax in args.image_wmax:
+        ha = synth.hour_angle_for_wmax(wmax) if wmax > 0 else 0.0
+        wl = synth.config_mwa(seed=2, ha0_rad=ha)
+        geo = aidg.Geometry(wl.grid_size, wl.subgrid_size, wl.kernel_support, wl.pixel_scale,
+                            aterm_interval=wl.aterm_interval)
+        A = torch.from_numpy(wl.aterms.astype(np.complex64)).cuda()
+        with aidg.Plan(geo, wl.n_stations, wl.baselines, wl.uvw, wl.freqs, A) as plan:
+            del A
+            W, N = plan.n_wlayers, wl.grid_size
+            gen = torch.Generator(device="cuda")
+            gen.manual_seed(4)
+            G = torch.randn(plan.grid_shape(), dtype=torch.complex64, device="cuda", generator=gen)
+            I = torch.randn(plan.image_shape(), dtype=torch.complex64, device="cuda", generator=gen)
+            Io = torch.empty_like(I)
+            Go = torch.empty_like(G)
+            plan.invert(G, Io)
+            plan.predict(I, Go)
+            torch.cuda.synchronize()
+            plan.set_profiling(True)
+            reps = 3
+            stream = torch.cuda.current_stream()
+            ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(reps)]
+            for r in range(reps):
+                ev[r][0].record(stream)
+                plan.invert(G, Io)
+                ev[r][1].record(stream)
+                plan.predict(I, Go)
+                ev[r][2].record(stream)
+            torch.cuda.synchronize()
+            kt = plan.kernel_times()
+            t_inv = float(np.median([e[0].elapsed_time(e[1]) for e in ev]))
+            t_pred = float(np.median([e[1].elapsed_time(e[2]) for e in ev]))
+            del G, I, Io, Go
+        P = N * N * 8
+        by = {"image_fft": reps * 16 * W * 2 * P,
+              "image_wstack": reps * ((4 * W * 2 + 4 * 2 + 4 * (W - 1) * 3) + 8 * W * 2) * P}
+        cls = {k: {"ms_per_launch": round(kt[k]["ms"] / max(kt[k]["launches"], 1), 4),
+                   "launches_per_call_pair": kt[k]["launches"] // reps,
+                   "gb_s": round(by[k] / (kt[k]["ms"] * 1e-3) / 1e9, 1)} for k in by}
+        dom = max(by, key=lambda k: kt[k]["ms"])
+        print(json.dumps({
+            "image_level": {"grid_size": N, "n_wlayers": W, "max_abs_w_lambda": wmax or "transit",
+                            "precision": "fp32", "plane_bytes": P},
+            "invert_ms": round(t_inv, 3), "predict_ms": round(t_pred, 3),
+            "classes": cls,
+            "roofline": {"kernel": dom, "bound": "hbm", "achieved": cls[dom]["gb_s"], "peak": 8000.0,
+                         "unit": "GB/s", "frac": round(cls[dom]["gb_s"] / 8000.0, 4)}}), flush=True)
+        torch.cuda.empty_cache()
+
+
 def dataclasses_replace(obj, **kw):
     import dataclasses
     return dataclasses.replace(obj, **kw)
@@ -413,7 +480,7 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (the design "
+        print("bench.py measures one GPU only: the library has no multi-GPU path (the design "
               "would shard baselines across GPUs and all-reduce the grid); run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
@@ -426,6 +493,9 @@ def main():
         return
     if args.kernel_sweep:
         kernel_sweep(args)
+        return
+    if args.image:
+        image_bench(args)
         return
     if args.copy_probe:
         import torch

@@ -1,4 +1,4 @@
-"""bench.py on the CPU: it refuses more than one GPU (this build has no multi-GPU
+"""bench.py on the CPU: it refuses more than one GPU (the library has no multi-GPU
 path) before touching a device, and the source hash that ties stored HBM counters
 to the library ignores comments."""
 import os
