@@ -20,14 +20,10 @@ __device__ __forceinline__ typename C2<R>::T cmul(typename C2<R>::T a, typename 
   return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
 }
 
-// exp(2 pi i theta) for a phase theta in turns, FP32 result.  The quarter-turn
-// reduction happens in FP64 (theta = q/4 + t, |t| <= 1/8, exact), t is rounded
-// once to FP32, and sin/cos(2 pi t) come from their Taylor series to degree 9
-// and 10 (truncation < 2e-9 for |2 pi t| <= pi/4), evaluated by Horner in FP32.
-__device__ __forceinline__ float2 phasor(double theta, float) {
-  const double q = rint(4.0 * theta);
-  const float t = (float)fma(q, -0.25, theta);
-  const int qi = (int)q;  // |theta| is bounded by the grid size in turns
+// exp(2 pi i (t + qi / 4)) for |t| <= 1/8 turn, FP32: sin/cos(2 pi t) from their
+// Taylor series to degree 9 and 10 (truncation < 2e-9 for |2 pi t| <= pi/4),
+// evaluated by Horner in FP32, then a rotation by qi quarter turns.
+__device__ __forceinline__ float2 phasor_quarter(float t, int qi) {
   const float t2 = t * t;
   float s = fmaf(t2, 42.058693944897634f, -76.70585975306136f);
   s = fmaf(t2, s, 81.60524927607504f);
@@ -45,6 +41,15 @@ __device__ __forceinline__ float2 phasor(double theta, float) {
   const float cc = odd ? s : c, ss = odd ? c : s;
   const unsigned sign_c = ((unsigned)(qi + 1) << 30) & 0x80000000u, sign_s = ((unsigned)qi << 30) & 0x80000000u;
   return {__uint_as_float(__float_as_uint(cc) ^ sign_c), __uint_as_float(__float_as_uint(ss) ^ sign_s)};
+}
+
+// exp(2 pi i theta) for a phase theta in turns, FP32 result.  The quarter-turn
+// reduction happens in FP64 (theta = q/4 + t, |t| <= 1/8, exact) and t is rounded
+// once to FP32.
+__device__ __forceinline__ float2 phasor(double theta, float) {
+  const double q = rint(4.0 * theta);
+  const float t = (float)fma(q, -0.25, theta);
+  return phasor_quarter(t, (int)q);  // |theta| is bounded by the grid size in turns
 }
 
 // FP64 variant: reduction to [-1/2, 1/2] and the device library's sincospi.

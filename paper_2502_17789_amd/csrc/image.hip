@@ -3,8 +3,9 @@
 // step 2).  A centred N x N transform is two passes of one-dimensional FFTs along
 // rows with a tiled transpose between them:
 //   image_fft_rows  one workgroup per row: the row is read into LDS times (-1)^x,
-//                   transformed by mixed-radix Stockham passes (radix 4/2/3/5,
-//                   twiddles from a table), and written back times (-1)^k.  The
+//                   transformed by mixed-radix Stockham passes (radix 4/2/3/5;
+//                   FP32 twiddles computed, FP64 ones from a table), and written
+//                   back times (-1)^k.  The
 //                   prediction variant first multiplies each image value by
 //                   exp(-2 pi i w0 n1) / (L^2 T).
 //   image_transpose 32 x 32 tiles through LDS.
@@ -15,6 +16,8 @@
 // sign cancels between the two passes of a plane.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "aidg_internal.h"
 #include "device_common.h"
 
@@ -24,15 +27,28 @@ namespace {
 constexpr int kFftThreads = 1024;
 constexpr int kTile = 32;
 
+// exp(-2 pi i a / M) for integers 0 <= a < M <= 8192, FP32, without a table (a
+// table read would expose a global-memory latency in every pass): the nearest
+// quarter turn q comes from an FP32 quotient (a near-tie leaves |t| a hair above
+// 1/8, where the polynomials are still accurate), the remainder 4a - qM is exact in
+// integers and is scaled once.
+__device__ __forceinline__ float2 root_of_unity(int a, int M, float inv_m) {
+  const int q = (int)rintf(4.0f * (float)a * inv_m);
+  const float2 p = phasor_quarter((float)(4 * a - q * M) * (0.25f * inv_m), q);
+  return {p.x, -p.y};
+}
+
 // One Stockham pass of radix R over the row held in LDS (Ls = product of the
 // earlier radices): butterfly j < N/R reads buf[j + i N/R], multiplies input i by
 // exp(DIR 2 pi i k i / (Ls R)) with k = j mod Ls, and writes its outputs to
 // buf[(j / Ls) Ls R + k + i Ls].  In place: every read, a barrier, every write.
+// FP32 twiddles are computed (root_of_unity); FP64 ones come from the table.
 template <int R, int DIR, typename V2>
 __device__ __forceinline__ void row_pass(V2* buf, int N, int Ls, const V2* __restrict__ tw) {
   using Rt = decltype(V2{}.x);
   constexpr int MAXB = (kMaxImageN / R + kFftThreads - 1) / kFftThreads;
-  const int m = N / R, tstep = N / (Ls * R);
+  const int m = N / R, tstep = N / (Ls * R), M = Ls * R;
+  const float inv_m = 1.0f / (float)M;
   V2 y[MAXB][R];
 #pragma unroll
   for (int b = 0; b < MAXB; ++b) {
@@ -43,7 +59,11 @@ __device__ __forceinline__ void row_pass(V2* buf, int N, int Ls, const V2* __res
       for (int i = 0; i < R; ++i) y[b][i] = buf[j + i * m];
 #pragma unroll
       for (int i = 1; i < R; ++i) {
-        V2 w = tw[k * i * tstep];  // exp(-2 pi i k i / (Ls R))
+        V2 w;  // exp(-2 pi i k i / (Ls R))
+        if constexpr (std::is_same_v<Rt, float>)
+          w = root_of_unity(k * i, M, inv_m);
+        else
+          w = tw[k * i * tstep];
         if (DIR > 0) w.y = -w.y;
         y[b][i] = cmul<Rt>(y[b][i], w);
       }
