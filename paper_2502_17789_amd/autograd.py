@@ -9,6 +9,12 @@ product with an incoming gradient g is M^H g, so
 each computed by the other hand-written kernel chain on the current stream.
 Visibilities that belong to no subgrid are ignored by gridding and set to zero
 by degridding, which keeps the pair adjoint.
+
+The image level pairs the same way: prediction G = P(I) (Eq. wunstack) is the exact
+adjoint of imaging I = P^H(G) (Eq. wstack), so
+    PredictFn.backward(gG) = invert(gG)    InvertFn.backward(gI) = predict(gI),
+and ``predict_vis`` (image -> visibilities, degrid after predict) is differentiable
+end to end.
 """
 from __future__ import annotations
 
@@ -55,3 +61,48 @@ def degrid(grid: torch.Tensor, plan) -> torch.Tensor:
 
 def grid(vis: torch.Tensor, plan) -> torch.Tensor:
     return GridFn.apply(vis, plan)
+
+
+class PredictFn(torch.autograd.Function):
+    """G = predict(I): image [4, N, N] -> grid layers [W, 4, N, N]."""
+
+    @staticmethod
+    def forward(ctx, image: torch.Tensor, plan) -> torch.Tensor:
+        ctx.plan = plan
+        return plan.predict(image.contiguous())
+
+    @staticmethod
+    def backward(ctx, g_grid: torch.Tensor):
+        g_image = None
+        if ctx.needs_input_grad[0]:
+            g_image = ctx.plan.invert(g_grid.contiguous())
+        return g_image, None
+
+
+class InvertFn(torch.autograd.Function):
+    """I = invert(G): grid layers [W, 4, N, N] -> image [4, N, N]."""
+
+    @staticmethod
+    def forward(ctx, grid: torch.Tensor, plan) -> torch.Tensor:
+        ctx.plan = plan
+        return plan.invert(grid.contiguous())
+
+    @staticmethod
+    def backward(ctx, g_image: torch.Tensor):
+        g_grid = None
+        if ctx.needs_input_grad[0]:
+            g_grid = ctx.plan.predict(g_image.contiguous())
+        return g_grid, None
+
+
+def predict(image: torch.Tensor, plan) -> torch.Tensor:
+    return PredictFn.apply(image, plan)
+
+
+def invert(grid: torch.Tensor, plan) -> torch.Tensor:
+    return InvertFn.apply(grid, plan)
+
+
+def predict_vis(image: torch.Tensor, plan) -> torch.Tensor:
+    """Visibilities of an image: degridding of its predicted grid layers."""
+    return DegridFn.apply(PredictFn.apply(image, plan), plan)

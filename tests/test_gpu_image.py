@@ -156,3 +156,69 @@ def test_unsupported_image_size_is_refused(aidg):
         G = torch.zeros(p.grid_shape(), dtype=torch.complex64, device="cuda")
         with pytest.raises(RuntimeError, match="2\\^a 3\\^b 5\\^c"):
             p.invert(G)
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_image_to_visibilities_gradient(aidg, precision):
+    """Loss Re sum conj(R) degrid(predict(I)) through autograd (backward: grid, then
+    invert) against central finite differences at 40 image pixels of the inner half
+    of the field.  The loss is linear in I, so the difference has no truncation
+    error and a large step (1e3 against unit-variance pixels) keeps the rounding of
+    the two loss evaluations small beside the change; errors are measured against
+    the RMS gradient over the probes.  FP64: bound 1e-6; FP32: median <= 1e-2,
+    max <= 5e-2."""
+    from paper_2502_17789_amd import autograd
+    wl, w_step = case("N480")
+    N = wl.grid_size
+    dt = torch.complex64 if precision == 0 else torch.complex128
+    with plan_for(aidg, wl, precision, w_step) as p:
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(5)
+        I = torch.randn(p.image_shape(), dtype=dt, device="cuda", generator=gen).requires_grad_(True)
+        Rv = torch.randn(p.vis_shape(), dtype=dt, device="cuda", generator=gen)
+
+        def loss(img):
+            return torch.real(torch.vdot(Rv.flatten(), autograd.predict_vis(img, p).flatten())).to(torch.float64)
+
+        L0 = loss(I)
+        L0.backward()
+        grad = I.grad.detach().clone()
+        rng = np.random.default_rng(6)
+        probes = [(int(rng.integers(4)), int(rng.integers(N // 4, 3 * N // 4)), int(rng.integers(N // 4, 3 * N // 4)))
+                  for _ in range(40)]
+        h = 1e3
+        errs, gs = [], []
+        with torch.no_grad():
+            for pol, y, x in probes:
+                fd = []
+                for unit in (1.0, 1.0j):
+                    Ip = I.detach().clone()
+                    Im = I.detach().clone()
+                    Ip[pol, y, x] += h * unit
+                    Im[pol, y, x] -= h * unit
+                    fd.append((loss(Ip) - loss(Im)).item() / (2 * h))
+                g = complex(grad[pol, y, x].item())
+                errs.append(abs(complex(fd[0], fd[1]) - g))
+                gs.append(abs(g))
+        rms = float(np.sqrt(np.mean(np.square(gs))))
+        e = np.array(errs) / rms
+        print(f"{'FP64' if precision else 'FP32'} image->vis gradient: max {e.max():.2e} median {np.median(e):.2e}",
+              flush=True)
+        if precision:
+            assert e.max() <= 1e-6
+        else:
+            assert np.median(e) <= 1e-2 and e.max() <= 5e-2
+
+
+def test_invert_autograd_is_the_adjoint(aidg):
+    """<invert(G), J> through autograd: its gradient with respect to G is predict(J)."""
+    from paper_2502_17789_amd import autograd
+    wl, w_step = case("N128")
+    with plan_for(aidg, wl, 1, w_step) as p:
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(8)
+        G = torch.randn(p.grid_shape(), dtype=torch.complex128, device="cuda", generator=gen).requires_grad_(True)
+        J = torch.randn(p.image_shape(), dtype=torch.complex128, device="cuda", generator=gen)
+        torch.real(torch.vdot(J.flatten(), autograd.invert(G, p).flatten())).backward()
+        ref = p.predict(J)
+        assert rel(host(G.grad), host(ref)) <= 1e-12
