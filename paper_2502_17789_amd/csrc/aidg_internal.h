@@ -118,7 +118,8 @@ struct ImageRadices {
   int32_t n;                     // number of Stockham passes
   int32_t r[kMaxImageRadices];   // radix of each pass
 };
-// Factorisation of N in pass order (4s first); false when N is not supported.
+// Factorisation of N in pass order (5s, 3s, then 4s and a 2); false when N is not
+// supported.
 bool image_radices(int N, int elem_bytes, ImageRadices* out);
 void kaiser_bessel_axis(int n, double beta, std::vector<double>* t);
 int launch_image_fft_rows(int precision, int dir, bool predict, const void* src, void* dst, int N,

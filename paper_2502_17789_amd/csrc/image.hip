@@ -48,24 +48,31 @@ __device__ __forceinline__ void row_pass(V2* buf, int N, int Ls, const V2* __res
   using Rt = decltype(V2{}.x);
   constexpr int MAXB = (kMaxImageN / R + kFftThreads - 1) / kFftThreads;
   const int m = N / R, tstep = N / (Ls * R), M = Ls * R;
-  const float inv_m = 1.0f / (float)M;
+  const float inv_m = 1.0f / (float)M, inv_ls = 1.0f / (float)Ls;
   V2 y[MAXB][R];
+  int kk[MAXB], gg[MAXB];
 #pragma unroll
   for (int b = 0; b < MAXB; ++b) {
     const int j = threadIdx.x + b * kFftThreads;
     if (j < m) {
-      const int k = j % Ls;
+      // j / Ls from an FP32 quotient: (j + 1/2) / Ls is at least 1/(2 Ls) away from an
+      // integer, far beyond the rounding for j < 8192 (checked exhaustively)
+      const int g = (int)(((float)j + 0.5f) * inv_ls), k = j - g * Ls;
+      gg[b] = g;
+      kk[b] = k;
 #pragma unroll
       for (int i = 0; i < R; ++i) y[b][i] = buf[j + i * m];
+      if (Ls > 1) {  // the first pass has unit twiddles
 #pragma unroll
-      for (int i = 1; i < R; ++i) {
-        V2 w;  // exp(-2 pi i k i / (Ls R))
-        if constexpr (std::is_same_v<Rt, float>)
-          w = root_of_unity(k * i, M, inv_m);
-        else
-          w = tw[k * i * tstep];
-        if (DIR > 0) w.y = -w.y;
-        y[b][i] = cmul<Rt>(y[b][i], w);
+        for (int i = 1; i < R; ++i) {
+          V2 w;  // exp(-2 pi i k i / (Ls R))
+          if constexpr (std::is_same_v<Rt, float>)
+            w = root_of_unity(k * i, M, inv_m);
+          else
+            w = tw[k * i * tstep];
+          if (DIR > 0) w.y = -w.y;
+          y[b][i] = cmul<Rt>(y[b][i], w);
+        }
       }
       butterfly<V2, R, DIR>(y[b]);
     }
@@ -75,7 +82,7 @@ __device__ __forceinline__ void row_pass(V2* buf, int N, int Ls, const V2* __res
   for (int b = 0; b < MAXB; ++b) {
     const int j = threadIdx.x + b * kFftThreads;
     if (j < m) {
-      const int k = j % Ls, base = (j / Ls) * Ls * R + k;
+      const int k = kk[b], base = gg[b] * Ls * R + k;
 #pragma unroll
       for (int i = 0; i < R; ++i) buf[base + i * Ls] = y[b][i];
     }

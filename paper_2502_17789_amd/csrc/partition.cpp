@@ -402,7 +402,9 @@ bool image_radices(int N, int elem_bytes, ImageRadices* out) {
   if (N < 2 || N > kMaxImageN || (int64_t)N * elem_bytes > kMaxImageRowBytes) return false;
   ImageRadices r{};
   int n = N;
-  for (int radix : {4, 2, 3, 5}) {
+  // odd radices first: their lane strides spread the early passes' strided LDS writes
+  // over the banks, where a stride of 4 complex values would conflict
+  for (int radix : {5, 3, 4, 2}) {
     while (n % radix == 0) {
       if (r.n == kMaxImageRadices) return false;
       r.r[r.n++] = radix;
