@@ -123,10 +123,10 @@ struct ImageRadices {
 bool image_radices(int N, int elem_bytes, ImageRadices* out);
 void kaiser_bessel_axis(int n, double beta, std::vector<double>* t);
 int launch_image_fft_rows(int precision, int dir, bool predict, const void* src, void* dst, int N,
-                          const ImageRadices& fr, const void* tw, const double* taper, double dl,
+                          const ImageRadices& fr, const void* tw, const double* itaper, double dl,
                           double w0, double inv_l2, void* stream);
 int launch_image_transpose(int precision, const void* src, void* dst, int N, void* stream);
-int launch_image_wstack(int precision, const void* B, void* img, int N, const double* taper, double dl,
+int launch_image_wstack(int precision, const void* B, void* img, int N, const double* itaper, double dl,
                         double w0, double inv_l2, int assign, void* stream);
 
 }  // namespace aidg

@@ -78,11 +78,12 @@ struct aidg_plan {
   int64_t* d_grp = nullptr;
   KernelArgs* d_args = nullptr;  // device copy of args()
   // image level (invert / predict): Stockham radices of N, twiddles exp(-2 pi i k / N)
-  // and the taper's axis at image resolution (FP64); absent when N is not supported
+  // and the reciprocal of the taper's axis at image resolution (FP64); absent when N
+  // is not supported
   ImageRadices img_fr{};
   bool img_ok = false;
   void* d_img_tw = nullptr;
-  double* d_img_taper = nullptr;
+  double* d_img_itaper = nullptr;
   hipEvent_t last = nullptr;
   std::atomic<bool> busy{false};
   // profiling: events around each kernel launch
@@ -123,7 +124,7 @@ struct aidg_plan {
 
   void release() {
     void* ptrs[] = {d_sg,      d_uvw,  d_fc,   d_aterms, d_taper,  d_tw,
-                    d_scratch, d_excl, d_grp,  d_args,   d_img_tw, d_img_taper};
+                    d_scratch, d_excl, d_grp,  d_args,   d_img_tw, d_img_itaper};
     hipStream_t fs = async_mem ? release_stream(device) : nullptr;
     int cur = device;
     if (fs) {
@@ -150,7 +151,7 @@ struct aidg_plan {
     d_grp = nullptr;
     d_args = nullptr;
     d_img_tw = nullptr;
-    d_img_taper = nullptr;
+    d_img_itaper = nullptr;
     last = nullptr;
   }
 };
@@ -467,11 +468,13 @@ aidg_status aidg_plan_create(const aidg_geometry* geo, int32_t n_stations, int32
     }
     const bool f32 = g.precision == AIDG_FP32;
     std::vector<float> Tf(T.begin(), T.end()), twf(tw.begin(), tw.end());
-    // image level: twiddles exp(-2 pi i k / N) and the taper axis t[X] at image resolution
+    // image level: twiddles exp(-2 pi i k / N) and the reciprocal 1 / t[X] of the taper
+    // axis at image resolution
     std::vector<double> img_t, img_tw;
     plan->img_ok = image_radices(g.N, (int)plan->elem, &plan->img_fr);
     if (plan->img_ok) {
       kaiser_bessel_axis(g.N, g.beta, &img_t);
+      for (double& v : img_t) v = 1.0 / v;
       img_tw.resize(2 * (size_t)g.N);
       for (int k = 0; k < g.N; ++k) {
         const double ang = -2.0 * M_PI * k / g.N;
@@ -521,7 +524,7 @@ aidg_status aidg_plan_create(const aidg_geometry* geo, int32_t n_stations, int32
         (st = dalloc(&plan->d_args, sizeof(KernelArgs), plan, "launch parameters", stream)) ||
         (plan->img_ok &&
          ((st = dalloc(&plan->d_img_tw, (size_t)g.N * plan->elem, plan, "image twiddles", stream)) ||
-          (st = dalloc(&plan->d_img_taper, (size_t)g.N * sizeof(double), plan, "image taper", stream))))) {
+          (st = dalloc(&plan->d_img_itaper, (size_t)g.N * sizeof(double), plan, "image taper", stream))))) {
       abandon();
       return st;
     }
@@ -545,7 +548,7 @@ aidg_status aidg_plan_create(const aidg_geometry* geo, int32_t n_stations, int32
         {plan->d_args, &host_args, sizeof(KernelArgs), hipMemcpyHostToDevice},
         {plan->d_img_tw, f32 ? (const void*)img_twf.data() : (const void*)img_tw.data(),
          plan->img_ok ? (size_t)g.N * plan->elem : 0, hipMemcpyHostToDevice},
-        {plan->d_img_taper, img_t.data(), plan->img_ok ? (size_t)g.N * sizeof(double) : 0,
+        {plan->d_img_itaper, img_t.data(), plan->img_ok ? (size_t)g.N * sizeof(double) : 0,
          hipMemcpyHostToDevice},
     };
     for (const Copy& c : copies) {
@@ -685,18 +688,18 @@ aidg_status aidg_invert(aidg_plan* plan, const void* grid, void* image, void* wo
       // rows: G[gv][gu] -> A[gv][X]; transpose -> B[X][gv]; rows -> B[X][Y]; add into img[Y][X]
       r = image_step(plan, st, kImageFft, [&] {
         return launch_image_fft_rows(prec, +1, false, G, A, N, plan->img_fr, plan->d_img_tw,
-                                     plan->d_img_taper, dl, 0.0, inv_l2, st);
+                                     plan->d_img_itaper, dl, 0.0, inv_l2, st);
       });
       if (r == AIDG_OK)
         r = image_step(plan, st, kImageWstack, [&] { return launch_image_transpose(prec, A, B, N, st); });
       if (r == AIDG_OK)
         r = image_step(plan, st, kImageFft, [&] {
           return launch_image_fft_rows(prec, +1, false, B, B, N, plan->img_fr, plan->d_img_tw,
-                                       plan->d_img_taper, dl, 0.0, inv_l2, st);
+                                       plan->d_img_itaper, dl, 0.0, inv_l2, st);
         });
       if (r == AIDG_OK)
         r = image_step(plan, st, kImageWstack, [&] {
-          return launch_image_wstack(prec, B, img, N, plan->d_img_taper, dl, plan->w0[w], inv_l2, w == 0, st);
+          return launch_image_wstack(prec, B, img, N, plan->d_img_itaper, dl, plan->w0[w], inv_l2, w == 0, st);
         });
     }
   }
@@ -727,14 +730,14 @@ aidg_status aidg_predict(aidg_plan* plan, const void* image, void* grid, void* w
       // rows -> B[gu][gv]; transpose -> G[gv][gu]
       r = image_step(plan, st, kImageFft, [&] {
         return launch_image_fft_rows(prec, -1, true, img, A, N, plan->img_fr, plan->d_img_tw,
-                                     plan->d_img_taper, dl, plan->w0[w], inv_l2, st);
+                                     plan->d_img_itaper, dl, plan->w0[w], inv_l2, st);
       });
       if (r == AIDG_OK)
         r = image_step(plan, st, kImageWstack, [&] { return launch_image_transpose(prec, A, B, N, st); });
       if (r == AIDG_OK)
         r = image_step(plan, st, kImageFft, [&] {
           return launch_image_fft_rows(prec, -1, false, B, B, N, plan->img_fr, plan->d_img_tw,
-                                       plan->d_img_taper, dl, 0.0, inv_l2, st);
+                                       plan->d_img_itaper, dl, 0.0, inv_l2, st);
         });
       if (r == AIDG_OK)
         r = image_step(plan, st, kImageWstack, [&] { return launch_image_transpose(prec, B, G, N, st); });

@@ -103,16 +103,27 @@ __device__ __forceinline__ void row_fft(V2* buf, const ImageRadices& fr, int N, 
   }
 }
 
-// exp(sign 2 pi i w0 n1(X, Y)) / (L^2 T(X, Y)) at image pixel (X, Y):
-// l = (X - N/2) dl, m = (Y - N/2) dl, n1 = -r^2 / (1 + sqrt(1 - r^2)).
+// exp(sign 2 pi i w0 n1(X, Y)) / (L^2 T(X, Y)) at image pixel (X, Y), with
+// l = (X - N/2) dl, m = (Y - N/2) dl and itaper[X] = 1 / t(X).  FP32 path: n1 = s - 1
+// with s = sqrt(1 - l^2 - m^2) from an FP32 square root and one FP64 residual
+// correction (s to about 1e-15, so w0 n1 keeps ~1e-12 turns, far below the FP32
+// phasor's own rounding).  FP64 path: the cancellation-free -r^2 / (1 + s) in FP64.
 template <typename R>
 __device__ __forceinline__ typename C2<R>::T wterm(int X, int Y, int N, double dl, double w0,
-                                                   const double* __restrict__ taper, double inv_l2,
+                                                   const double* __restrict__ itaper, double inv_l2,
                                                    double sign) {
-  const double l = (X - N / 2) * dl, m = (Y - N / 2) * dl, r2 = l * l + m * m;
-  const double n1 = -r2 / (1.0 + sqrt(1.0 - r2));
+  const double l = (X - N / 2) * dl, m = (Y - N / 2) * dl;
+  double n1;
+  if constexpr (std::is_same_v<R, float>) {
+    const double x = fma(-l, l, fma(-m, m, 1.0));
+    const float s0 = sqrtf((float)x);
+    n1 = (double)s0 + fma(-(double)s0, (double)s0, x) * (double)(0.5f / s0) - 1.0;
+  } else {
+    const double r2 = l * l + m * m;
+    n1 = -r2 / (1.0 + sqrt(1.0 - r2));
+  }
   const auto ph = phasor(sign * w0 * n1, R());
-  const R sc = (R)(inv_l2 / (taper[X] * taper[Y]));
+  const R sc = (R)(inv_l2 * itaper[X] * itaper[Y]);
   return {ph.x * sc, ph.y * sc};
 }
 
@@ -124,7 +135,7 @@ __global__ __launch_bounds__(kFftThreads) void image_fft_rows(const typename C2<
                                                               typename C2<R>::T* dst, int N,
                                                               ImageRadices fr,
                                                               const typename C2<R>::T* __restrict__ tw,
-                                                              const double* __restrict__ taper,
+                                                              const double* __restrict__ itaper,
                                                               double dl, double w0, double inv_l2) {
   using V2 = typename C2<R>::T;
   extern __shared__ unsigned char smem_raw[];
@@ -133,7 +144,7 @@ __global__ __launch_bounds__(kFftThreads) void image_fft_rows(const typename C2<
   const V2* s = src + (size_t)row * N;
   for (int x = threadIdx.x; x < N; x += kFftThreads) {
     V2 v = s[x];
-    if constexpr (PREDICT) v = cmul<R>(v, wterm<R>(x, row, N, dl, w0, taper, inv_l2, -1.0));
+    if constexpr (PREDICT) v = cmul<R>(v, wterm<R>(x, row, N, dl, w0, itaper, inv_l2, -1.0));
     if (x & 1) v = V2{-v.x, -v.y};
     buf[x] = v;
   }
@@ -171,7 +182,7 @@ __global__ __launch_bounds__(256) void image_transpose(const V2* __restrict__ sr
 template <typename R>
 __global__ __launch_bounds__(256) void image_wstack(const typename C2<R>::T* __restrict__ B,
                                                     typename C2<R>::T* __restrict__ img, int N,
-                                                    const double* __restrict__ taper, double dl,
+                                                    const double* __restrict__ itaper, double dl,
                                                     double w0, double inv_l2, int assign) {
   using V2 = typename C2<R>::T;
   __shared__ V2 tile[kTile][kTile + 1];
@@ -185,7 +196,7 @@ __global__ __launch_bounds__(256) void image_wstack(const typename C2<R>::T* __r
   for (int j = ty; j < kTile; j += 256 / kTile) {
     const int Y = by + j, X = bx + tx;
     if (X < N && Y < N) {
-      const V2 v = cmul<R>(tile[tx][j], wterm<R>(X, Y, N, dl, w0, taper, inv_l2, 1.0));
+      const V2 v = cmul<R>(tile[tx][j], wterm<R>(X, Y, N, dl, w0, itaper, inv_l2, 1.0));
       V2* o = img + (size_t)Y * N + X;
       *o = assign ? v : V2{o->x + v.x, o->y + v.y};
     }
@@ -194,7 +205,7 @@ __global__ __launch_bounds__(256) void image_wstack(const typename C2<R>::T* __r
 
 template <typename R>
 int fft_rows_t(int dir, bool predict, const void* src, void* dst, int N, const ImageRadices& fr,
-               const void* tw, const double* taper, double dl, double w0, double inv_l2,
+               const void* tw, const double* itaper, double dl, double w0, double inv_l2,
                hipStream_t st) {
   using V2 = typename C2<R>::T;
   const size_t lds = (size_t)N * sizeof(V2);
@@ -203,25 +214,25 @@ int fft_rows_t(int dir, bool predict, const void* src, void* dst, int N, const I
   const V2* t = reinterpret_cast<const V2*>(tw);
   if (predict)
     hipLaunchKernelGGL((image_fft_rows<R, -1, true>), dim3(N), dim3(kFftThreads), lds, st, s, d, N, fr,
-                       t, taper, dl, w0, inv_l2);
+                       t, itaper, dl, w0, inv_l2);
   else if (dir > 0)
     hipLaunchKernelGGL((image_fft_rows<R, 1, false>), dim3(N), dim3(kFftThreads), lds, st, s, d, N, fr,
-                       t, taper, dl, w0, inv_l2);
+                       t, itaper, dl, w0, inv_l2);
   else
     hipLaunchKernelGGL((image_fft_rows<R, -1, false>), dim3(N), dim3(kFftThreads), lds, st, s, d, N, fr,
-                       t, taper, dl, w0, inv_l2);
+                       t, itaper, dl, w0, inv_l2);
   return (int)hipGetLastError();
 }
 
 }  // namespace
 
 int launch_image_fft_rows(int precision, int dir, bool predict, const void* src, void* dst, int N,
-                          const ImageRadices& fr, const void* tw, const double* taper, double dl,
+                          const ImageRadices& fr, const void* tw, const double* itaper, double dl,
                           double w0, double inv_l2, void* stream) {
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   return precision == AIDG_FP64
-             ? fft_rows_t<double>(dir, predict, src, dst, N, fr, tw, taper, dl, w0, inv_l2, st)
-             : fft_rows_t<float>(dir, predict, src, dst, N, fr, tw, taper, dl, w0, inv_l2, st);
+             ? fft_rows_t<double>(dir, predict, src, dst, N, fr, tw, itaper, dl, w0, inv_l2, st)
+             : fft_rows_t<float>(dir, predict, src, dst, N, fr, tw, itaper, dl, w0, inv_l2, st);
 }
 
 int launch_image_transpose(int precision, const void* src, void* dst, int N, void* stream) {
@@ -236,17 +247,17 @@ int launch_image_transpose(int precision, const void* src, void* dst, int N, voi
   return (int)hipGetLastError();
 }
 
-int launch_image_wstack(int precision, const void* B, void* img, int N, const double* taper, double dl,
+int launch_image_wstack(int precision, const void* B, void* img, int N, const double* itaper, double dl,
                         double w0, double inv_l2, int assign, void* stream) {
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const dim3 grid((N + kTile - 1) / kTile, (N + kTile - 1) / kTile);
   if (precision == AIDG_FP64)
     hipLaunchKernelGGL((image_wstack<double>), grid, dim3(256), 0, st,
-                       reinterpret_cast<const double2*>(B), reinterpret_cast<double2*>(img), N, taper,
+                       reinterpret_cast<const double2*>(B), reinterpret_cast<double2*>(img), N, itaper,
                        dl, w0, inv_l2, assign);
   else
     hipLaunchKernelGGL((image_wstack<float>), grid, dim3(256), 0, st,
-                       reinterpret_cast<const float2*>(B), reinterpret_cast<float2*>(img), N, taper,
+                       reinterpret_cast<const float2*>(B), reinterpret_cast<float2*>(img), N, itaper,
                        dl, w0, inv_l2, assign);
   return (int)hipGetLastError();
 }
