@@ -222,3 +222,30 @@ def test_invert_autograd_is_the_adjoint(aidg):
         torch.real(torch.vdot(J.flatten(), autograd.invert(G, p).flatten())).backward()
         ref = p.predict(J)
         assert rel(host(G.grad), host(ref)) <= 1e-12
+
+
+def test_invert_at_the_largest_row_size(aidg, orc):
+    """N = 8192 in FP32: a row fills exactly 64 KB of LDS, 7 passes (radix 4^6 and 2).
+    One polarisation (all the plan's w-layers) against the oracle's FP64 transform."""
+    wl = synth.config_tiny(206, N=8192, L=32, K=8, fov_deg=20.0)
+    with plan_for(aidg, wl) as p:
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(9)
+        G = torch.randn(p.grid_shape(), dtype=torch.complex64, device="cuda", generator=gen)
+        I = p.invert(G)
+        torch.cuda.synchronize()
+        Ih = I[2].cpu().numpy().astype(np.complex128)
+        del I
+        ref = orc.invert(G[:, 2:3].cpu().numpy().astype(np.complex128), p.wlayers(),
+                         wl.subgrid_size, wl.kernel_support, wl.pixel_scale)[0]
+        err = rel(Ih, ref)
+        print(f"N=8192 invert, W={p.n_wlayers}, one polarisation: {err:.2e}", flush=True)
+        assert err <= TOL[0]
+
+
+def test_fp64_rows_beyond_64_kb_are_refused(aidg):
+    """FP64 at N = 8000: a row of complex128 values would take 125 KB of LDS."""
+    wl = synth.config_tiny(207, N=8000, L=32, K=8, fov_deg=20.0)
+    with plan_for(aidg, wl, precision=1) as p:
+        with pytest.raises(RuntimeError, match="64 KB"):
+            p._image_workspace(torch.device("cuda"))
