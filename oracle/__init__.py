@@ -30,13 +30,14 @@ LIB = os.path.join(HERE, "liboracle.so")
 SUBGRID_DTYPE = np.dtype([
     ("bl", "<i4"), ("st1", "<i4"), ("st2", "<i4"), ("t0", "<i4"), ("nt", "<i4"),
     ("c0", "<i4"), ("nc", "<i4"), ("U0", "<i4"), ("V0", "<i4"), ("wlayer", "<i4"),
-    ("aint", "<i4"), ("reserved", "<i4"), ("w0", "<f8"), ("vis_offset", "<i8")])
+    ("aint", "<i4"), ("folded", "<i4"), ("w0", "<f8"), ("vis_offset", "<i8")])
 assert SUBGRID_DTYPE.itemsize == 64
 
 CHECK_CODES = {
     0: "ok", 1: "bad baseline/stations", 2: "sub-table outside table", 3: "A-term interval",
     4: "window off grid", 5: "uv beyond (L-K)/2", 6: "w beyond layer", 7: "visibility twice",
     8: "placeable visibility missing", 9: "inconsistent layer w0", 10: "vis_offset",
+    11: "fold flag",
 }
 
 _lib = None
@@ -93,22 +94,22 @@ def taper(L: int, K: int, beta: float = 0.0) -> np.ndarray:
     return T
 
 
-def partition(wl, w_step: float) -> np.ndarray:
+def partition(wl, w_step: float, fold: int = 0) -> np.ndarray:
     bl, uvw, f = _arrs(wl)
     cap = max(1024, wl.n_vis)
     out = np.zeros(cap, SUBGRID_DTYPE)
     n = lib().oracle_partition(*_geo(wl), *_obs(wl), _p(bl), _p(uvw), _p(f),
-                               ctypes.c_double(w_step), _p(out), ctypes.c_int64(cap))
+                               ctypes.c_double(w_step), ctypes.c_int(fold), _p(out), ctypes.c_int64(cap))
     assert n >= 0
     return out[:n].copy()
 
 
-def check_partition(wl, table: np.ndarray, w_step: float) -> tuple[int, int]:
+def check_partition(wl, table: np.ndarray, w_step: float, fold: int = 0) -> tuple[int, int]:
     bl, uvw, f = _arrs(wl)
     table = np.ascontiguousarray(table, SUBGRID_DTYPE)
     bad = ctypes.c_int64(0)
     code = lib().oracle_check_partition(*_geo(wl), *_obs(wl), _p(bl), _p(uvw), _p(f),
-                                        ctypes.c_double(w_step), _p(table),
+                                        ctypes.c_double(w_step), ctypes.c_int(fold), _p(table),
                                         ctypes.c_int64(table.shape[0]), ctypes.byref(bad))
     return int(code), int(bad.value)
 

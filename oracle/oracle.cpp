@@ -39,9 +39,12 @@ constexpr double kTwoPi = 6.28318530717958647692528676655900577;
 // array (64 bytes).  bl/st1/st2: baseline and its stations; [t0, t0+nt) x
 // [c0, c0+nc): the visibility sub-table; (U0, V0): integer centre cell;
 // wlayer/w0: w-layer index and its w value in wavelengths; aint: A-term
-// interval; vis_offset: flat index of visibility (bl, t0, c0).
+// interval; folded: the sub-table is gridded at (-u, -v, -w) by the Hermitian
+// symmetry V(-u,-v,-w) = V(u,v,w)^H (Sec. 2.4 footnote): its visibilities enter
+// conjugate-transposed and the A-terms of st2 stand on the left; vis_offset: flat
+// index of visibility (bl, t0, c0).
 struct Subgrid {
-  int32_t bl, st1, st2, t0, nt, c0, nc, U0, V0, wlayer, aint, reserved;
+  int32_t bl, st1, st2, t0, nt, c0, nc, U0, V0, wlayer, aint, folded;
   double w0;
   int64_t vis_offset;
 };
@@ -116,6 +119,7 @@ inline double kb(int x, int L, double beta) {
 
 struct Problem {
   int N, L, K;
+  int fold;             // fold rows with w < 0 to -uvw (w >= 0 layers at odd multiples)
   double dl, fov, du, beta;
   int n_st, nbl, nt, nc, aterm_interval, n_int;
   const int32_t* baselines;
@@ -151,6 +155,7 @@ Problem make_problem(int N, int L, int K, double dl, double beta, int n_st, int 
   p.uvw = uvw;
   p.freqs = freqs;
   p.aterms = aterms;
+  p.fold = 0;
   return p;
 }
 
@@ -163,6 +168,7 @@ Problem make_problem(int N, int L, int K, double dl, double beta, int n_st, int 
 void subgrid_image(const Problem& P, const Subgrid& s, const double* vis, int stage, double* out) {
   const int L = P.L;
   const double u0 = (s.U0 - P.N / 2) * P.du, v0 = (s.V0 - P.N / 2) * P.du;
+  const double sg = s.folded ? -1.0 : 1.0;  // folded: the visibility enters at -uvw as V^H
   std::vector<Mat2> S((size_t)L * L, zero_mat());
   for (int y = 0; y < L; ++y) {
     const double m = P.lpix(y);
@@ -174,9 +180,11 @@ void subgrid_image(const Problem& P, const Subgrid& s, const double* vis, int st
         const double* um = P.uvw + 3 * ((size_t)s.bl * P.nt + t);
         for (int c = s.c0; c < s.c0 + s.nc; ++c) {
           const double f = P.freqs[c] / kSpeedOfLight;
-          const double phi = (um[0] * f - u0) * l + (um[1] * f - v0) * m + (um[2] * f - s.w0) * n1;
+          const double phi =
+              (sg * um[0] * f - u0) * l + (sg * um[1] * f - v0) * m + (sg * um[2] * f - s.w0) * n1;
           const cd ph = turns_phasor(phi);
-          const Mat2 V = load_mat(vis + 8 * (((size_t)s.bl * P.nt + t) * P.nc + c));
+          Mat2 V = load_mat(vis + 8 * (((size_t)s.bl * P.nt + t) * P.nc + c));
+          if (s.folded) V = herm(V);
           for (int i = 0; i < 4; ++i) acc.a[i] += V.a[i] * ph;
         }
       }
@@ -187,8 +195,8 @@ void subgrid_image(const Problem& P, const Subgrid& s, const double* vis, int st
     for (int x = 0; x < L; ++x) {
       Mat2 r = S[(size_t)y * L + x];
       if (stage >= 2) {
-        const Mat2 Ap = load_mat(P.aterm(s.aint, s.st1, x, y));
-        const Mat2 Aq = load_mat(P.aterm(s.aint, s.st2, x, y));
+        const Mat2 Ap = load_mat(P.aterm(s.aint, s.folded ? s.st2 : s.st1, x, y));
+        const Mat2 Aq = load_mat(P.aterm(s.aint, s.folded ? s.st1 : s.st2, x, y));
         r = scale(mul(mul(herm(Ap), r), Aq), cd(P.taper(x, y), 0.0));
       }
       for (int pol = 0; pol < 4; ++pol) {
@@ -243,9 +251,15 @@ struct Cells {
   double gu, gv, w;
 };
 
+// -1 for a row that the fold moves to -uvw (fold mode and w < 0), else +1.
+inline double row_sign(const Problem& P, int bl, int t) {
+  return P.fold && P.uvw[3 * ((size_t)bl * P.nt + t) + 2] < 0 ? -1.0 : 1.0;
+}
+
+// Grid cells and w of a visibility, after the fold of its row.
 inline Cells cells_of(const Problem& P, int bl, int t, int c) {
   const double* um = P.uvw + 3 * ((size_t)bl * P.nt + t);
-  const double f = P.freqs[c] / kSpeedOfLight;
+  const double f = row_sign(P, bl, t) * P.freqs[c] / kSpeedOfLight;
   return {um[0] * f / P.du + P.N / 2, um[1] * f / P.du + P.N / 2, um[2] * f};
 }
 
@@ -256,8 +270,14 @@ inline bool placeable(const Problem& P, const Cells& c) {
   return c.gu >= lo && c.gu <= hi && c.gv >= lo && c.gv <= hi;
 }
 
-inline long long layer_of(double w, double w_step) {
-  return w_step > 0 ? (long long)std::nearbyint(w / w_step) : 0;
+// Layer j of w: nearest j w_step; with the fold (w >= 0) the layers sit at odd
+// multiples of w_step / 2 (Sec. 2.4: {w_max, 3 w_max, ...}), j = floor(w / w_step).
+inline long long layer_of(double w, double w_step, int fold) {
+  if (w_step <= 0) return 0;
+  return fold ? (long long)std::floor(w / w_step) : (long long)std::nearbyint(w / w_step);
+}
+inline double layer_w0(long long j, double w_step, int fold) {
+  return w_step > 0 ? (fold ? (j + 0.5) * w_step : j * w_step) : 0.0;
 }
 
 // Centre cell for a span [lo, hi]: nearest integer to the middle (ties down),
@@ -274,11 +294,12 @@ bool rect_fits(const Problem& P, int bl, int t0, int nt, int c0, int nc, double 
   double ulo = 1e300, uhi = -1e300, vlo = 1e300, vhi = -1e300;
   long long lay = 0;
   bool first = true;
-  for (int t = t0; t < t0 + nt; ++t)
+  for (int t = t0; t < t0 + nt; ++t) {
+    if (row_sign(P, bl, t) != row_sign(P, bl, t0)) return false;  // one fold state
     for (int c = c0; c < c0 + nc; ++c) {
       const Cells q = cells_of(P, bl, t, c);
       if (!placeable(P, q)) return false;
-      const long long j = layer_of(q.w, w_step);
+      const long long j = layer_of(q.w, w_step, P.fold);
       if (first) lay = j;
       else if (j != lay) return false;
       first = false;
@@ -287,6 +308,7 @@ bool rect_fits(const Problem& P, int bl, int t0, int nt, int c0, int nc, double 
       vlo = std::min(vlo, q.gv);
       vhi = std::max(vhi, q.gv);
     }
+  }
   const double half = (P.L - P.K) / 2.0;
   const int cu = centre_for(ulo, uhi, P.L, P.N), cv = centre_for(vlo, vhi, P.L, P.N);
   if (std::max(uhi - cu, cu - ulo) > half || std::max(vhi - cv, cv - vlo) > half) return false;
@@ -312,16 +334,19 @@ void oracle_taper(int L, int K, double beta, double* T) {
 // Partition every baseline's (time, channel) table into rectangular sub-tables
 // that satisfy the subgrid constraints of Sec. 2.2, 2.4 and 3.3: uv within
 // (L-K)/2 cells of an integer centre whose window lies on the grid, one w-layer
-// (|w - w0| <= w_step/2, w0 = j w_step), one A-term interval.  This is the
-// oracle's own, deliberately simple scheme (independent of the library's):
+// (|w - w0| <= w_step/2, w0 = j w_step), one A-term interval.  With fold set,
+// rows with w < 0 are taken at -uvw (Sec. 2.4 footnote), a sub-table holds rows of
+// one fold state, and the layers sit at w0 = (j + 1/2) w_step for w >= 0.  This is
+// the oracle's own, deliberately simple scheme (independent of the library's):
 // single-row greedy channel runs, then vertical merging of identical runs while
 // the merged rectangle still fits.  Returns the number of subgrids written, or
 // -(needed) when cap is too small.  wlayer = j - j_min over the whole table.
 int64_t oracle_partition(int N, int L, int K, double dl, int n_st, int nbl, int nt, int nc,
                          int aterm_interval, const int32_t* baselines, const double* uvw,
-                         const double* freqs, double w_step, Subgrid* out, int64_t cap) {
+                         const double* freqs, double w_step, int fold, Subgrid* out, int64_t cap) {
   Problem P = make_problem(N, L, K, dl, 1.0, n_st, nbl, nt, nc, aterm_interval, 1, baselines, uvw,
                            freqs, nullptr);
+  P.fold = fold;
   struct Rect {
     int bl, t0, nt, c0, nc, U0, V0;
     long long layer;
@@ -400,7 +425,8 @@ int64_t oracle_partition(int N, int L, int K, double dl, int n_st, int nbl, int 
     s.V0 = r.V0;
     s.wlayer = (int32_t)(r.layer - jmin);
     s.aint = r.t0 / aterm_interval;
-    s.w0 = w_step > 0 ? r.layer * w_step : 0.0;
+    s.folded = row_sign(P, r.bl, r.t0) < 0;
+    s.w0 = layer_w0(r.layer, w_step, fold);
     s.vis_offset = ((int64_t)r.bl * nt + r.t0) * nc + r.c0;
   }
   return (int64_t)rects.size();
@@ -415,12 +441,15 @@ int64_t oracle_partition(int N, int L, int K, double dl, int n_st, int nbl, int 
 //   6 a visibility beyond w_step/2 of w0, or w0 not a layer value
 //   7 visibility in two subgrids   8 placeable visibility in no subgrid
 //   9 one wlayer index with two w0 values   10 wrong vis_offset
+//   11 fold flag not the fold state of its rows (w < 0 in fold mode), or set
+//      without fold mode
 int oracle_check_partition(int N, int L, int K, double dl, int n_st, int nbl, int nt, int nc,
                            int aterm_interval, const int32_t* baselines, const double* uvw,
-                           const double* freqs, double w_step, const Subgrid* sg, int64_t nsg,
-                           int64_t* bad) {
+                           const double* freqs, double w_step, int fold, const Subgrid* sg,
+                           int64_t nsg, int64_t* bad) {
   Problem P = make_problem(N, L, K, dl, 1.0, n_st, nbl, nt, nc, aterm_interval, 1, baselines, uvw,
                            freqs, nullptr);
+  P.fold = fold;
   const double half = (L - K) / 2.0, tol = 1e-9;
   std::vector<uint8_t> cover((size_t)nbl * nt * nc, 0);
   std::vector<std::pair<int, double>> layer_w;
@@ -435,11 +464,12 @@ int oracle_check_partition(int N, int L, int K, double dl, int n_st, int nbl, in
       return 3;
     if (s.U0 - L / 2 < 0 || s.U0 + L / 2 > N || s.V0 - L / 2 < 0 || s.V0 + L / 2 > N) return 4;
     if (w_step > 0) {
-      const double j = s.w0 / w_step;
+      const double j = s.w0 / w_step - (fold ? 0.5 : 0.0);
       if (std::fabs(j - std::nearbyint(j)) > 1e-9) return 6;
     } else if (s.w0 != 0.0) {
       return 6;
     }
+    if (s.folded && !fold) return 11;
     bool seen = false;
     for (auto& lw : layer_w)
       if (lw.first == s.wlayer) {
@@ -450,6 +480,7 @@ int oracle_check_partition(int N, int L, int K, double dl, int n_st, int nbl, in
     if (s.vis_offset != ((int64_t)s.bl * nt + s.t0) * nc + s.c0) return 10;
     for (int t = s.t0; t < s.t0 + s.nt; ++t)
       for (int c = s.c0; c < s.c0 + s.nc; ++c) {
+        if ((row_sign(P, s.bl, t) < 0) != (s.folded != 0)) return 11;
         const Cells q = cells_of(P, s.bl, t, c);
         if (std::fabs(q.gu - s.U0) > half + tol || std::fabs(q.gv - s.V0) > half + tol) return 5;
         if (w_step > 0 && std::fabs(q.w - s.w0) > 0.5 * w_step * (1 + 1e-12) + 1e-12) return 6;
@@ -560,11 +591,12 @@ int oracle_degrid(int N, int L, int K, double dl, double beta, int n_st, int nbl
       for (int x = 0; x < L; ++x) {
         Mat2 S;
         for (int pol = 0; pol < 4; ++pol) S.a[pol] = img[((size_t)pol * L + y) * L + x];
-        const Mat2 Ap = load_mat(P.aterm(s.aint, s.st1, x, y));
-        const Mat2 Aq = load_mat(P.aterm(s.aint, s.st2, x, y));
+        const Mat2 Ap = load_mat(P.aterm(s.aint, s.folded ? s.st2 : s.st1, x, y));
+        const Mat2 Aq = load_mat(P.aterm(s.aint, s.folded ? s.st1 : s.st2, x, y));
         Sp[(size_t)y * L + x] = scale(mul(mul(Ap, S), herm(Aq)), cd(P.taper(x, y), 0.0));
       }
     const double u0 = (s.U0 - N / 2) * P.du, v0 = (s.V0 - N / 2) * P.du;
+    const double sg = s.folded ? -1.0 : 1.0;  // folded: predicted at -uvw, written as V^H
     for (int t = s.t0; t < s.t0 + s.nt; ++t) {
       const double* um = P.uvw + 3 * ((size_t)s.bl * nt + t);
       for (int c = s.c0; c < s.c0 + s.nc; ++c) {
@@ -576,13 +608,13 @@ int oracle_degrid(int N, int L, int K, double dl, double beta, int n_st, int nbl
             const double l = P.lpix(x);
             const double n1 = n_minus_one(l, m);
             const double phi =
-                (um[0] * f - u0) * l + (um[1] * f - v0) * m + (um[2] * f - s.w0) * n1;
+                (sg * um[0] * f - u0) * l + (sg * um[1] * f - v0) * m + (sg * um[2] * f - s.w0) * n1;
             const cd ph = std::conj(turns_phasor(phi));
             const Mat2& v = Sp[(size_t)y * L + x];
             for (int q = 0; q < 4; ++q) acc.a[q] += v.a[q] * ph;
           }
         }
-        store_mat(vis_out + 8 * (((size_t)s.bl * nt + t) * nc + c), acc);
+        store_mat(vis_out + 8 * (((size_t)s.bl * nt + t) * nc + c), s.folded ? herm(acc) : acc);
       }
     }
   }

@@ -498,3 +498,67 @@ def test_degrid_of_predicted_lattice_sources_is_the_direct_prediction(orc, seed,
     mask = orc.coverage_mask(wl, table).astype(bool)
     assert mask.sum() > 0.8 * mask.size
     assert rel(V[mask], Vd[mask]) < 1e-11
+
+
+# ------------------------------------------------------------------ w >= 0 fold
+
+
+def herm_part(M):
+    """(M + M^H) / 2 per 2x2 [[XX, XY], [YX, YY]] in the last axis."""
+    H = np.conj(M[..., [0, 2, 1, 3]])
+    return 0.5 * (M + H)
+
+
+FOLD_CASES = [dict(seed=51, ha0_deg=0.0), dict(seed=52, ha0_deg=-60.0)]
+
+
+@pytest.mark.parametrize("case", FOLD_CASES)
+def test_fold_partition_is_valid(orc, case):
+    wl = synth.config_tiny(**case)
+    table = orc.partition(wl, 12.0, fold=1)
+    assert orc.check_partition(wl, table, 12.0, fold=1) == (0, -1)
+    assert table["folded"].sum() > 0 and (table["w0"] > 0).all()
+    bad = table.copy()
+    assert orc.check_partition(wl, bad, 12.0, fold=0)[0] in (6, 11)
+    i = int(np.flatnonzero(bad["folded"])[0])
+    bad["folded"][i] = 0
+    assert orc.check_partition(wl, bad, 12.0, fold=1)[0] in (5, 6, 11)
+
+
+@pytest.mark.parametrize("case", FOLD_CASES)
+def test_folded_gridding_keeps_the_hermitian_image(orc, case):
+    """A folded visibility contributes the conjugate transpose of its unfolded image
+    term (V(-u,-v,-w) = V^H, Sec. 2.4 footnote), so at lattice pixels the Hermitian
+    part of invert(grid(V)) with the fold is that of the direct image, for any V."""
+    wl = synth.config_tiny(**case)
+    N, L, K = wl.grid_size, wl.subgrid_size, wl.kernel_support
+    rng = np.random.default_rng(case["seed"])
+    V = synth.random_vis((wl.n_baselines, wl.n_times, wl.n_chans), rng)
+    table = orc.partition(wl, 12.0, fold=1)
+    I = orc.invert(orc.grid(wl, V, table), orc.layer_w(table), L, K, wl.pixel_scale)
+    xs, ys = lattice_all(L)
+    sel = rng.choice(xs.shape[0], 100, replace=False)
+    xs, ys = xs[sel], ys[sel]
+    X, Y = N // 2 + (xs - L // 2) * (N // L), N // 2 + (ys - L // 2) * (N // L)
+    l, m = orc.lattice_dirs(wl, xs, ys)
+    ref = orc.direct_image(wl, V, l, m, xs, ys, mask=orc.coverage_mask(wl, table))
+    assert rel(herm_part(I[:, Y, X].T), herm_part(ref)) < 1e-11
+    assert rel(I[:, Y, X].T, ref) > 1e-3  # the anti-Hermitian part differs: the fold is not trivial
+
+
+@pytest.mark.parametrize("case", FOLD_CASES)
+def test_folded_degridding_of_lattice_sources_is_the_direct_prediction(orc, case):
+    """A sky of Hermitian brightness matrices: the fold predicts V^H at -uvw and
+    returns its conjugate transpose, which is the direct prediction (Eq. 1)."""
+    wl = synth.config_tiny(**case)
+    N, L, K = wl.grid_size, wl.subgrid_size, wl.kernel_support
+    rng = np.random.default_rng(case["seed"] + 7)
+    src = synth.point_sources(4, wl.fov, 0.5, 5.0, rng, L=L, on_lattice=True)
+    I = np.zeros((4, N, N), np.complex128)
+    for s in range(4):
+        I[:, N // 2 + (src["ys"][s] - L // 2) * (N // L), N // 2 + (src["xs"][s] - L // 2) * (N // L)] += src["B"][s]
+    table = orc.partition(wl, 12.0, fold=1)
+    V = orc.degrid(wl, orc.predict(I, orc.layer_w(table), L, K, wl.pixel_scale), table)
+    Vd = orc.direct_predict(wl, src["l"], src["m"], src["B"], src["xs"], src["ys"])
+    mask = orc.coverage_mask(wl, table).astype(bool)
+    assert rel(V[mask], Vd[mask]) < 1e-11
