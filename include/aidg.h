@@ -99,7 +99,16 @@ typedef struct {
                               cell); 0 = automatic (largest power of two <= 2(L-K)/3), 1 = any cell.
                               Subgrids with the same centre and w-layer share one subgrid FFT
                               and one add to the grid (and one split + inverse FFT) */
-  int32_t reserved;        /* 0 */
+  int32_t w_fold;          /* 1: fold rows with w < 0 to (-u, -v, -w) by the Hermitian
+                              symmetry V(-u,-v,-w) = V(u,v,w)^H (Sec. 2.4 footnote): their
+                              visibilities are gridded conjugate-transposed with the two
+                              stations' A-terms swapped, and degridding returns the
+                              conjugate transpose of what it predicts there.  All layers
+                              are then at w >= 0, at odd multiples of w_step / 2
+                              (w0 = (j + 1/2) w_step, the paper's {w_max, 3 w_max, ...}).
+                              Degridding of a fold-mode plan is exact for Hermitian
+                              brightness (any physical sky); the image of a fold-mode grid
+                              has the right Hermitian part.  0: no fold (default) */
   int64_t workspace_bytes; /* device budget for the group images of one batch
                               (4 L^2 complex each); 0 = 2 GiB */
 } aidg_geometry;
@@ -113,7 +122,8 @@ typedef struct {
   int32_t U0, V0;         /* centre cell */
   int32_t wlayer;         /* index into the plan's w-layers, 0 .. W-1 */
   int32_t aint;           /* A-term interval = t0 / aterm_interval */
-  int32_t reserved;       /* 0 */
+  int32_t folded;         /* 1: the sub-table's rows are folded to -uvw (w_fold plans
+                             only); its U0, V0, w0 refer to the folded coordinates */
   double w0;              /* w of the layer, wavelengths */
   int64_t vis_offset;     /* flat index of visibility (bl, t0, c0) */
 } aidg_subgrid;

@@ -25,7 +25,7 @@ FP32, FP64 = 0, 1
 SUBGRID_DTYPE = np.dtype([
     ("bl", "<i4"), ("st1", "<i4"), ("st2", "<i4"), ("t0", "<i4"), ("nt", "<i4"),
     ("c0", "<i4"), ("nc", "<i4"), ("U0", "<i4"), ("V0", "<i4"), ("wlayer", "<i4"),
-    ("aint", "<i4"), ("reserved", "<i4"), ("w0", "<f8"), ("vis_offset", "<i8")])
+    ("aint", "<i4"), ("folded", "<i4"), ("w0", "<f8"), ("vis_offset", "<i8")])
 
 
 class AidgError(RuntimeError):
@@ -41,7 +41,7 @@ class _Geometry(ctypes.Structure):
                 ("taper_beta", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("reseed_channels", ctypes.c_int32), ("strict_range", ctypes.c_int32),
                 ("max_subgrid_vis", ctypes.c_int32), ("center_lattice", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("workspace_bytes", ctypes.c_int64)]
+                ("w_fold", ctypes.c_int32), ("workspace_bytes", ctypes.c_int64)]
 
 
 class _PlanInfo(ctypes.Structure):
@@ -87,12 +87,13 @@ class Geometry:
     max_subgrid_vis: int = 0
     workspace_bytes: int = 0
     center_lattice: int = 0
+    w_fold: int = 0
 
     def to_c(self) -> _Geometry:
         return _Geometry(self.grid_size, self.subgrid_size, self.kernel_support, self.aterm_interval,
                          self.pixel_scale, self.w_step, self.taper_beta, self.precision,
                          self.reseed_channels, self.strict_range, self.max_subgrid_vis,
-                         self.center_lattice, 0, self.workspace_bytes)
+                         self.center_lattice, self.w_fold, self.workspace_bytes)
 
 
 _lib = None

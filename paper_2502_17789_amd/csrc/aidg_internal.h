@@ -24,18 +24,22 @@ constexpr int64_t kGroupVisFactor = 8;
 struct alignas(16) SubgridDev {
   int32_t t0, nt, c0, nc;      // sub-table
   int32_t U0, V0, wlayer, R;   // centre cell, layer, reseed interval (1: every channel)
-  int32_t ap, aq, bl, group;   // A-term plane index (aint * n_st + station) of p and q;
-                               // baseline; (layer, centre) group in the plan's order
+  int32_t ap, aq, bl, group;   // A-term plane index (aint * n_st + station) of the left and
+                               // right station (swapped for a folded sub-table); baseline;
+                               // (layer, centre) group in the plan's order
   int64_t vis0;                // flat visibility index of (bl, t0, c0)
-  int64_t uvw0;                // flat uvw row index of (bl, t0)
+  int64_t uvw0;                // flat uvw row index of (bl, t0); folded sub-tables index the
+                               // negated copy that follows the table
   double dfc;                  // channel spacing / c (s/m * Hz ... i.e. 1/m) for the recurrence
   double w0;                   // layer w, wavelengths
+  int32_t fold;                // 1: visibilities enter and leave conjugate-transposed
+  int32_t pad1, pad2, pad3;
 };
-static_assert(sizeof(SubgridDev) == 80, "SubgridDev layout");
+static_assert(sizeof(SubgridDev) == 96, "SubgridDev layout");
 
 // Geometry after validation, with derived quantities.
 struct Geometry {
-  int N, L, K, aterm_interval, precision, R, strict, max_sg_vis, lattice;
+  int N, L, K, aterm_interval, precision, R, strict, max_sg_vis, lattice, fold;
   double dl, fov, du, beta, w_step;
   int64_t workspace;
 };

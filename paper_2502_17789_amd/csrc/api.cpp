@@ -357,7 +357,8 @@ aidg_status aidg_plan_create(const aidg_geometry* geo, int32_t n_stations, int32
     } else {
       plan->W = (int)(pr.jmax - pr.jmin + 1);
       plan->w0.resize(plan->W);
-      for (int j = 0; j < plan->W; ++j) plan->w0[j] = pr.w_step > 0 ? (pr.jmin + j) * pr.w_step : 0.0;
+      for (int j = 0; j < plan->W; ++j)
+        plan->w0[j] = pr.w_step > 0 ? (pr.jmin + j + (g.fold ? 0.5 : 0.0)) * pr.w_step : 0.0;
     }
     // Order: subgrids with the same w-layer and centre are consecutive, so that a
     // group shares one image sum, one FFT and one grid update (gridding) or one
@@ -424,8 +425,17 @@ aidg_status aidg_plan_create(const aidg_geometry* geo, int32_t n_stations, int32
       plan->vp_prefix[i + 1] = plan->vp_prefix[i] + (int64_t)s.nt * s.nc * g.L * g.L;
     }
 
-    // device records
+    // device records; folded sub-tables read their rows from a negated copy of uvw
+    // and swap the stations' A-terms
     const double inv_c = 1.0 / kSpeedOfLight;
+    bool any_folded = false;
+    for (const auto& s : plan->table) any_folded = any_folded || s.folded;
+    const size_t uvw_rows = (size_t)n_baselines * n_times;
+    std::vector<double> uvw_dev(uvw_m, uvw_m + 3 * uvw_rows);
+    if (any_folded) {
+      uvw_dev.resize(6 * uvw_rows);
+      for (size_t i = 0; i < 3 * uvw_rows; ++i) uvw_dev[3 * uvw_rows + i] = -uvw_m[i];
+    }
     std::vector<SubgridDev> dev(plan->table.size());
     for (size_t i = 0; i < plan->table.size(); ++i) {
       const aidg_subgrid& s = plan->table[i];
@@ -438,11 +448,12 @@ aidg_status aidg_plan_create(const aidg_geometry* geo, int32_t n_stations, int32
       d.U0 = s.U0;
       d.V0 = s.V0;
       d.wlayer = s.wlayer;
-      d.ap = s.aint * n_stations + s.st1;
-      d.aq = s.aint * n_stations + s.st2;
+      d.ap = s.aint * n_stations + (s.folded ? s.st2 : s.st1);
+      d.aq = s.aint * n_stations + (s.folded ? s.st1 : s.st2);
       d.bl = s.bl;
       d.vis0 = s.vis_offset;
-      d.uvw0 = (int64_t)s.bl * n_times + s.t0;
+      d.uvw0 = (int64_t)s.bl * n_times + s.t0 + (s.folded ? (int64_t)uvw_rows : 0);
+      d.fold = s.folded;
       d.w0 = s.w0;
       d.group = plan->sg_group[i];
       const double df = s.nc > 1 ? freqs_hz[s.c0 + 1] - freqs_hz[s.c0] : 0.0;
@@ -513,7 +524,7 @@ aidg_status aidg_plan_create(const aidg_geometry* geo, int32_t n_stations, int32
       delete plan;
     };
     if ((st = dalloc(&plan->d_sg, dev.size() * sizeof(SubgridDev), plan, "subgrid table", stream)) ||
-        (st = dalloc(&plan->d_uvw, (size_t)n_baselines * n_times * 3 * sizeof(double), plan, "uvw", stream)) ||
+        (st = dalloc(&plan->d_uvw, uvw_dev.size() * sizeof(double), plan, "uvw", stream)) ||
         (st = dalloc(&plan->d_fc, fc.size() * sizeof(double), plan, "frequencies", stream)) ||
         (st = dalloc(&plan->d_aterms, plan->aterm_bytes, plan, "A-terms", stream)) ||
         (st = dalloc(&plan->d_taper, (size_t)L * L * (f32 ? 4 : 8), plan, "taper", stream)) ||
@@ -536,7 +547,7 @@ aidg_status aidg_plan_create(const aidg_geometry* geo, int32_t n_stations, int32
       hipMemcpyKind kind;
     } copies[] = {
         {plan->d_sg, dev.data(), dev.size() * sizeof(SubgridDev), hipMemcpyHostToDevice},
-        {plan->d_uvw, uvw_m, (size_t)n_baselines * n_times * 3 * sizeof(double), hipMemcpyHostToDevice},
+        {plan->d_uvw, uvw_dev.data(), uvw_dev.size() * sizeof(double), hipMemcpyHostToDevice},
         {plan->d_fc, fc.data(), fc.size() * sizeof(double), hipMemcpyHostToDevice},
         {plan->d_aterms, aterms, plan->aterm_bytes, hipMemcpyDeviceToDevice},
         {plan->d_taper, f32 ? (const void*)Tf.data() : (const void*)T.data(), (size_t)L * L * (f32 ? 4 : 8),

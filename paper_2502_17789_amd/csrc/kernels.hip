@@ -231,7 +231,14 @@ __global__ __launch_bounds__(kThreads) void grid_dft(const Group g) {
     const int nv = s.nt * s.nc;
     for (int i = threadIdx.x; i < 2 * nv; i += kThreads) {
       const int k = i >> 1, row = k / s.nc, c = k - row * s.nc;
-      vlds[i] = reinterpret_cast<const V4*>(vis)[(s.vis0 + (int64_t)row * a.nc_total + c) * 2 + (i & 1)];
+      const V4* src = reinterpret_cast<const V4*>(vis) + (s.vis0 + (int64_t)row * a.nc_total + c) * 2;
+      if (s.fold) {
+        // folded sub-table: stage V^H = [[conj XX, conj YX], [conj XY, conj YY]]
+        const V4 h0 = src[0], h1 = src[1];
+        vlds[i] = (i & 1) ? V4{h0.z, -h0.w, h1.z, -h1.w} : V4{h0.x, -h0.y, h1.x, -h1.y};
+      } else {
+        vlds[i] = src[i & 1];
+      }
     }
     R acc[kPix][8];
 #pragma unroll
@@ -736,7 +743,14 @@ __attribute__((amdgpu_waves_per_eu(DegridTune<L, R>::W))) void degrid_dft(const 
   __syncthreads();
   for (int i = threadIdx.x; i < nv * 8; i += kThreads) {
     const int r = i / (s.nc * 8), rem = i % (s.nc * 8);
-    vis[(s.vis0 + (int64_t)r * a.nc_total) * 8 + rem] = accs[i];
+    R val = accs[i];
+    if (s.fold) {
+      // folded sub-table: write the conjugate transpose of the prediction at -uvw
+      const int comp = rem & 7, pol = comp >> 1, src = (pol == 1 ? 2 : pol == 2 ? 1 : pol) * 2 + (comp & 1);
+      val = accs[i - comp + src];
+      if (comp & 1) val = -val;
+    }
+    vis[(s.vis0 + (int64_t)r * a.nc_total) * 8 + rem] = val;
   }
 }
 

@@ -71,6 +71,11 @@ aidg_status validate_geometry(const aidg_geometry* g, Geometry* o, std::string* 
     *err = "center_lattice must be >= 0";
     return AIDG_E_INVALID;
   }
+  if (g->w_fold != 0 && g->w_fold != 1) {
+    *err = "w_fold must be 0 or 1";
+    return AIDG_E_INVALID;
+  }
+  o->fold = g->w_fold;
   if (g->center_lattice > 0) {
     o->lattice = g->center_lattice;
   } else {
@@ -105,19 +110,24 @@ struct Ctx {
   int nbl, nt, nc;
   const double* uvw;
   const double* freqs;
+  // -1 for a row the fold moves to -uvw (fold mode and w < 0), else +1
+  double sign(int bl, int t) const { return g.fold && uvw[3 * ((size_t)bl * nt + t) + 2] < 0 ? -1.0 : 1.0; }
   double cell(int bl, int t, int c, int axis) const {
-    return uvw[3 * ((size_t)bl * nt + t) + axis] * freqs[c] / kSpeedOfLight / g.du + g.N / 2;
+    return sign(bl, t) * uvw[3 * ((size_t)bl * nt + t) + axis] * freqs[c] / kSpeedOfLight / g.du + g.N / 2;
   }
   double wl(int bl, int t, int c) const {
-    return uvw[3 * ((size_t)bl * nt + t) + 2] * freqs[c] / kSpeedOfLight;
+    return sign(bl, t) * uvw[3 * ((size_t)bl * nt + t) + 2] * freqs[c] / kSpeedOfLight;
   }
   bool placeable(int bl, int t, int c) const {
     const double gu = cell(bl, t, c, 0), gv = cell(bl, t, c, 1);
     const double lo = g.K / 2.0, hi = g.N - g.K / 2.0;
     return gu >= lo && gu <= hi && gv >= lo && gv <= hi && std::isfinite(gu) && std::isfinite(gv);
   }
+  // nearest layer j w_step; with the fold (w >= 0) layers at (j + 1/2) w_step
   int64_t layer(int bl, int t, int c) const {
-    return g.w_step > 0 ? (int64_t)std::nearbyint(wl(bl, t, c) / g.w_step) : 0;
+    if (!(g.w_step > 0)) return 0;
+    const double j = wl(bl, t, c) / g.w_step;
+    return (int64_t)(g.fold ? std::floor(j) : std::nearbyint(j));
   }
 };
 
@@ -159,9 +169,10 @@ bool centre(double lo, double hi, double half, int L, int N, int lattice, int* c
   return false;
 }
 
-// Add row t, channels [c0, c1), to box b; false if a visibility is unplaceable
-// or in another layer.
-bool add_row(const Ctx& x, int bl, int t, int c0, int c1, int64_t layer, Box* b) {
+// Add row t, channels [c0, c1), to box b; false if the row has another fold state
+// than sgn, or a visibility is unplaceable or in another layer.
+bool add_row(const Ctx& x, int bl, int t, int c0, int c1, int64_t layer, double sgn, Box* b) {
+  if (x.sign(bl, t) != sgn) return false;
   for (int c = c0; c < c1; ++c) {
     if (!x.placeable(bl, t, c) || x.layer(bl, t, c) != layer) return false;
     b->add(x.cell(bl, t, c, 0), x.cell(bl, t, c, 1));
@@ -205,7 +216,7 @@ void tile(const Ctx& x, int bl, int ts, int te, int c_lo, int c_hi, PartitionRes
     int t1 = ts + 1;
     while (t1 < te && (int64_t)(t1 - ts + 1) * (e - c) <= g.max_sg_vis) {
       Box q = b;
-      if (!add_row(x, bl, t1, c, e, lay, &q)) break;
+      if (!add_row(x, bl, t1, c, e, lay, x.sign(bl, ts), &q)) break;
       if (!centre(q.ulo, q.uhi, half, g.L, g.N, g.lattice, &cu) || !centre(q.vlo, q.vhi, half, g.L, g.N, g.lattice, &cv))
         break;
       b = q;
@@ -227,7 +238,8 @@ void tile(const Ctx& x, int bl, int ts, int te, int c_lo, int c_hi, PartitionRes
     s.V0 = V0;
     s.wlayer = (int32_t)lay;  // raw layer number, rebased by the caller
     s.aint = ts / g.aterm_interval;
-    s.w0 = g.w_step > 0 ? lay * g.w_step : 0.0;
+    s.folded = x.sign(bl, ts) < 0;
+    s.w0 = g.w_step > 0 ? (lay + (g.fold ? 0.5 : 0.0)) * g.w_step : 0.0;
     s.vis_offset = ((int64_t)bl * x.nt + ts) * x.nc + c;
     sgs->push_back(s);
     tile(x, bl, t1, te, c, e, out, sgs, baselines);
@@ -325,6 +337,10 @@ aidg_status adopt_table(const Geometry& g, int n_st, int nbl, int nt, int nc,
     w0[s.wlayer] = s.w0;
     if (s.vis_offset != ((int64_t)s.bl * nt + s.t0) * nc + s.c0) {
       *err = std::string(msg) + "vis_offset does not match (bl, t0, c0)";
+      return AIDG_E_INVALID;
+    }
+    if (s.folded != 0 && (s.folded != 1 || !g.fold)) {
+      *err = std::string(msg) + "folded sub-table needs a w_fold plan (folded is 0 or 1)";
       return AIDG_E_INVALID;
     }
     for (int t = s.t0; t < s.t0 + s.nt; ++t)

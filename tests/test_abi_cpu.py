@@ -79,13 +79,29 @@ def test_auto_w_step_formula():
 @pytest.mark.parametrize("bad", [dict(subgrid_size=33), dict(kernel_support=32), dict(grid_size=30),
                                  dict(pixel_scale=-1.0), dict(aterm_interval=0),
                                  dict(pixel_scale=math.radians(120) / 512), dict(max_subgrid_vis=2049),
-                                 dict(max_subgrid_vis=-1), dict(center_lattice=-2)])
+                                 dict(max_subgrid_vis=-1), dict(center_lattice=-2), dict(w_fold=2)])
 def test_invalid_geometry_rejected(bad):
     kw = dict(grid_size=512, subgrid_size=32, kernel_support=8, pixel_scale=math.radians(10) / 512)
     kw.update(bad)
     with pytest.raises(aidg.AidgError) as e:
         aidg.partition(aidg.Geometry(**kw), 2, np.array([[0, 1]]), np.zeros((1, 1, 3)), np.array([1e8]))
     assert e.value.status == aidg.AIDG_E_INVALID
+
+
+@pytest.mark.parametrize("seed,ha0_deg", [(51, 0.0), (52, -60.0)])
+def test_fold_partition_valid_and_fewer_layers(orc, seed, ha0_deg):
+    """w_fold: the library's partition passes the oracle's checker in fold mode, holds
+    folded sub-tables, puts every layer at w0 = (j + 1/2) w_step > 0, and needs no
+    more layers than the unfolded partition (about half when w takes both signs)."""
+    wl = synth.config_tiny(seed, ha0_deg=ha0_deg)
+    geo = dict(grid_size=wl.grid_size, subgrid_size=wl.subgrid_size, kernel_support=wl.kernel_support,
+               pixel_scale=wl.pixel_scale, aterm_interval=wl.aterm_interval, w_step=12.0)
+    t1, ws = aidg.partition(aidg.Geometry(**geo, w_fold=1), wl.n_stations, wl.baselines, wl.uvw, wl.freqs)
+    t0, _ = aidg.partition(aidg.Geometry(**geo), wl.n_stations, wl.baselines, wl.uvw, wl.freqs)
+    assert orc.check_partition(wl, t1, ws, fold=1) == (0, -1)
+    assert t1["folded"].sum() > 0 and (t1["w0"] > 0).all()
+    assert np.allclose(((t1["w0"] / ws) - 0.5) % 1.0, 0.0)
+    assert len(np.unique(t1["w0"])) <= len(np.unique(t0["w0"]))
 
 
 def test_strict_range_reports_range_error():
