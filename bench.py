@@ -105,6 +105,8 @@ def parse():
                     help="image-level w-stacking (invert and predict) at the MWA-like size, FP32, at "
                          "max |w| of --image-wmax wavelengths (JSON line per case)")
     ap.add_argument("--image-wmax", type=float, nargs="+", default=[0.0, 250.0])
+    ap.add_argument("--image-fold", type=int, nargs="+", default=[0, 1],
+                    help="image mode: w_fold settings to run at max |w| > 0")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device-to-device 3 times (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -410,11 +412,12 @@ def image_bench(args):
     import synth
 
     torch.cuda.set_device(0)
-    for wmax in args.image_wmax:
+    cases = [(w, f) for w in args.image_wmax for f in (args.image_fold if w > 0 else [0])]
+    for wmax, fold in cases:
         ha = synth.hour_angle_for_wmax(wmax) if wmax > 0 else 0.0
         wl = synth.config_mwa(seed=2, ha0_rad=ha)
         geo = aidg.Geometry(wl.grid_size, wl.subgrid_size, wl.kernel_support, wl.pixel_scale,
-                            aterm_interval=wl.aterm_interval)
+                            aterm_interval=wl.aterm_interval, w_fold=fold)
         A = torch.from_numpy(wl.aterms.astype(np.complex64)).cuda()
         with aidg.Plan(geo, wl.n_stations, wl.baselines, wl.uvw, wl.freqs, A) as plan:
             del A
@@ -452,7 +455,7 @@ def image_bench(args):
         dom = max(by, key=lambda k: kt[k]["ms"])
         print(json.dumps({
             "image_level": {"grid_size": N, "n_wlayers": W, "max_abs_w_lambda": wmax or "transit",
-                            "precision": "fp32", "plane_bytes": P},
+                            "w_fold": fold, "precision": "fp32", "plane_bytes": P},
             "invert_ms": round(t_inv, 3), "predict_ms": round(t_pred, 3),
             "classes": cls,
             "roofline": {"kernel": dom, "bound": "hbm", "achieved": cls[dom]["gb_s"], "peak": 8000.0,
