@@ -13,6 +13,11 @@ adjoint identity between gridding and degridding.
 The image-level step (w-stacking, ``invert`` / ``predict``) is plain numpy in
 FP64 on top of numpy's FFT; it is pinned by a brute-force DFT matrix, the adjoint
 identity, and the direct imaging and prediction equations at the subgrid lattice.
+
+The inverse A-term mode (Sec. 3.3: gridding with A_p^-1 . A_q^-H normalised by
+||A_p^-1 A_q^-H||_F, the image divided by the weighted average of that factor) is
+pinned by unitary Jones terms (where it is the adjoint mode over sqrt 2), a closed
+form for diagonal Jones terms, and exact recovery of a lattice source's brightness.
 """
 from __future__ import annotations
 
@@ -128,7 +133,8 @@ def layer_w(table: np.ndarray) -> np.ndarray:
     return w
 
 
-def grid_subgrid(wl, vis: np.ndarray, sg, stage: int, beta: float = 0.0) -> np.ndarray:
+def grid_subgrid(wl, vis: np.ndarray, sg, stage: int, beta: float = 0.0,
+                 aterm_mode: int = 0) -> np.ndarray:
     bl, uvw, f = _arrs(wl)
     A = _c128(wl.aterms)
     vis = _c128(vis)
@@ -137,12 +143,14 @@ def grid_subgrid(wl, vis: np.ndarray, sg, stage: int, beta: float = 0.0) -> np.n
     out = np.zeros((4, L, L), np.complex128)
     lib().oracle_grid_subgrid(*_geo(wl), ctypes.c_double(beta), *_obs(wl),
                               ctypes.c_int(A.shape[0]), _p(bl), _p(uvw), _p(f), _p(A), _p(vis),
-                              _p(sgr), ctypes.c_int(stage), _p(out))
+                              _p(sgr), ctypes.c_int(stage), ctypes.c_int(aterm_mode), _p(out))
     return out
 
 
 def grid(wl, vis: np.ndarray, table: np.ndarray, W: int | None = None, beta: float = 0.0,
-         nthreads: int = 0, out: np.ndarray | None = None) -> np.ndarray:
+         nthreads: int = 0, out: np.ndarray | None = None, aterm_mode: int = 0) -> np.ndarray:
+    """Gridding; aterm_mode 0 applies A_p^H . A_q, 1 the normalised inverse
+    A_p^-1 . A_q^-H / ||A_p^-1 A_q^-H||_F of Sec. 3.3."""
     bl, uvw, f = _arrs(wl)
     A = _c128(wl.aterms)
     vis = _c128(vis)
@@ -153,9 +161,24 @@ def grid(wl, vis: np.ndarray, table: np.ndarray, W: int | None = None, beta: flo
     rc = lib().oracle_grid(*_geo(wl), ctypes.c_double(beta), *_obs(wl), ctypes.c_int(A.shape[0]),
                            _p(bl), _p(uvw), _p(f), _p(A), _p(vis), _p(table),
                            ctypes.c_int64(table.shape[0]), ctypes.c_int(W), _p(G),
-                           ctypes.c_int(nthreads))
+                           ctypes.c_int(nthreads), ctypes.c_int(aterm_mode))
     assert rc == 0
     return G
+
+
+def aterm_norm(wl, table: np.ndarray) -> np.ndarray:
+    """Weighted average over the table's subgrids (weights: visibility counts) of the
+    inverse mode's normalisation factor 1 / ||A_p^-1 A_q^-H||_F (Sec. 3.3), on the
+    L x L subgrid lattice [y][x]."""
+    bl, uvw, f = _arrs(wl)
+    A = _c128(wl.aterms)
+    table = np.ascontiguousarray(table, SUBGRID_DTYPE)
+    L = wl.subgrid_size
+    out = np.zeros((L, L))
+    lib().oracle_aterm_norm(ctypes.c_int(wl.grid_size), ctypes.c_int(L), ctypes.c_double(wl.pixel_scale),
+                            *_obs(wl), ctypes.c_int(A.shape[0]), _p(bl), _p(uvw), _p(f), _p(A),
+                            _p(table), ctypes.c_int64(table.shape[0]), _p(out))
+    return out
 
 
 def degrid(wl, G: np.ndarray, table: np.ndarray, beta: float = 0.0, nthreads: int = 0) -> np.ndarray:
@@ -267,12 +290,32 @@ def centred_dft2(a: np.ndarray, sign: int) -> np.ndarray:
     return np.fft.fftshift(t, axes=(-2, -1))
 
 
-def invert(G: np.ndarray, w0, L: int, K: int, dl: float, beta: float = 0.0) -> np.ndarray:
+def lattice_to_image(M: np.ndarray, N: int) -> np.ndarray:
+    """Bilinear interpolation of an L x L subgrid-lattice map [y][x] at the N x N image
+    pixels, periodic over the field of view.  Image pixel X sits at lattice coordinate
+    g = (X - N/2) L / N + L/2; the value mixes lattice points floor(g) and floor(g) + 1
+    (mod L) with weights 1 - frac(g) and frac(g), per axis."""
+    L = M.shape[-1]
+    g = (np.arange(N) - N // 2) * (L / N) + L // 2
+    i0 = np.floor(g).astype(np.int64)
+    fr = g - i0
+    i0 %= L
+    i1 = (i0 + 1) % L
+    rows = M[i0, :] * (1 - fr)[:, None] + M[i1, :] * fr[:, None]   # [Y][x]
+    return rows[:, i0] * (1 - fr)[None, :] + rows[:, i1] * fr[None, :]
+
+
+def invert(G: np.ndarray, w0, L: int, K: int, dl: float, beta: float = 0.0,
+           norm: np.ndarray | None = None) -> np.ndarray:
     """Imaging by w-stacking (Sec. 2.4, Eq. wstack; Sec. 2.5 imaging step 3):
     I[p][Y][X] = 1 / (L^2 T(X, Y)) sum_w exp(+2 pi i w0_w n1(X, Y)) F+{G_w[p]}(Y, X),
     F+ the centred transform with exp(+2 pi i (u l + v m)) over (gv, gu).  The 1/L^2
     undoes the unnormalised subgrid transforms, so that at subgrid-lattice pixels the
-    image of gridded visibilities is the direct A-term image.  G: [W][P][N][N]."""
+    image of gridded visibilities is the direct A-term image.  G: [W][P][N][N].
+
+    ``norm`` (the inverse A-term mode, Sec. 3.3): the L x L weighted-average
+    normalisation map of ``aterm_norm``; the image is divided by its bilinear
+    interpolation at every pixel, and set to 0 where that is 0."""
     G = np.asarray(G)
     N = G.shape[-1]
     t = image_taper(N, K, beta)
@@ -280,7 +323,11 @@ def invert(G: np.ndarray, w0, L: int, K: int, dl: float, beta: float = 0.0) -> n
     out = np.zeros(G.shape[1:], np.complex128)
     for j in range(G.shape[0]):
         out += centred_dft2(G[j].astype(np.complex128), +1) * np.exp(2j * np.pi * w0[j] * n1)
-    return out / (L * L * np.outer(t, t))
+    out = out / (L * L * np.outer(t, t))
+    if norm is not None:
+        c = lattice_to_image(np.asarray(norm, np.float64), N)
+        out = np.where(c > 0, out / np.where(c > 0, c, 1.0), 0.0)
+    return out
 
 
 def predict(I: np.ndarray, w0, L: int, K: int, dl: float, beta: float = 0.0) -> np.ndarray:

@@ -97,6 +97,22 @@ inline Mat2 zero_mat() {
   for (int i = 0; i < 4; ++i) r.a[i] = cd(0.0, 0.0);
   return r;
 }
+// Inverse of a 2x2 matrix, adj(x) / det(x); the zero matrix when det(x) = 0.
+inline Mat2 inverse(const Mat2& x) {
+  const cd det = x.a[0] * x.a[3] - x.a[1] * x.a[2];
+  if (det == cd(0.0, 0.0)) return zero_mat();
+  Mat2 r;
+  r.a[0] = x.a[3] / det;
+  r.a[1] = -x.a[1] / det;
+  r.a[2] = -x.a[2] / det;
+  r.a[3] = x.a[0] / det;
+  return r;
+}
+inline double frobenius(const Mat2& x) {
+  double s = 0.0;
+  for (int i = 0; i < 4; ++i) s += std::norm(x.a[i]);
+  return std::sqrt(s);
+}
 
 // exp(2 pi i phi) for a phase in turns, reduced to [-1/2, 1/2] first.
 inline cd turns_phasor(double phi) {
@@ -120,6 +136,7 @@ inline double kb(int x, int L, double beta) {
 struct Problem {
   int N, L, K;
   int fold;             // fold rows with w < 0 to -uvw (w >= 0 layers at odd multiples)
+  int amode;            // gridding A-term: 0 A_p^H . A_q, 1 normalised A_p^-1 . A_q^-H (Sec. 3.3)
   double dl, fov, du, beta;
   int n_st, nbl, nt, nc, aterm_interval, n_int;
   const int32_t* baselines;
@@ -156,14 +173,25 @@ Problem make_problem(int N, int L, int K, double dl, double beta, int n_st, int 
   p.freqs = freqs;
   p.aterms = aterms;
   p.fold = 0;
+  p.amode = 0;
   return p;
 }
 
 // ---------------------------------------------------------------- gridding steps
 
+// Normalisation factor of the inverse A-term mode at one pixel (Sec. 3.3, A-term
+// application): 1 / ||A_p^-1 (A_q^-1)^H||_F, and 0 where the product vanishes (a
+// singular A-term).
+double inverse_norm_factor(const Mat2& Ap, const Mat2& Aq) {
+  const double n = frobenius(mul(inverse(Ap), herm(inverse(Aq))));
+  return n > 0.0 ? 1.0 / n : 0.0;
+}
+
 // G1 + G2 (Sec. 2.4 Eq. withw with the A-term deferred as in Sec. 3.3):
 //   S(x,y)  = sum_k V_k exp(+2 pi i phi_k(x,y))
-//   S'(x,y) = T(x,y) A_p(x,y)^H S(x,y) A_q(x,y)
+//   S'(x,y) = T(x,y) A_p(x,y)^H S(x,y) A_q(x,y)                       (amode 0)
+//   S'(x,y) = T(x,y) f(x,y) A_p(x,y)^-1 S(x,y) A_q(x,y)^-H,
+//             f = 1 / ||A_p^-1 A_q^-H||_F                               (amode 1)
 // stage 1 returns S, stage 2 returns S'.  out: complex [4][L][L].
 void subgrid_image(const Problem& P, const Subgrid& s, const double* vis, int stage, double* out) {
   const int L = P.L;
@@ -197,7 +225,12 @@ void subgrid_image(const Problem& P, const Subgrid& s, const double* vis, int st
       if (stage >= 2) {
         const Mat2 Ap = load_mat(P.aterm(s.aint, s.folded ? s.st2 : s.st1, x, y));
         const Mat2 Aq = load_mat(P.aterm(s.aint, s.folded ? s.st1 : s.st2, x, y));
-        r = scale(mul(mul(herm(Ap), r), Aq), cd(P.taper(x, y), 0.0));
+        if (P.amode == 1) {
+          const double f = inverse_norm_factor(Ap, Aq);
+          r = scale(mul(mul(inverse(Ap), r), herm(inverse(Aq))), cd(P.taper(x, y) * f, 0.0));
+        } else {
+          r = scale(mul(mul(herm(Ap), r), Aq), cd(P.taper(x, y), 0.0));
+        }
       }
       for (int pol = 0; pol < 4; ++pol) {
         double* o = out + 2 * (((size_t)pol * L + y) * L + x);
@@ -510,9 +543,10 @@ int oracle_check_partition(int N, int L, int K, double dl, int n_st, int nbl, in
 int oracle_grid_subgrid(int N, int L, int K, double dl, double beta, int n_st, int nbl, int nt,
                         int nc, int aterm_interval, int n_int, const int32_t* baselines,
                         const double* uvw, const double* freqs, const double* aterms,
-                        const double* vis, const Subgrid* s, int stage, double* out) {
+                        const double* vis, const Subgrid* s, int stage, int amode, double* out) {
   Problem P = make_problem(N, L, K, dl, beta, n_st, nbl, nt, nc, aterm_interval, n_int, baselines,
                            uvw, freqs, aterms);
+  P.amode = amode;
   if (stage == 3) subgrid_uv(P, *s, vis, out);
   else subgrid_image(P, *s, vis, stage, out);
   return 0;
@@ -525,9 +559,10 @@ int oracle_grid_subgrid(int N, int L, int K, double dl, double beta, int n_st, i
 int oracle_grid(int N, int L, int K, double dl, double beta, int n_st, int nbl, int nt, int nc,
                 int aterm_interval, int n_int, const int32_t* baselines, const double* uvw,
                 const double* freqs, const double* aterms, const double* vis, const Subgrid* sg,
-                int64_t nsg, int W, double* grid, int nthreads) {
+                int64_t nsg, int W, double* grid, int nthreads, int amode) {
   Problem P = make_problem(N, L, K, dl, beta, n_st, nbl, nt, nc, aterm_interval, n_int, baselines,
                            uvw, freqs, aterms);
+  P.amode = amode;
 #ifdef _OPENMP
   if (nthreads > 0) omp_set_num_threads(nthreads);
 #endif
@@ -553,6 +588,34 @@ int oracle_grid(int N, int L, int K, double dl, double beta, int n_st, int nbl, 
           }
     }
   }
+  return 0;
+}
+
+// Weighted average of the inverse mode's normalisation factor over all subgrids
+// (Sec. 3.3, A-term application), each subgrid weighted by its visibility count:
+//   M(x,y) = sum_s nvis_s f_s(x,y) / sum_s nvis_s,  f_s = 1 / ||A_p^-1 A_q^-H||_F.
+// out: [L][L] (y major), zero when the table holds no visibilities.
+int oracle_aterm_norm(int N, int L, double dl, int n_st, int nbl, int nt, int nc,
+                      int aterm_interval, int n_int, const int32_t* baselines, const double* uvw,
+                      const double* freqs, const double* aterms, const Subgrid* sg, int64_t nsg,
+                      double* out) {
+  Problem P = make_problem(N, L, 0, dl, 1.0, n_st, nbl, nt, nc, aterm_interval, n_int, baselines,
+                           uvw, freqs, aterms);
+  double total = 0.0;
+  for (size_t i = 0; i < (size_t)L * L; ++i) out[i] = 0.0;
+  for (int64_t i = 0; i < nsg; ++i) {
+    const Subgrid& s = sg[i];
+    const double nv = double(s.nt) * s.nc;
+    total += nv;
+    for (int y = 0; y < L; ++y)
+      for (int x = 0; x < L; ++x) {
+        const Mat2 Ap = load_mat(P.aterm(s.aint, s.folded ? s.st2 : s.st1, x, y));
+        const Mat2 Aq = load_mat(P.aterm(s.aint, s.folded ? s.st1 : s.st2, x, y));
+        out[(size_t)y * L + x] += nv * inverse_norm_factor(Ap, Aq);
+      }
+  }
+  if (total > 0.0)
+    for (size_t i = 0; i < (size_t)L * L; ++i) out[i] /= total;
   return 0;
 }
 

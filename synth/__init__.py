@@ -304,15 +304,18 @@ def config_tiny(seed: int, n_st: int = 5, n_t: int = 6, n_c: int = 5, N: int = 1
                 L: int = 32, K: int = 8, fov_deg: float = 20.0, diameter_m: float = 300.0,
                 aterm_interval: int = 3, screen_rms: float = 1.0, ha0_deg: float = 20.0,
                 f_lo: float = 140e6, f_hi: float = 160e6, complex_jones: bool = True,
-                w_step: float = 0.0) -> Workload:
-    """Small randomised geometry for exact-identity and property tests."""
+                w_step: float = 0.0, beam_fwhm_deg: float | None = None) -> Workload:
+    """Small randomised geometry for exact-identity and property tests; with
+    ``beam_fwhm_deg`` the Jones terms carry a Gaussian beam (non-unitary, varying over
+    the field)."""
     rng = np.random.default_rng(seed)
     bl, uvw, f = observation(n_st, diameter_m, n_t, 30.0, f_lo, f_hi, n_c, rng,
                              ha0_rad=math.radians(ha0_deg))
     dl = math.radians(fov_deg) / N
     n_int = (n_t + aterm_interval - 1) // aterm_interval
     A = make_aterms(n_int, n_st, L, N * dl, screen_rms, 6, rng, kind="white",
-                    complex_jones=complex_jones)
+                    complex_jones=complex_jones,
+                    beam_fwhm_rad=None if beam_fwhm_deg is None else math.radians(beam_fwhm_deg))
     return Workload(f"tiny{seed}", n_st, bl, uvw, f, N, L, K, dl, aterm_interval, A,
                     w_step=w_step)
 

@@ -12,8 +12,11 @@ the oracle's own formulas:
   * IDG degridding of lattice point sources against direct prediction (Eq. 1);
   * the adjoint identity between gridding and degridding;
   * Jones factorisation, linearity, permutation invariance, Hermitian symmetry
-    of the measurement equation (Sec. 2.4 footnote) and partition validity.
+    of the measurement equation (Sec. 2.4 footnote) and partition validity;
+  * the inverse A-term mode (Sec. 3.3) against unitary Jones terms, a closed form
+    for diagonal ones, and recovery of a lattice source's brightness.
 """
+import dataclasses
 import math
 
 import numpy as np
@@ -562,3 +565,108 @@ def test_folded_degridding_of_lattice_sources_is_the_direct_prediction(orc, case
     Vd = orc.direct_predict(wl, src["l"], src["m"], src["B"], src["xs"], src["ys"])
     mask = orc.coverage_mask(wl, table).astype(bool)
     assert rel(V[mask], Vd[mask]) < 1e-11
+
+
+# ------------------------------------------------------------------ inverse A-term mode
+
+
+def random_unitary_jones(shape, rng):
+    """Random 2x2 unitaries [..., 4] = e^{i t/2} [[a, b], [-conj(b) e^{i t}, conj(a) e^{i t}]]
+    with |a|^2 + |b|^2 = 1."""
+    z = rng.standard_normal(shape + (2,)) + 1j * rng.standard_normal(shape + (2,))
+    z /= np.linalg.norm(z, axis=-1, keepdims=True)
+    a, b = z[..., 0], z[..., 1]
+    e = np.exp(1j * rng.uniform(0, 2 * np.pi, shape))
+    return np.stack([a, b, -np.conj(b) * e, np.conj(a) * e], axis=-1) * np.sqrt(np.conj(e))[..., None]
+
+
+def test_inverse_mode_with_unitary_jones_is_the_adjoint_mode_over_sqrt2(orc):
+    """For unitary A, A^-1 = A^H and ||A_p^-1 A_q^-H||_F = ||U||_F = sqrt(2): the
+    inverse mode's subgrid image is the adjoint mode's divided by sqrt(2), and the
+    normalisation map is 1/sqrt(2) everywhere."""
+    wl = synth.config_tiny(71)
+    rng = np.random.default_rng(71)
+    A = random_unitary_jones(wl.aterms.shape[:-1], rng)
+    M = A.reshape(A.shape[:-1] + (2, 2))
+    assert np.allclose(M @ M.conj().swapaxes(-1, -2), np.eye(2), atol=1e-12)
+    wl = dataclasses.replace(wl, aterms=A)
+    V = synth.random_vis((wl.n_baselines, wl.n_times, wl.n_chans), rng)
+    table = orc.partition(wl, 0.0)
+    for s in table[:: max(1, table.shape[0] // 5)]:
+        adj = orc.grid_subgrid(wl, V, s, 2)
+        inv = orc.grid_subgrid(wl, V, s, 2, aterm_mode=1)
+        assert rel(inv, adj / math.sqrt(2)) < 1e-12
+    assert np.allclose(orc.aterm_norm(wl, table), 1 / math.sqrt(2), rtol=1e-13)
+
+
+def test_aterm_norm_of_diagonal_jones_is_the_closed_form(orc):
+    """A = diag(a, d): A_p^-1 A_q^-H = diag(1/(a_p a_q*), 1/(d_p d_q*)), so the factor is
+    1 / sqrt(1/|a_p a_q|^2 + 1/|d_p d_q|^2), and 0 where a station's A-term is zero."""
+    wl = synth.config_tiny(72)
+    rng = np.random.default_rng(72)
+    shp = wl.aterms.shape[:-1]
+    a = (0.3 + rng.uniform(0, 1, shp)) * np.exp(1j * rng.uniform(0, 2 * np.pi, shp))
+    d = (0.3 + rng.uniform(0, 1, shp)) * np.exp(1j * rng.uniform(0, 2 * np.pi, shp))
+    a[:, 1, :5, :7] = 0.0   # station 1 blind in a corner: singular A-terms there
+    d[:, 1, :5, :7] = 0.0
+    A = np.zeros(shp + (4,), np.complex128)
+    A[..., 0], A[..., 3] = a, d
+    wl = dataclasses.replace(wl, aterms=A)
+    table = orc.partition(wl, 0.0)
+    acc = np.zeros(shp[-2:])
+    tot = 0.0
+    with np.errstate(divide="ignore"):
+        for s in table:
+            nv = float(s["nt"] * s["nc"])
+            p, q, i = s["st1"], s["st2"], s["aint"]
+            x = 1 / np.abs(a[i, p] * a[i, q]) ** 2 + 1 / np.abs(d[i, p] * d[i, q]) ** 2
+            acc += nv / np.sqrt(x)
+            tot += nv
+    got = orc.aterm_norm(wl, table)
+    assert rel(got, acc / tot) < 1e-13
+
+
+@pytest.mark.parametrize("seed,w_step", [(73, 0.0), (74, 12.0)])
+def test_inverse_mode_image_of_a_lattice_source_is_its_brightness(orc, seed, w_step):
+    """Sec. 3.3: gridding with A^-1 recovers the true brightness.  A point source B on a
+    subgrid-lattice pixel, non-unitary direction-dependent Jones (beam, unequal gains,
+    leakage): after inverse-mode gridding, w-stacking and division by the weighted
+    average normalisation, the image at that pixel is K B, K the number of gridded
+    visibilities -- each contributes f_k B, and the average of f_k is what divides."""
+    wl = synth.config_tiny(seed, beam_fwhm_deg=15.0)
+    N, L, K = wl.grid_size, wl.subgrid_size, wl.kernel_support
+    rng = np.random.default_rng(seed)
+    src = synth.point_sources(1, wl.fov, 1.0, 3.0, rng, L=L, on_lattice=True)
+    V = orc.direct_predict(wl, src["l"], src["m"], src["B"], src["xs"], src["ys"])
+    table = orc.partition(wl, w_step)
+    w0 = orc.layer_w(table)
+    nrm = orc.aterm_norm(wl, table)
+    I = orc.invert(orc.grid(wl, V, table, aterm_mode=1), w0, L, K, wl.pixel_scale, norm=nrm)
+    X = N // 2 + (int(src["xs"][0]) - L // 2) * (N // L)
+    Y = N // 2 + (int(src["ys"][0]) - L // 2) * (N // L)
+    Kc = int(orc.coverage_mask(wl, table).sum())
+    assert Kc > 0.8 * V.shape[0] * V.shape[1] * V.shape[2]
+    assert rel(I[:, Y, X], Kc * src["B"][0]) < 1e-11
+    # the adjoint mode does not recover B under these Jones terms
+    Ia = orc.invert(orc.grid(wl, V, table), w0, L, K, wl.pixel_scale)
+    assert rel(Ia[:, Y, X], Kc * src["B"][0]) > 1e-2
+
+
+def test_lattice_to_image_is_bilinear(orc):
+    """At image pixels that are lattice pixels the map is returned unchanged; between
+    them an affine map is reproduced exactly (away from the periodic wrap)."""
+    L, N = 16, 128
+    rng = np.random.default_rng(75)
+    M = rng.uniform(0.5, 2.0, (L, L))
+    img = orc.lattice_to_image(M, N)
+    x = np.arange(L)
+    Xs = N // 2 + (x - L // 2) * (N // L)
+    assert np.array_equal(img[np.ix_(Xs, Xs)], M)
+    aff = 0.7 + 0.05 * x[None, :] - 0.03 * x[:, None]
+    img = orc.lattice_to_image(aff, N)
+    X = np.arange(N)
+    g = (X - N // 2) * (L / N) + L // 2
+    inner_px = g <= L - 1
+    exp = 0.7 + 0.05 * g[None, :] - 0.03 * g[:, None]
+    sel = np.ix_(inner_px, inner_px)
+    assert np.abs(img[sel] - exp[sel]).max() < 1e-13
