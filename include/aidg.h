@@ -24,7 +24,8 @@
  *   u_k = uvw_m[b][t][0] f_c / c (metres to wavelengths), likewise v, w.
  *   Polarisations are the 2x2 row-major Jones layout [[XX, XY], [YX, YY]];
  *   V_pq = A_p B A_q^H.  Gridding applies A^H (the adjoint of degridding); for
- *   unitary A (phase screens) this equals the paper's A^-1 of Eq. withw.
+ *   unitary A (phase screens) this equals the paper's A^-1 of Eq. withw, which
+ *   the geometry's aterm_mode = 1 selects for any A (normalised, Sec. 3.3).
  *   The taper is the separable Kaiser-Bessel window of Sec. 4.2,
  *   T(x,y) = t(x) t(y), t(x) = I0(beta sqrt(1 - (2 (x - L/2)/L)^2)) / I0(beta).
  *   Subgrid DFTs are unnormalised; all image-domain scaling is left to the caller.
@@ -61,7 +62,7 @@
 extern "C" {
 #endif
 
-#define AIDG_ABI_VERSION 3
+#define AIDG_ABI_VERSION 4
 
 typedef enum {
   AIDG_OK = 0,
@@ -75,7 +76,7 @@ typedef enum {
 
 enum { AIDG_FP32 = 0, AIDG_FP64 = 1 };
 
-/* Imaging geometry and numerics of a plan. */
+/* Imaging geometry and numerics of a plan.  80 bytes. */
 typedef struct {
   int32_t grid_size;       /* N: even, >= subgrid_size */
   int32_t subgrid_size;    /* L: 32, 64 or 96 */
@@ -109,6 +110,17 @@ typedef struct {
                               Degridding of a fold-mode plan is exact for Hermitian
                               brightness (any physical sky); the image of a fold-mode grid
                               has the right Hermitian part.  0: no fold (default) */
+  int32_t aterm_mode;      /* A-term of gridding (Sec. 3.3, A-term application).
+                              0 (default): A_p^H S A_q, the exact adjoint of degridding.
+                              1 (inverse): the paper's A^-1 of Eq. withw, normalised:
+                              S' = T f A_p^-1 S A_q^-H with f = 1 / ||A_p^-1 A_q^-H||_F
+                              per pixel (f = 0 where an A-term is singular), and
+                              aidg_invert divides the image by the bilinear interpolation
+                              (periodic over the field) of the weighted-average map
+                              M(x, y) = sum_s nvis_s f_s(x, y) / sum_s nvis_s over the
+                              plan's subgrids (0 where M interpolates to 0).  Degridding
+                              and aidg_predict are the same in both modes, so in mode 1
+                              gridding is not the adjoint of degridding */
   int64_t workspace_bytes; /* device budget for the group images of one batch
                               (4 L^2 complex each); 0 = 2 GiB */
 } aidg_geometry;
@@ -183,8 +195,15 @@ aidg_status aidg_plan_subgrids(const aidg_plan* plan, aidg_subgrid* out, int64_t
 /* Copy the w of each layer (cap entries at most) to host memory. */
 aidg_status aidg_plan_wlayers(const aidg_plan* plan, double* w0, int32_t cap);
 
-/* Replace the plan's A-terms (device buffer, same layout and precision). */
+/* Replace the plan's A-terms (device buffer, same layout and precision).  In the
+ * inverse A-term mode this also recomputes the inverse planes and the normalisation
+ * map on hip_stream. */
 aidg_status aidg_plan_set_aterms(aidg_plan* plan, const void* aterms, void* hip_stream);
+
+/* Inverse A-term mode: copy the weighted-average normalisation map M [L][L] (y major,
+ * FP64, see aterm_mode) to host memory; cap entries at most.  Waits for the plan's
+ * queued work.  AIDG_E_INVALID for a plan in the adjoint mode. */
+aidg_status aidg_plan_aterm_norm(aidg_plan* plan, double* out, int64_t cap);
 
 /* Gridding: ACCUMULATE the plan's visibilities into grid (both device). */
 aidg_status aidg_grid(aidg_plan* plan, const void* vis, void* grid, void* hip_stream);

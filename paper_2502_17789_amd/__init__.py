@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libaidg.so")
 AIDG_OK, AIDG_E_INVALID, AIDG_E_NOMEM, AIDG_E_DEVICE, AIDG_E_UNSUPPORTED, AIDG_E_RANGE, AIDG_E_BUSY = range(7)
 STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "NOMEM", 3: "DEVICE", 4: "UNSUPPORTED", 5: "RANGE", 6: "BUSY"}
 FP32, FP64 = 0, 1
+ATERM_ADJOINT, ATERM_INVERSE = 0, 1  # A-term of gridding: A^H (adjoint of degridding) or normalised A^-1
 
 # aidg_subgrid (64 bytes), see include/aidg.h
 SUBGRID_DTYPE = np.dtype([
@@ -41,7 +42,8 @@ class _Geometry(ctypes.Structure):
                 ("taper_beta", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("reseed_channels", ctypes.c_int32), ("strict_range", ctypes.c_int32),
                 ("max_subgrid_vis", ctypes.c_int32), ("center_lattice", ctypes.c_int32),
-                ("w_fold", ctypes.c_int32), ("workspace_bytes", ctypes.c_int64)]
+                ("w_fold", ctypes.c_int32), ("aterm_mode", ctypes.c_int32),
+                ("workspace_bytes", ctypes.c_int64)]
 
 
 class _PlanInfo(ctypes.Structure):
@@ -88,16 +90,17 @@ class Geometry:
     workspace_bytes: int = 0
     center_lattice: int = 0
     w_fold: int = 0
+    aterm_mode: int = ATERM_ADJOINT
 
     def to_c(self) -> _Geometry:
         return _Geometry(self.grid_size, self.subgrid_size, self.kernel_support, self.aterm_interval,
                          self.pixel_scale, self.w_step, self.taper_beta, self.precision,
                          self.reseed_channels, self.strict_range, self.max_subgrid_vis,
-                         self.center_lattice, self.w_fold, self.workspace_bytes)
+                         self.center_lattice, self.w_fold, self.aterm_mode, self.workspace_bytes)
 
 
 _lib = None
-ABI_VERSION = 3  # the structure layouts above follow include/aidg.h at this version
+ABI_VERSION = 4  # the structure layouts above follow include/aidg.h at this version
 
 
 def library() -> ctypes.CDLL:
@@ -118,6 +121,7 @@ def library() -> ctypes.CDLL:
         "aidg_plan_subgrids": (I32, [P, P, I64]),
         "aidg_plan_wlayers": (I32, [P, P, I32]),
         "aidg_plan_set_aterms": (I32, [P, P, P]),
+        "aidg_plan_aterm_norm": (I32, [P, P, I64]),
         "aidg_grid": (I32, [P, P, P, P]),
         "aidg_degrid": (I32, [P, P, P, P]),
         "aidg_plan_set_profiling": (I32, [P, I32]),
@@ -242,6 +246,14 @@ class Plan:
         n_int = (self.nt + self.geometry.aterm_interval - 1) // self.geometry.aterm_interval
         self._check_tensor(aterms, (n_int, self.n_stations, L, L, 4), "aterms")
         _check(library().aidg_plan_set_aterms(self._h, _dptr(aterms), _stream_handle(stream)))
+
+    def aterm_norm(self):
+        """Inverse A-term mode: the weighted-average normalisation map [L, L] (float64,
+        host) that ``invert`` divides the image by (after bilinear interpolation)."""
+        L = self.geometry.subgrid_size
+        out = np.zeros((L, L), np.float64)
+        _check(library().aidg_plan_aterm_norm(self._h, out.ctypes.data_as(ctypes.c_void_p), L * L))
+        return out
 
     def grid(self, vis, out=None, stream=None):
         """Grid ``vis`` [nbl, nt, nc, 4]; accumulates into ``out`` (zeros if None)."""

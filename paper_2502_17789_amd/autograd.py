@@ -15,10 +15,21 @@ adjoint of imaging I = P^H(G) (Eq. wstack), so
     PredictFn.backward(gG) = invert(gG)    InvertFn.backward(gI) = predict(gI),
 and ``predict_vis`` (image -> visibilities, degrid after predict) is differentiable
 end to end.
+
+A plan in the inverse A-term mode grids with normalised A^-1 and divides its image by
+the normalisation map: neither is the adjoint of degridding or prediction, so these
+functions refuse such plans.
 """
 from __future__ import annotations
 
 import torch
+
+
+def _adjoint_plan(plan):
+    if getattr(plan.geometry, "aterm_mode", 0) != 0:
+        raise ValueError("autograd needs a plan in the adjoint A-term mode (aterm_mode = 0): "
+                         "inverse-mode gridding is not the adjoint of degridding")
+    return plan
 
 
 class DegridFn(torch.autograd.Function):
@@ -26,7 +37,7 @@ class DegridFn(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, grid: torch.Tensor, plan) -> torch.Tensor:
-        ctx.plan = plan
+        ctx.plan = _adjoint_plan(plan)
         return plan.degrid(grid.contiguous())
 
     @staticmethod
@@ -43,7 +54,7 @@ class GridFn(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, vis: torch.Tensor, plan) -> torch.Tensor:
-        ctx.plan = plan
+        ctx.plan = _adjoint_plan(plan)
         return plan.grid(vis.contiguous())
 
     @staticmethod
@@ -68,7 +79,7 @@ class PredictFn(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, image: torch.Tensor, plan) -> torch.Tensor:
-        ctx.plan = plan
+        ctx.plan = _adjoint_plan(plan)
         return plan.predict(image.contiguous())
 
     @staticmethod
@@ -84,7 +95,7 @@ class InvertFn(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, grid: torch.Tensor, plan) -> torch.Tensor:
-        ctx.plan = plan
+        ctx.plan = _adjoint_plan(plan)
         return plan.invert(grid.contiguous())
 
     @staticmethod

@@ -39,7 +39,7 @@ static_assert(sizeof(SubgridDev) == 96, "SubgridDev layout");
 
 // Geometry after validation, with derived quantities.
 struct Geometry {
-  int N, L, K, aterm_interval, precision, R, strict, max_sg_vis, lattice, fold;
+  int N, L, K, aterm_interval, precision, R, strict, max_sg_vis, lattice, fold, amode;
   double dl, fov, du, beta, w_step;
   int64_t workspace;
 };
@@ -69,6 +69,7 @@ struct KernelArgs {
   const double* uvw;        // device [nbl][nt][3] metres
   const double* fc;         // device [nc] f / c
   const void* aterms;       // device [n_int][n_st][L][L][4]
+  const void* ainvh;        // device (A^-1)^H planes of the inverse A-term mode, else null
   const void* taper;        // device [L][L] taper times (-1)^(x+y)
   const void* twiddle;      // device [L] exp(-2 pi i k / L)
   const int64_t* grp_begin; // device [n_groups + 1]: first subgrid of each (layer, centre) group
@@ -131,6 +132,15 @@ int launch_image_fft_rows(int precision, int dir, bool predict, const void* src,
                           double w0, double inv_l2, void* stream);
 int launch_image_transpose(int precision, const void* src, void* dst, int N, void* stream);
 int launch_image_wstack(int precision, const void* B, void* img, int N, const double* itaper, double dl,
-                        double w0, double inv_l2, int assign, void* stream);
+                        double w0, double inv_l2, int assign, const double* nmap, int L, void* stream);
+
+// Inverse A-term mode (aterm.hip): (A^-1)^H of n 2x2 matrices, and the weighted-average
+// normalisation map [L2] from (A_p plane, A_q plane) pairs [n_pairs][2] with their
+// visibility counts, summed in n_chunks chunks of chunk_len pairs through partial
+// [n_chunks][L2].
+int launch_aterm_inverse_h(int precision, const void* A, void* B, int64_t n, void* stream);
+int launch_aterm_norm(int precision, const void* B, const int32_t* pairs, const double* count, int64_t n_pairs,
+                      int n_chunks, int64_t chunk_len, int L2, double inv_total, double* partial, double* map,
+                      void* stream);
 
 }  // namespace aidg

@@ -84,6 +84,17 @@ struct aidg_plan {
   bool img_ok = false;
   void* d_img_tw = nullptr;
   double* d_img_itaper = nullptr;
+  // inverse A-term mode: (A^-1)^H planes for the gridder, the distinct (A_p plane,
+  // A_q plane) pairs of the table [n][2] with their visibility counts, the partial sums
+  // [chunks][L^2] and the weighted-average normalisation map [L^2]
+  void* d_ainvh = nullptr;
+  int32_t* d_npairs = nullptr;
+  double* d_ncount = nullptr;
+  double* d_npartial = nullptr;
+  double* d_nmap = nullptr;
+  int64_t n_pairs = 0, pair_chunk = 1;
+  int n_chunks = 1;
+  double n_total = 0.0;
   hipEvent_t last = nullptr;
   std::atomic<bool> busy{false};
   // profiling: events around each kernel launch
@@ -104,6 +115,7 @@ struct aidg_plan {
     a.uvw = d_uvw;
     a.fc = d_fc;
     a.aterms = d_aterms;
+    a.ainvh = d_ainvh;
     a.taper = d_taper;
     a.twiddle = d_tw;
     a.grp_begin = d_grp;
@@ -123,8 +135,9 @@ struct aidg_plan {
   bool async_mem = false;
 
   void release() {
-    void* ptrs[] = {d_sg,      d_uvw,  d_fc,   d_aterms, d_taper,  d_tw,
-                    d_scratch, d_excl, d_grp,  d_args,   d_img_tw, d_img_itaper};
+    void* ptrs[] = {d_sg,     d_uvw,       d_fc,    d_aterms,  d_taper,    d_tw,     d_scratch,
+                    d_excl,   d_grp,       d_args,  d_img_tw,  d_img_itaper, d_ainvh, d_npairs,
+                    d_ncount, d_npartial,  d_nmap};
     hipStream_t fs = async_mem ? release_stream(device) : nullptr;
     int cur = device;
     if (fs) {
@@ -152,6 +165,9 @@ struct aidg_plan {
     d_args = nullptr;
     d_img_tw = nullptr;
     d_img_itaper = nullptr;
+    d_ainvh = nullptr;
+    d_npairs = nullptr;
+    d_ncount = d_npartial = d_nmap = nullptr;
     last = nullptr;
   }
 };
@@ -235,6 +251,19 @@ aidg_status dalloc(T** p, size_t bytes, aidg_plan* plan, const char* what, hipSt
   *p = reinterpret_cast<T*>(q);
   plan->device_bytes += n;
   return AIDG_OK;
+}
+
+// Inverse A-term mode: recompute the (A^-1)^H planes and the normalisation map from
+// the plan's A-terms, on stream.
+aidg_status refresh_inverse_aterms(aidg_plan* p, hipStream_t stream) {
+  if (!p->g.amode) return AIDG_OK;
+  const int64_t n = (int64_t)p->n_int * p->n_st * p->g.L * p->g.L;
+  int rc = launch_aterm_inverse_h(p->g.precision, p->d_aterms, p->d_ainvh, n, stream);
+  if (rc == 0)
+    rc = launch_aterm_norm(p->g.precision, p->d_ainvh, p->d_npairs, p->d_ncount, p->n_pairs, p->n_chunks,
+                           p->pair_chunk, p->g.L * p->g.L, p->n_total > 0 ? 1.0 / p->n_total : 0.0,
+                           p->d_npartial, p->d_nmap, stream);
+  return rc == 0 ? AIDG_OK : hip_fail((hipError_t)rc, "inverse A-term kernels");
 }
 
 }  // namespace
@@ -463,6 +492,24 @@ aidg_status aidg_plan_create(const aidg_geometry* geo, int32_t n_stations, int32
       d.dfc = df * inv_c;
       d.R = uniform ? g.R : 1;
     }
+    // inverse A-term mode: distinct (A_p plane, A_q plane) pairs with their visibility
+    // counts, for the normalisation map
+    std::vector<int32_t> pairs;
+    std::vector<double> pair_count;
+    if (g.amode) {
+      std::map<std::pair<int32_t, int32_t>, double> cnt;
+      for (const SubgridDev& d : dev) cnt[{d.ap, d.aq}] += (double)d.nt * d.nc;
+      for (const auto& kv : cnt) {
+        pairs.push_back(kv.first.first);
+        pairs.push_back(kv.first.second);
+        pair_count.push_back(kv.second);
+        plan->n_total += kv.second;
+      }
+      plan->n_pairs = (int64_t)pair_count.size();
+      // about 64 pairs per chunk and at most 64 chunks
+      plan->n_chunks = (int)std::max<int64_t>(1, std::min<int64_t>(64, (plan->n_pairs + 63) / 64));
+      plan->pair_chunk = std::max<int64_t>(1, (plan->n_pairs + plan->n_chunks - 1) / plan->n_chunks);
+    }
     std::vector<double> fc(n_chans);
     for (int c = 0; c < n_chans; ++c) fc[c] = freqs_hz[c] * inv_c;
     const int L = g.L;
@@ -535,7 +582,14 @@ aidg_status aidg_plan_create(const aidg_geometry* geo, int32_t n_stations, int32
         (st = dalloc(&plan->d_args, sizeof(KernelArgs), plan, "launch parameters", stream)) ||
         (plan->img_ok &&
          ((st = dalloc(&plan->d_img_tw, (size_t)g.N * plan->elem, plan, "image twiddles", stream)) ||
-          (st = dalloc(&plan->d_img_itaper, (size_t)g.N * sizeof(double), plan, "image taper", stream))))) {
+          (st = dalloc(&plan->d_img_itaper, (size_t)g.N * sizeof(double), plan, "image taper", stream)))) ||
+        (g.amode &&
+         ((st = dalloc(&plan->d_ainvh, plan->aterm_bytes, plan, "inverse A-terms", stream)) ||
+          (st = dalloc(&plan->d_npairs, pairs.size() * sizeof(int32_t), plan, "A-term pairs", stream)) ||
+          (st = dalloc(&plan->d_ncount, pair_count.size() * sizeof(double), plan, "pair counts", stream)) ||
+          (st = dalloc(&plan->d_npartial, (size_t)plan->n_chunks * L * L * sizeof(double), plan,
+                       "normalisation partial sums", stream)) ||
+          (st = dalloc(&plan->d_nmap, (size_t)L * L * sizeof(double), plan, "normalisation map", stream))))) {
       abandon();
       return st;
     }
@@ -561,6 +615,8 @@ aidg_status aidg_plan_create(const aidg_geometry* geo, int32_t n_stations, int32
          plan->img_ok ? (size_t)g.N * plan->elem : 0, hipMemcpyHostToDevice},
         {plan->d_img_itaper, img_t.data(), plan->img_ok ? (size_t)g.N * sizeof(double) : 0,
          hipMemcpyHostToDevice},
+        {plan->d_npairs, pairs.data(), pairs.size() * sizeof(int32_t), hipMemcpyHostToDevice},
+        {plan->d_ncount, pair_count.data(), pair_count.size() * sizeof(double), hipMemcpyHostToDevice},
     };
     for (const Copy& c : copies) {
       if (!c.n) continue;
@@ -569,6 +625,10 @@ aidg_status aidg_plan_create(const aidg_geometry* geo, int32_t n_stations, int32
         abandon();
         return hip_fail(e, "hipMemcpyAsync (plan upload)");
       }
+    }
+    if ((st = refresh_inverse_aterms(plan, stream)) != AIDG_OK) {
+      abandon();
+      return st;
     }
     if ((e = hipEventCreateWithFlags(&plan->last, hipEventDisableTiming)) != hipSuccess ||
         (e = hipEventRecord(plan->last, stream)) != hipSuccess ||
@@ -628,8 +688,22 @@ aidg_status aidg_plan_set_aterms(aidg_plan* plan, const void* aterms, void* hip_
   hipError_t e = hipStreamWaitEvent(st, plan->last, 0);
   if (e == hipSuccess)
     e = hipMemcpyAsync(plan->d_aterms, aterms, plan->aterm_bytes, hipMemcpyDeviceToDevice, st);
-  if (e == hipSuccess) e = hipEventRecord(plan->last, st);
-  return e == hipSuccess ? AIDG_OK : hip_fail(e, "A-term copy");
+  if (e != hipSuccess) return hip_fail(e, "A-term copy");
+  const aidg_status r = refresh_inverse_aterms(plan, st);
+  if (r != AIDG_OK) return r;
+  e = hipEventRecord(plan->last, st);
+  return e == hipSuccess ? AIDG_OK : hip_fail(e, "hipEventRecord");
+}
+
+aidg_status aidg_plan_aterm_norm(aidg_plan* plan, double* out, int64_t cap) {
+  if (!plan || (!out && cap > 0)) return fail(AIDG_E_INVALID, "NULL plan or output");
+  if (!plan->g.amode) return fail(AIDG_E_INVALID, "the plan is in the adjoint A-term mode (no normalisation)");
+  BusyGuard guard(plan);
+  if (!guard.ok) return fail(AIDG_E_BUSY, "plan in use by another thread");
+  hipError_t e = hipEventSynchronize(plan->last);
+  const int64_t n = std::min<int64_t>(cap, (int64_t)plan->g.L * plan->g.L);
+  if (e == hipSuccess && n > 0) e = hipMemcpy(out, plan->d_nmap, (size_t)n * sizeof(double), hipMemcpyDeviceToHost);
+  return e == hipSuccess ? AIDG_OK : hip_fail(e, "normalisation map copy");
 }
 
 aidg_status aidg_grid(aidg_plan* plan, const void* vis, void* grid, void* hip_stream) {
@@ -710,7 +784,8 @@ aidg_status aidg_invert(aidg_plan* plan, const void* grid, void* image, void* wo
         });
       if (r == AIDG_OK)
         r = image_step(plan, st, kImageWstack, [&] {
-          return launch_image_wstack(prec, B, img, N, plan->d_img_itaper, dl, plan->w0[w], inv_l2, w == 0, st);
+          return launch_image_wstack(prec, B, img, N, plan->d_img_itaper, dl, plan->w0[w], inv_l2, w == 0,
+                                     plan->d_nmap, plan->g.L, st);
         });
     }
   }

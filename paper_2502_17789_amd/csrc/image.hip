@@ -11,7 +11,8 @@
 //   image_transpose 32 x 32 tiles through LDS.
 //   image_wstack    a transposing tile pass that adds one layer's transform times
 //                   exp(+2 pi i w0 n1) / (L^2 T) into the image (or stores it, for
-//                   the first layer).
+//                   the first layer); with the inverse A-term mode's normalisation
+//                   map, also divided by that map's bilinear interpolation.
 // For even N, (-1)^k FFT[(-1)^x a](k) is the centred transform times (-1)^(N/2); the
 // sign cancels between the two passes of a plane.
 #include <hip/hip_runtime.h>
@@ -176,6 +177,21 @@ __global__ __launch_bounds__(256) void image_transpose(const V2* __restrict__ sr
   }
 }
 
+// Bilinear interpolation of an L x L lattice map [y][x] at image pixel (X, Y), periodic
+// over the field: pixel X sits at lattice coordinate (X - N/2) L / N + L/2.
+__device__ __forceinline__ double lattice_bilinear(const double* __restrict__ M, int L, int N, int X, int Y) {
+  const double sc = (double)L / (double)N;
+  const double gx = (double)(X - N / 2) * sc + (double)(L / 2);
+  const double gy = (double)(Y - N / 2) * sc + (double)(L / 2);
+  const double flx = floor(gx), fly = floor(gy);
+  const double fx = gx - flx, fy = gy - fly;
+  const int x0 = (((int)flx % L) + L) % L, y0 = (((int)fly % L) + L) % L;
+  const int x1 = x0 + 1 == L ? 0 : x0 + 1, y1 = y0 + 1 == L ? 0 : y0 + 1;
+  const double r0 = M[y0 * L + x0] * (1.0 - fx) + M[y0 * L + x1] * fx;
+  const double r1 = M[y1 * L + x0] * (1.0 - fx) + M[y1 * L + x1] * fx;
+  return r0 * (1.0 - fy) + r1 * fy;
+}
+
 // One layer of Eq. wstack: img[Y][X] (+)= B[X][Y] * wterm(X, Y) with sign +1.  B is
 // the layer's transform with rows X (the second row pass ran along v); tiles are
 // read along Y and written along X.
@@ -183,7 +199,8 @@ template <typename R>
 __global__ __launch_bounds__(256) void image_wstack(const typename C2<R>::T* __restrict__ B,
                                                     typename C2<R>::T* __restrict__ img, int N,
                                                     const double* __restrict__ itaper, double dl,
-                                                    double w0, double inv_l2, int assign) {
+                                                    double w0, double inv_l2, int assign,
+                                                    const double* __restrict__ nmap, int L) {
   using V2 = typename C2<R>::T;
   __shared__ V2 tile[kTile][kTile + 1];
   const int bx = blockIdx.x * kTile, by = blockIdx.y * kTile;  // X and Y ranges
@@ -196,7 +213,12 @@ __global__ __launch_bounds__(256) void image_wstack(const typename C2<R>::T* __r
   for (int j = ty; j < kTile; j += 256 / kTile) {
     const int Y = by + j, X = bx + tx;
     if (X < N && Y < N) {
-      const V2 v = cmul<R>(tile[tx][j], wterm<R>(X, Y, N, dl, w0, itaper, inv_l2, 1.0));
+      V2 v = cmul<R>(tile[tx][j], wterm<R>(X, Y, N, dl, w0, itaper, inv_l2, 1.0));
+      if (nmap) {  // inverse A-term mode: divide by the normalisation (0 where it is 0)
+        const double c = lattice_bilinear(nmap, L, N, X, Y);
+        const R f = c > 0.0 ? (R)(1.0 / c) : (R)0;
+        v = V2{v.x * f, v.y * f};
+      }
       V2* o = img + (size_t)Y * N + X;
       *o = assign ? v : V2{o->x + v.x, o->y + v.y};
     }
@@ -248,17 +270,17 @@ int launch_image_transpose(int precision, const void* src, void* dst, int N, voi
 }
 
 int launch_image_wstack(int precision, const void* B, void* img, int N, const double* itaper, double dl,
-                        double w0, double inv_l2, int assign, void* stream) {
+                        double w0, double inv_l2, int assign, const double* nmap, int L, void* stream) {
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const dim3 grid((N + kTile - 1) / kTile, (N + kTile - 1) / kTile);
   if (precision == AIDG_FP64)
     hipLaunchKernelGGL((image_wstack<double>), grid, dim3(256), 0, st,
                        reinterpret_cast<const double2*>(B), reinterpret_cast<double2*>(img), N, itaper,
-                       dl, w0, inv_l2, assign);
+                       dl, w0, inv_l2, assign, nmap, L);
   else
     hipLaunchKernelGGL((image_wstack<float>), grid, dim3(256), 0, st,
                        reinterpret_cast<const float2*>(B), reinterpret_cast<float2*>(img), N, itaper,
-                       dl, w0, inv_l2, assign);
+                       dl, w0, inv_l2, assign, nmap, L);
   return (int)hipGetLastError();
 }
 

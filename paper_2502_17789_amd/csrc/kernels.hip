@@ -205,7 +205,10 @@ __global__ __launch_bounds__(kThreads) void grid_dft(const Group g) {
   const KernelArgs& a = gs.a;
   const R* __restrict__ vis = reinterpret_cast<const R*>(gs.in);
   R* __restrict__ scratch = reinterpret_cast<R*>(g.scratch);
-  const V2* At = reinterpret_cast<const V2*>(a.aterms);
+  // Inverse A-term mode: the planes are B = (A^-1)^H, so that B_p^H S B_q is
+  // A_p^-1 S A_q^-H, scaled by 1 / ||B_p^H B_q||_F (Sec. 3.3)
+  const bool inv = a.ainvh != nullptr;
+  const V2* At = reinterpret_cast<const V2*>(inv ? a.ainvh : a.aterms);
 
   // The group's image, sum over its subgrids of T (-1)^(x+y) A_p^H S A_q, builds up
   // in its scratch slot; each lane owns its pixels there, so it reads back only
@@ -330,7 +333,15 @@ __global__ __launch_bounds__(kThreads) void grid_dft(const Group g) {
       const V2 t1 = cmul<R>(a0, s1) + cmul<R>(a2, s3);
       const V2 t2 = cmul<R>(a1, s0) + cmul<R>(a3, s2);
       const V2 t3 = cmul<R>(a1, s1) + cmul<R>(a3, s3);
-      const R w = taper[pix];
+      R w = taper[pix];
+      if (inv) {
+        // ||B_p^H B_q||_F^2 with B_p^H = [[a0, a2], [a1, a3]] (a already conjugated)
+        const V2 m0 = cmul<R>(a0, b0) + cmul<R>(a2, b2), m1 = cmul<R>(a0, b1) + cmul<R>(a2, b3);
+        const V2 m2 = cmul<R>(a1, b0) + cmul<R>(a3, b2), m3 = cmul<R>(a1, b1) + cmul<R>(a3, b3);
+        const R n2 = m0.x * m0.x + m0.y * m0.y + m1.x * m1.x + m1.y * m1.y + m2.x * m2.x + m2.y * m2.y +
+                     m3.x * m3.x + m3.y * m3.y;
+        w = n2 > (R)0 ? w / sqrt(n2) : (R)0;
+      }
       V2 c[4] = {(cmul<R>(t0, b0) + cmul<R>(t1, b2)) * w, (cmul<R>(t0, b1) + cmul<R>(t1, b3)) * w,
                  (cmul<R>(t2, b0) + cmul<R>(t3, b2)) * w, (cmul<R>(t2, b1) + cmul<R>(t3, b3)) * w};
 #pragma unroll

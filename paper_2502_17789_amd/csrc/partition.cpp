@@ -76,6 +76,11 @@ aidg_status validate_geometry(const aidg_geometry* g, Geometry* o, std::string* 
     return AIDG_E_INVALID;
   }
   o->fold = g->w_fold;
+  if (g->aterm_mode != 0 && g->aterm_mode != 1) {
+    *err = "aterm_mode must be 0 (adjoint) or 1 (inverse)";
+    return AIDG_E_INVALID;
+  }
+  o->amode = g->aterm_mode;
   if (g->center_lattice > 0) {
     o->lattice = g->center_lattice;
   } else {

@@ -79,7 +79,8 @@ def test_auto_w_step_formula():
 @pytest.mark.parametrize("bad", [dict(subgrid_size=33), dict(kernel_support=32), dict(grid_size=30),
                                  dict(pixel_scale=-1.0), dict(aterm_interval=0),
                                  dict(pixel_scale=math.radians(120) / 512), dict(max_subgrid_vis=2049),
-                                 dict(max_subgrid_vis=-1), dict(center_lattice=-2), dict(w_fold=2)])
+                                 dict(max_subgrid_vis=-1), dict(center_lattice=-2), dict(w_fold=2),
+                                 dict(aterm_mode=2)])
 def test_invalid_geometry_rejected(bad):
     kw = dict(grid_size=512, subgrid_size=32, kernel_support=8, pixel_scale=math.radians(10) / 512)
     kw.update(bad)
@@ -120,3 +121,15 @@ def test_partition_valid_mwa_full_size(orc):
     occ = table["nt"] * table["nc"]
     assert occ.sum() == wl.n_vis
     assert 5e4 < table.shape[0] < 5e5
+
+
+def test_autograd_refuses_the_inverse_aterm_mode():
+    """Inverse-mode gridding is not the adjoint of degridding: the differentiable
+    wrappers refuse such plans before touching the device."""
+    import types
+    from paper_2502_17789_amd import autograd
+    geo = aidg.Geometry(64, 32, 8, 1e-3, aterm_mode=aidg.ATERM_INVERSE)
+    with pytest.raises(ValueError):
+        autograd._adjoint_plan(types.SimpleNamespace(geometry=geo))
+    ok = types.SimpleNamespace(geometry=aidg.Geometry(64, 32, 8, 1e-3))
+    assert autograd._adjoint_plan(ok) is ok
