@@ -107,6 +107,8 @@ def parse():
     ap.add_argument("--image-wmax", type=float, nargs="+", default=[0.0, 250.0])
     ap.add_argument("--image-fold", type=int, nargs="+", default=[0, 1],
                     help="image mode: w_fold settings to run at max |w| > 0")
+    ap.add_argument("--aterm-mode", type=int, choices=[0, 1], default=0,
+                    help="A-term of gridding: 0 adjoint (A^H), 1 the paper's normalised A^-1")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device-to-device 3 times (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -124,7 +126,7 @@ def workload_description(wl, info):
     }
 
 
-def cpu_baseline(wl, n_bl: int):
+def cpu_baseline(wl, n_bl: int, aterm_mode: int = 0):
     """FP64 oracle (test infrastructure) on a fixed random subset of baselines."""
     import oracle
     import synth
@@ -137,7 +139,7 @@ def cpu_baseline(wl, n_bl: int):
     table = oracle.partition(sub, 0.0)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     t0 = time.perf_counter()
-    G = oracle.grid(sub, V, table, nthreads=threads)
+    G = oracle.grid(sub, V, table, nthreads=threads, aterm_mode=aterm_mode)
     t1 = time.perf_counter()
     oracle.degrid(sub, G, table, nthreads=threads)
     t2 = time.perf_counter()
@@ -417,7 +419,7 @@ def image_bench(args):
         ha = synth.hour_angle_for_wmax(wmax) if wmax > 0 else 0.0
         wl = synth.config_mwa(seed=2, ha0_rad=ha)
         geo = aidg.Geometry(wl.grid_size, wl.subgrid_size, wl.kernel_support, wl.pixel_scale,
-                            aterm_interval=wl.aterm_interval, w_fold=fold)
+                            aterm_interval=wl.aterm_interval, w_fold=fold, aterm_mode=args.aterm_mode)
         A = torch.from_numpy(wl.aterms.astype(np.complex64)).cuda()
         with aidg.Plan(geo, wl.n_stations, wl.baselines, wl.uvw, wl.freqs, A) as plan:
             del A
@@ -455,7 +457,8 @@ def image_bench(args):
         dom = max(by, key=lambda k: kt[k]["ms"])
         print(json.dumps({
             "image_level": {"grid_size": N, "n_wlayers": W, "max_abs_w_lambda": wmax or "transit",
-                            "w_fold": fold, "precision": "fp32", "plane_bytes": P},
+                            "w_fold": fold, "aterm_mode": args.aterm_mode, "precision": "fp32",
+                            "plane_bytes": P},
             "invert_ms": round(t_inv, 3), "predict_ms": round(t_pred, 3),
             "classes": cls,
             "roofline": {"kernel": dom, "bound": "hbm", "achieved": cls[dom]["gb_s"], "peak": 8000.0,
@@ -518,7 +521,7 @@ def main():
     torch.cuda.set_device(0)
     wl = synth.config_mwa(seed=2)
     geo = aidg.Geometry(wl.grid_size, wl.subgrid_size, wl.kernel_support, wl.pixel_scale,
-                        aterm_interval=wl.aterm_interval)
+                        aterm_interval=wl.aterm_interval, aterm_mode=args.aterm_mode)
     A = torch.from_numpy(wl.aterms.astype(np.complex64)).cuda()
     t0 = time.perf_counter()
     plan = aidg.Plan(geo, wl.n_stations, wl.baselines, wl.uvw, wl.freqs, A)
@@ -589,7 +592,8 @@ def main():
         "ms_per_step": round(ms_per_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": workload_description(wl, info),
+        "config": {**workload_description(wl, info),
+                   "aterm_mode": "inverse (normalised A^-1)" if args.aterm_mode else "adjoint (A^H)"},
         "grid_mvis_s": round(n / (np.median(t_grid) * 1e-3) / 1e6, 3),
         "degrid_mvis_s": round(n / (np.median(t_degrid) * 1e-3) / 1e6, 3),
         "latency_ms": {"p50": round(float(np.percentile(t_job, 50)), 3),
@@ -603,7 +607,7 @@ def main():
     plan.close()
     del V, G, Vout, A
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_baselines)
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_baselines, args.aterm_mode)
     print(json.dumps(out), flush=True)
 
 

@@ -785,7 +785,7 @@ aidg_status aidg_invert(aidg_plan* plan, const void* grid, void* image, void* wo
       if (r == AIDG_OK)
         r = image_step(plan, st, kImageWstack, [&] {
           return launch_image_wstack(prec, B, img, N, plan->d_img_itaper, dl, plan->w0[w], inv_l2, w == 0,
-                                     plan->d_nmap, plan->g.L, st);
+                                     w == plan->W - 1 ? plan->d_nmap : nullptr, plan->g.L, st);
         });
     }
   }

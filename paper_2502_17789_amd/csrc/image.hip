@@ -11,8 +11,9 @@
 //   image_transpose 32 x 32 tiles through LDS.
 //   image_wstack    a transposing tile pass that adds one layer's transform times
 //                   exp(+2 pi i w0 n1) / (L^2 T) into the image (or stores it, for
-//                   the first layer); with the inverse A-term mode's normalisation
-//                   map, also divided by that map's bilinear interpolation.
+//                   the first layer); in the last layer's pass of the inverse A-term
+//                   mode, the sum is divided by the normalisation map's bilinear
+//                   interpolation.
 // For even N, (-1)^k FFT[(-1)^x a](k) is the centred transform times (-1)^(N/2); the
 // sign cancels between the two passes of a plane.
 #include <hip/hip_runtime.h>
@@ -178,18 +179,18 @@ __global__ __launch_bounds__(256) void image_transpose(const V2* __restrict__ sr
 }
 
 // Bilinear interpolation of an L x L lattice map [y][x] at image pixel (X, Y), periodic
-// over the field: pixel X sits at lattice coordinate (X - N/2) L / N + L/2.
-__device__ __forceinline__ double lattice_bilinear(const double* __restrict__ M, int L, int N, int X, int Y) {
-  const double sc = (double)L / (double)N;
-  const double gx = (double)(X - N / 2) * sc + (double)(L / 2);
-  const double gy = (double)(Y - N / 2) * sc + (double)(L / 2);
-  const double flx = floor(gx), fly = floor(gy);
-  const double fx = gx - flx, fy = gy - fly;
-  const int x0 = (((int)flx % L) + L) % L, y0 = (((int)fly % L) + L) % L;
+// over the field: pixel X sits at lattice coordinate g = (X - N/2) L / N + L/2, i.e.
+// g N = (X - N/2) L + (L/2) N, an integer in [0, L N); its quotient by N is the lower
+// lattice point (the upper one wraps to 0 past L - 1) and its remainder the weight.
+template <typename R>
+__device__ __forceinline__ R lattice_bilinear(const double* __restrict__ M, int L, int N, R inv_n, int X, int Y) {
+  const int nx = (X - N / 2) * L + (L / 2) * N, ny = (Y - N / 2) * L + (L / 2) * N;
+  const int x0 = nx / N, y0 = ny / N;
+  const R fx = (R)(nx - x0 * N) * inv_n, fy = (R)(ny - y0 * N) * inv_n;
   const int x1 = x0 + 1 == L ? 0 : x0 + 1, y1 = y0 + 1 == L ? 0 : y0 + 1;
-  const double r0 = M[y0 * L + x0] * (1.0 - fx) + M[y0 * L + x1] * fx;
-  const double r1 = M[y1 * L + x0] * (1.0 - fx) + M[y1 * L + x1] * fx;
-  return r0 * (1.0 - fy) + r1 * fy;
+  const R r0 = (R)M[y0 * L + x0] * ((R)1 - fx) + (R)M[y0 * L + x1] * fx;
+  const R r1 = (R)M[y1 * L + x0] * ((R)1 - fx) + (R)M[y1 * L + x1] * fx;
+  return r0 * ((R)1 - fy) + r1 * fy;
 }
 
 // One layer of Eq. wstack: img[Y][X] (+)= B[X][Y] * wterm(X, Y) with sign +1.  B is
@@ -213,14 +214,15 @@ __global__ __launch_bounds__(256) void image_wstack(const typename C2<R>::T* __r
   for (int j = ty; j < kTile; j += 256 / kTile) {
     const int Y = by + j, X = bx + tx;
     if (X < N && Y < N) {
-      V2 v = cmul<R>(tile[tx][j], wterm<R>(X, Y, N, dl, w0, itaper, inv_l2, 1.0));
-      if (nmap) {  // inverse A-term mode: divide by the normalisation (0 where it is 0)
-        const double c = lattice_bilinear(nmap, L, N, X, Y);
-        const R f = c > 0.0 ? (R)(1.0 / c) : (R)0;
-        v = V2{v.x * f, v.y * f};
-      }
+      const V2 v = cmul<R>(tile[tx][j], wterm<R>(X, Y, N, dl, w0, itaper, inv_l2, 1.0));
       V2* o = img + (size_t)Y * N + X;
-      *o = assign ? v : V2{o->x + v.x, o->y + v.y};
+      V2 r = assign ? v : V2{o->x + v.x, o->y + v.y};
+      if (nmap) {  // last layer, inverse A-term mode: divide the sum by the normalisation
+        const R c = lattice_bilinear<R>(nmap, L, N, (R)1 / (R)N, X, Y);
+        const R f = c > (R)0 ? (R)1 / c : (R)0;  // 0 where the map is 0
+        r = V2{r.x * f, r.y * f};
+      }
+      *o = r;
     }
   }
 }
