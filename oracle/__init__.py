@@ -14,6 +14,10 @@ The image-level step (w-stacking, ``invert`` / ``predict``) is plain numpy in
 FP64 on top of numpy's FFT; it is pinned by a brute-force DFT matrix, the adjoint
 identity, and the direct imaging and prediction equations at the subgrid lattice.
 
+Stokes-I grids (one complex value per cell, I = (XX + YY) / 2) are defined on top of
+the 4-polarisation functions, and pinned by the direct image and prediction of
+unpolarised lattice sources and by their adjoint relation.
+
 The inverse A-term mode (Sec. 3.3: gridding with A_p^-1 . A_q^-H normalised by
 ||A_p^-1 A_q^-H||_F, the image divided by the weighted average of that factor) is
 pinned by unitary Jones terms (where it is the adjoint mode over sqrt 2), a closed
@@ -164,6 +168,32 @@ def grid(wl, vis: np.ndarray, table: np.ndarray, W: int | None = None, beta: flo
                            ctypes.c_int(nthreads), ctypes.c_int(aterm_mode))
     assert rc == 0
     return G
+
+
+def stokes_i_reduce(G: np.ndarray) -> np.ndarray:
+    """Stokes-I grid of a 4-polarisation grid (the master grid of Sec. 5: 1 complex value
+    per cell for Stokes I): I = (XX + YY) / 2.  [W][4][N][N] -> [W][1][N][N]."""
+    G = np.asarray(G)
+    return 0.5 * (G[:, 0:1] + G[:, 3:4])
+
+
+def stokes_i_expand(GI: np.ndarray) -> np.ndarray:
+    """The 4-polarisation grid of an unpolarised brightness B = I [[1, 0], [0, 1]]:
+    XX = YY = I, XY = YX = 0.  [W][1][N][N] -> [W][4][N][N]."""
+    GI = np.asarray(GI, np.complex128)
+    z = np.zeros_like(GI)
+    return np.concatenate([GI, z, z, GI], axis=1)
+
+
+def grid_stokes_i(wl, vis: np.ndarray, table: np.ndarray, W: int | None = None, beta: float = 0.0,
+                  nthreads: int = 0, aterm_mode: int = 0) -> np.ndarray:
+    """Gridding onto a Stokes-I grid: the Stokes-I part of the A-term-corrected 4-pol grid."""
+    return stokes_i_reduce(grid(wl, vis, table, W=W, beta=beta, nthreads=nthreads, aterm_mode=aterm_mode))
+
+
+def degrid_stokes_i(wl, GI: np.ndarray, table: np.ndarray, beta: float = 0.0, nthreads: int = 0) -> np.ndarray:
+    """Degridding from a Stokes-I grid: the 4-pol visibilities of the unpolarised grid."""
+    return degrid(wl, stokes_i_expand(GI), table, beta=beta, nthreads=nthreads)
 
 
 def aterm_norm(wl, table: np.ndarray) -> np.ndarray:

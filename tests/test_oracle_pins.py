@@ -14,7 +14,9 @@ the oracle's own formulas:
   * Jones factorisation, linearity, permutation invariance, Hermitian symmetry
     of the measurement equation (Sec. 2.4 footnote) and partition validity;
   * the inverse A-term mode (Sec. 3.3) against unitary Jones terms, a closed form
-    for diagonal ones, and recovery of a lattice source's brightness.
+    for diagonal ones, and recovery of a lattice source's brightness;
+  * Stokes-I grids against the direct image and prediction of unpolarised lattice
+    sources, and their adjoint relation.
 """
 import dataclasses
 import math
@@ -670,3 +672,62 @@ def test_lattice_to_image_is_bilinear(orc):
     exp = 0.7 + 0.05 * g[None, :] - 0.03 * g[:, None]
     sel = np.ix_(inner_px, inner_px)
     assert np.abs(img[sel] - exp[sel]).max() < 1e-13
+
+
+# ------------------------------------------------------------------ Stokes-I grids
+
+
+@pytest.mark.parametrize("seed,w_step", [(91, 0.0), (92, 12.0)])
+def test_stokes_i_image_is_the_mean_of_the_parallel_hands(orc, seed, w_step):
+    """At lattice pixels the image of a Stokes-I grid is (XX + YY) / 2 of the direct
+    A-term image of the visibilities."""
+    wl = synth.config_tiny(seed)
+    N, L, K = wl.grid_size, wl.subgrid_size, wl.kernel_support
+    rng = np.random.default_rng(seed)
+    V = synth.random_vis((wl.n_baselines, wl.n_times, wl.n_chans), rng)
+    table = orc.partition(wl, w_step)
+    GI = orc.grid_stokes_i(wl, V, table)
+    assert GI.shape[1] == 1
+    I = orc.invert(GI, orc.layer_w(table), L, K, wl.pixel_scale)
+    xs, ys = lattice_all(L)
+    sel = rng.choice(xs.shape[0], 60, replace=False)
+    xs, ys = xs[sel], ys[sel]
+    X, Y = N // 2 + (xs - L // 2) * (N // L), N // 2 + (ys - L // 2) * (N // L)
+    l, m = orc.lattice_dirs(wl, xs, ys)
+    ref = orc.direct_image(wl, V, l, m, xs, ys, mask=orc.coverage_mask(wl, table))
+    assert rel(I[0, Y, X], 0.5 * (ref[:, 0] + ref[:, 3])) < 1e-11
+
+
+@pytest.mark.parametrize("seed,w_step", [(93, 0.0), (94, 12.0)])
+def test_stokes_i_degridding_of_unpolarised_sources_is_the_direct_prediction(orc, seed, w_step):
+    """Unpolarised lattice point sources (B = I [[1, 0], [0, 1]]) on a Stokes-I image:
+    degridding its prediction gives their direct 4-pol visibilities A_p B A_q^H."""
+    wl = synth.config_tiny(seed)
+    N, L, K = wl.grid_size, wl.subgrid_size, wl.kernel_support
+    rng = np.random.default_rng(seed)
+    src = synth.point_sources(3, wl.fov, 0.5, 5.0, rng, L=L, on_lattice=True, pol_frac=0.0)
+    assert np.allclose(src["B"][:, 1:3], 0) and np.allclose(src["B"][:, 0], src["B"][:, 3])
+    I = np.zeros((1, N, N), np.complex128)
+    for s in range(3):
+        X = N // 2 + (src["xs"][s] - L // 2) * (N // L)
+        Y = N // 2 + (src["ys"][s] - L // 2) * (N // L)
+        I[0, Y, X] += src["B"][s, 0]
+    table = orc.partition(wl, w_step)
+    V = orc.degrid_stokes_i(wl, orc.predict(I, orc.layer_w(table), L, K, wl.pixel_scale), table)
+    Vd = orc.direct_predict(wl, src["l"], src["m"], src["B"], src["xs"], src["ys"])
+    mask = orc.coverage_mask(wl, table).astype(bool)
+    assert rel(V[mask], Vd[mask]) < 1e-11
+
+
+def test_stokes_i_gridding_and_degridding_are_adjoint_up_to_two(orc):
+    """Reduction (XX + YY)/2 and expansion I -> diag(I, I) satisfy R^H = E / 2, so
+    <grid_I(V), G> = <V, degrid_I(G)> / 2."""
+    wl = synth.config_tiny(95)
+    rng = np.random.default_rng(95)
+    table = orc.partition(wl, 12.0)
+    V = synth.random_vis((wl.n_baselines, wl.n_times, wl.n_chans), rng)
+    V *= orc.coverage_mask(wl, table)[..., None]
+    GI = synth.random_grid(orc.n_layers(table), wl.grid_size, rng)[:, :1]
+    lhs = inner(orc.grid_stokes_i(wl, V, table), GI)
+    rhs = 0.5 * inner(V, orc.degrid_stokes_i(wl, GI, table))
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
