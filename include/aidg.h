@@ -37,7 +37,8 @@
  *   aterms     device c64|c128 [n_int][n_st][L][L][4]  n_int = ceil(nt / aterm_interval),
  *                                                      pixel [y][x], Jones row-major
  *   vis        device c64|c128 [nbl][nt][nc][4]
- *   grid       device c64|c128 [W][4][N][N]            W w-layers, u (gu) fastest
+ *   grid       device c64|c128 [W][P][N][N]            W w-layers, u (gu) fastest; P = 4
+ *                                                      planes (XX, XY, YX, YY), 1 with stokes_i
  * c64 with precision AIDG_FP32, c128 with AIDG_FP64.
  *
  * Ownership: host arrays are read during the call that receives them and may be
@@ -62,7 +63,7 @@
 extern "C" {
 #endif
 
-#define AIDG_ABI_VERSION 4
+#define AIDG_ABI_VERSION 5
 
 typedef enum {
   AIDG_OK = 0,
@@ -121,6 +122,15 @@ typedef struct {
                               plan's subgrids (0 where M interpolates to 0).  Degridding
                               and aidg_predict are the same in both modes, so in mode 1
                               gridding is not the adjoint of degridding */
+  int32_t stokes_i;        /* 1: Stokes-I grids, one complex value per cell (Sec. 5.5: the
+                              master grid of Stokes-I imaging holds one complex value per
+                              pixel, that of IQUV imaging four).  Gridding
+                              adds I = (S'_XX + S'_YY) / 2 of each A-term-corrected subgrid
+                              image; degridding reads I and predicts the visibilities of the
+                              unpolarised brightness B = I [[1, 0], [0, 1]].  Grids are
+                              [W][1][N][N] and images [1][N][N].  Gridding is then the
+                              adjoint of degridding up to a factor 2:
+                              <grid(V), G> = <V, degrid(G)> / 2.  0: four planes (default) */
   int64_t workspace_bytes; /* device budget for the group images of one batch
                               (4 L^2 complex each); 0 = 2 GiB */
 } aidg_geometry;
@@ -240,7 +250,8 @@ void aidg_plan_destroy(aidg_plan* plan);
  * its inverse for prediction (Eq. wunstack, prediction step 2).
  * Image pixel (X, Y), 0 <= X, Y < N, sits at l = (X - N/2) dl, m = (Y - N/2) dl,
  * with n1 = sqrt(1 - l^2 - m^2) - 1.  Image layout: device [4][N][N] (pol, Y, X), X
- * fastest, c64 / c128 as the plan's precision.
+ * fastest, c64 / c128 as the plan's precision; [1][N][N] for a stokes_i plan, whose grids
+ * are [W][1][N][N].
  *   aidg_invert:  I[p](X, Y) = 1 / (L^2 T(X, Y)) sum_w exp(+2 pi i w0_w n1)
  *                              sum_{gu, gv} G_w[p][gv][gu] exp(+2 pi i (u l + v m))
  *   aidg_predict: G_w[p][gv][gu] = sum_{X, Y} I[p](X, Y) exp(-2 pi i w0_w n1)

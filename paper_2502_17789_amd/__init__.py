@@ -43,7 +43,7 @@ class _Geometry(ctypes.Structure):
                 ("reseed_channels", ctypes.c_int32), ("strict_range", ctypes.c_int32),
                 ("max_subgrid_vis", ctypes.c_int32), ("center_lattice", ctypes.c_int32),
                 ("w_fold", ctypes.c_int32), ("aterm_mode", ctypes.c_int32),
-                ("workspace_bytes", ctypes.c_int64)]
+                ("stokes_i", ctypes.c_int32), ("workspace_bytes", ctypes.c_int64)]
 
 
 class _PlanInfo(ctypes.Structure):
@@ -91,16 +91,23 @@ class Geometry:
     center_lattice: int = 0
     w_fold: int = 0
     aterm_mode: int = ATERM_ADJOINT
+    stokes_i: int = 0
+
+    @property
+    def n_pol(self) -> int:
+        """Grid and image planes: 4 (XX, XY, YX, YY), or 1 for Stokes-I grids."""
+        return 1 if self.stokes_i else 4
 
     def to_c(self) -> _Geometry:
         return _Geometry(self.grid_size, self.subgrid_size, self.kernel_support, self.aterm_interval,
                          self.pixel_scale, self.w_step, self.taper_beta, self.precision,
                          self.reseed_channels, self.strict_range, self.max_subgrid_vis,
-                         self.center_lattice, self.w_fold, self.aterm_mode, self.workspace_bytes)
+                         self.center_lattice, self.w_fold, self.aterm_mode, self.stokes_i,
+                         self.workspace_bytes)
 
 
 _lib = None
-ABI_VERSION = 4  # the structure layouts above follow include/aidg.h at this version
+ABI_VERSION = 5  # the structure layouts above follow include/aidg.h at this version
 
 
 def library() -> ctypes.CDLL:
@@ -231,7 +238,7 @@ class Plan:
 
     def grid_shape(self):
         N = self.geometry.grid_size
-        return (self.n_wlayers, 4, N, N)
+        return (self.n_wlayers, self.geometry.n_pol, N, N)
 
     def vis_shape(self):
         return (self.nbl, self.nt, self.nc, 4)
@@ -266,7 +273,7 @@ class Plan:
         return out
 
     def degrid(self, grid, out=None, stream=None):
-        """Degrid ``grid`` [W, 4, N, N] into ``out`` [nbl, nt, nc, 4] (overwritten)."""
+        """Degrid ``grid`` [W, P, N, N] into ``out`` [nbl, nt, nc, 4] (overwritten)."""
         import torch
         self._check_tensor(grid, self.grid_shape(), "grid")
         if out is None:
@@ -277,7 +284,7 @@ class Plan:
 
     def image_shape(self):
         N = self.geometry.grid_size
-        return (4, N, N)
+        return (self.geometry.n_pol, N, N)
 
     def _image_workspace(self, device):
         import torch
@@ -289,7 +296,7 @@ class Plan:
         return ws
 
     def invert(self, grid, out=None, stream=None):
-        """Image ``grid`` [W, 4, N, N] by w-stacking into ``out`` [4, N, N] (overwritten)."""
+        """Image ``grid`` [W, P, N, N] by w-stacking into ``out`` [P, N, N] (overwritten)."""
         import torch
         self._check_tensor(grid, self.grid_shape(), "grid")
         if out is None:

@@ -16,6 +16,10 @@ adjoint of imaging I = P^H(G) (Eq. wstack), so
 and ``predict_vis`` (image -> visibilities, degrid after predict) is differentiable
 end to end.
 
+On a Stokes-I plan, gridding reduces to I = (XX + YY) / 2 and degridding expands I to
+[[I, 0], [0, I]]; the reduction's adjoint is half the expansion, so there
+    DegridFn.backward(gV) = 2 grid(gV)     GridFn.backward(gG) = degrid(gG) / 2.
+
 A plan in the inverse A-term mode grids with normalised A^-1 and divides its image by
 the normalisation map: neither is the adjoint of degridding or prediction, so these
 functions refuse such plans.
@@ -46,6 +50,8 @@ class DegridFn(torch.autograd.Function):
         g_grid = None
         if ctx.needs_input_grad[0]:
             g_grid = plan.grid(g_vis.contiguous())
+            if plan.geometry.stokes_i:
+                g_grid = g_grid * 2
         return g_grid, None
 
 
@@ -63,6 +69,8 @@ class GridFn(torch.autograd.Function):
         g_vis = None
         if ctx.needs_input_grad[0]:
             g_vis = plan.degrid(g_grid.contiguous())
+            if plan.geometry.stokes_i:
+                g_vis = g_vis * 0.5
         return g_vis, None
 
 

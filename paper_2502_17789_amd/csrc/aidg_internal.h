@@ -40,6 +40,7 @@ static_assert(sizeof(SubgridDev) == 96, "SubgridDev layout");
 // Geometry after validation, with derived quantities.
 struct Geometry {
   int N, L, K, aterm_interval, precision, R, strict, max_sg_vis, lattice, fold, amode;
+  int npol;  // grid planes: 4, or 1 for Stokes-I grids
   double dl, fov, du, beta, w_step;
   int64_t workspace;
 };
@@ -73,7 +74,8 @@ struct KernelArgs {
   const void* taper;        // device [L][L] taper times (-1)^(x+y)
   const void* twiddle;      // device [L] exp(-2 pi i k / L)
   const int64_t* grp_begin; // device [n_groups + 1]: first subgrid of each (layer, centre) group
-  int nt_total, nc_total, N, pad;
+  int nt_total, nc_total, N;
+  int npol;                 // grid planes: 4 (XX, XY, YX, YY) or 1 (Stokes I)
   double du;                // uv cell size, wavelengths
   double lstep;             // FOV / L, subgrid lattice spacing in direction cosines
 };

@@ -122,7 +122,7 @@ struct aidg_plan {
     a.nt_total = nt;
     a.nc_total = nc;
     a.N = g.N;
-    a.pad = 0;
+    a.npol = g.npol;
     a.du = g.du;
     a.lstep = g.fov / g.L;
     return a;
@@ -659,7 +659,7 @@ aidg_status aidg_plan_info_get(const aidg_plan* plan, aidg_plan_info* info) {
   info->w_step = plan->g.w_step;
   info->device_bytes = (int64_t)plan->device_bytes;
   info->workspace_bytes = (int64_t)plan->scratch_bytes;
-  info->grid_bytes = (int64_t)plan->W * 4 * plan->g.N * plan->g.N * (int64_t)plan->elem;
+  info->grid_bytes = (int64_t)plan->W * plan->g.npol * plan->g.N * plan->g.N * (int64_t)plan->elem;
   info->vis_bytes = info->n_vis * 4 * (int64_t)plan->elem;
   info->n_batches = plan->batch_begin.empty() ? 0 : (int64_t)plan->batch_begin.size() - 1;
   info->n_groups = plan->grp_begin.empty() ? 0 : (int64_t)plan->grp_begin.size() - 1;
@@ -766,10 +766,10 @@ aidg_status aidg_invert(aidg_plan* plan, const void* grid, void* image, void* wo
   char* A = static_cast<char*>(workspace);
   char* B = A + plane;
   const double dl = plan->g.dl, inv_l2 = 1.0 / ((double)plan->g.L * plan->g.L);
-  for (int pol = 0; pol < 4 && r == AIDG_OK; ++pol) {
+  for (int pol = 0; pol < plan->g.npol && r == AIDG_OK; ++pol) {
     char* img = static_cast<char*>(image) + pol * plane;
     for (int w = 0; w < plan->W && r == AIDG_OK; ++w) {
-      const char* G = static_cast<const char*>(grid) + ((size_t)w * 4 + pol) * plane;
+      const char* G = static_cast<const char*>(grid) + ((size_t)w * plan->g.npol + pol) * plane;
       // rows: G[gv][gu] -> A[gv][X]; transpose -> B[X][gv]; rows -> B[X][Y]; add into img[Y][X]
       r = image_step(plan, st, kImageFft, [&] {
         return launch_image_fft_rows(prec, +1, false, G, A, N, plan->img_fr, plan->d_img_tw,
@@ -809,9 +809,9 @@ aidg_status aidg_predict(aidg_plan* plan, const void* image, void* grid, void* w
   char* B = A + plane;
   const double dl = plan->g.dl, inv_l2 = 1.0 / ((double)plan->g.L * plan->g.L);
   for (int w = 0; w < plan->W && r == AIDG_OK; ++w) {
-    for (int pol = 0; pol < 4 && r == AIDG_OK; ++pol) {
+    for (int pol = 0; pol < plan->g.npol && r == AIDG_OK; ++pol) {
       const char* img = static_cast<const char*>(image) + pol * plane;
-      char* G = static_cast<char*>(grid) + ((size_t)w * 4 + pol) * plane;
+      char* G = static_cast<char*>(grid) + ((size_t)w * plan->g.npol + pol) * plane;
       // rows of img[Y][X] times the w-term -> A[Y][gu]; transpose -> B[gu][Y];
       // rows -> B[gu][gv]; transpose -> G[gv][gu]
       r = image_step(plan, st, kImageFft, [&] {

@@ -30,6 +30,10 @@
 //              combine through LDS atomics; the finished visibilities are written
 //              once (Eq. degridder).
 //
+// A Stokes-I plan (npol = 1) keeps one grid plane: grid_dft adds (XX + YY) / 2 of the
+// corrected image and fft_add transforms that plane only; split_ifft stores the group
+// image as I [[1, 0], [0, 1]], which degrid_dft reads like any other.
+//
 // The centred DFT of Sec. 2.3 relates to a plain FFT by a checkerboard:
 //   sum_{x,y} s(x,y) e^{-2 pi i [(a-L/2)(x-L/2) + (b-L/2)(y-L/2)]/L}
 //     = (-1)^(a+b) FFT[(-1)^(x+y) s](a,b)     (even L),
@@ -344,10 +348,16 @@ __global__ __launch_bounds__(kThreads) void grid_dft(const Group g) {
       }
       V2 c[4] = {(cmul<R>(t0, b0) + cmul<R>(t1, b2)) * w, (cmul<R>(t0, b1) + cmul<R>(t1, b3)) * w,
                  (cmul<R>(t2, b0) + cmul<R>(t3, b2)) * w, (cmul<R>(t2, b1) + cmul<R>(t3, b3)) * w};
+      if (a.npol == 1) {  // Stokes-I grid: I = (XX + YY) / 2 of the corrected image
+        V2 ci = (c[0] + c[3]) * (R)0.5;
+        if (si != gs.sb) ci += out[pix];
+        out[pix] = ci;
+      } else {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        if (si != gs.sb) c[q] += out[q * L * L + pix];
-        out[q * L * L + pix] = c[q];
+        for (int q = 0; q < 4; ++q) {
+          if (si != gs.sb) c[q] += out[q * L * L + pix];
+          out[q * L * L + pix] = c[q];
+        }
       }
     }
   }
@@ -425,6 +435,7 @@ __global__ __launch_bounds__(kThreads) void fft_add(const Group g) {
   const int64_t local = blockIdx.y;
   const GroupSlot gs = resolve_group(g, local);
   const KernelArgs& a = gs.a;
+  if (pol >= a.npol) return;  // a Stokes-I plan has one plane (whole workgroup)
   const SubgridDev s = load_uniform(a.sg + gs.sb);  // centre and w-layer of the group
   R* grid = reinterpret_cast<R*>(gs.out);
   const V2* in = reinterpret_cast<const V2*>(g.scratch) + (local * 4 + pol) * L * L;
@@ -433,7 +444,7 @@ __global__ __launch_bounds__(kThreads) void fft_add(const Group g) {
   __syncthreads();
   fft_lines<L, -1, true>(buf, tw);
   fft_lines<L, -1, false>(buf, tw);
-  R* win = grid + 2 * ((((int64_t)s.wlayer * 4 + pol) * a.N + (s.V0 - L / 2)) * a.N + (s.U0 - L / 2));
+  R* win = grid + 2 * ((((int64_t)s.wlayer * a.npol + pol) * a.N + (s.V0 - L / 2)) * a.N + (s.U0 - L / 2));
   for (int e = threadIdx.x; e < L * L; e += kThreads) {
     const int b = e / L, c = e % L;
     V2 val = buf[b * pitch(L) + c];
@@ -453,11 +464,20 @@ __global__ __launch_bounds__(kThreads) void split_ifft(const Group g) {
   const int64_t local = blockIdx.y;
   const GroupSlot gs = resolve_group(g, local);
   const KernelArgs& a = gs.a;
+  R* __restrict__ scratch = reinterpret_cast<R*>(g.scratch);
+  V2* out = reinterpret_cast<V2*>(scratch) + (local * 4 + pol) * L * L;
+  // A Stokes-I plan stores its group image as [[I, 0], [0, I]]: planes 0 and 3 are the
+  // transform of the one grid plane, planes 1 and 2 zero (whole workgroups).
+  const bool stokes = a.npol == 1;
+  if (stokes && (pol == 1 || pol == 2)) {
+    for (int e = threadIdx.x; e < L * L; e += kThreads) out[e] = V2{0, 0};
+    return;
+  }
+  const int gp = stokes ? 0 : pol;  // grid plane
   const SubgridDev s = load_uniform(a.sg + gs.sb);  // centre and w-layer of the group
   const R* __restrict__ grid = reinterpret_cast<const R*>(gs.in);
-  R* __restrict__ scratch = reinterpret_cast<R*>(g.scratch);
   const V2* win = reinterpret_cast<const V2*>(grid) +
-                  (((int64_t)s.wlayer * 4 + pol) * a.N + (s.V0 - L / 2)) * a.N + (s.U0 - L / 2);
+                  (((int64_t)s.wlayer * a.npol + gp) * a.N + (s.V0 - L / 2)) * a.N + (s.U0 - L / 2);
   for (int e = threadIdx.x; e < L * L; e += kThreads) {
     const int b = e / L, c = e % L;
     V2 val = win[(int64_t)b * a.N + c];
@@ -468,7 +488,6 @@ __global__ __launch_bounds__(kThreads) void split_ifft(const Group g) {
   __syncthreads();
   fft_lines<L, +1, true>(buf, tw);
   fft_lines<L, +1, false>(buf, tw);
-  V2* out = reinterpret_cast<V2*>(scratch) + (local * 4 + pol) * L * L;
   for (int e = threadIdx.x; e < L * L; e += kThreads) out[e] = buf[(e / L) * pitch(L) + e % L];
 }
 

@@ -81,6 +81,11 @@ aidg_status validate_geometry(const aidg_geometry* g, Geometry* o, std::string* 
     return AIDG_E_INVALID;
   }
   o->amode = g->aterm_mode;
+  if (g->stokes_i != 0 && g->stokes_i != 1) {
+    *err = "stokes_i must be 0 or 1";
+    return AIDG_E_INVALID;
+  }
+  o->npol = g->stokes_i ? 1 : 4;
   if (g->center_lattice > 0) {
     o->lattice = g->center_lattice;
   } else {

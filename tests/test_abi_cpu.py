@@ -80,7 +80,7 @@ def test_auto_w_step_formula():
                                  dict(pixel_scale=-1.0), dict(aterm_interval=0),
                                  dict(pixel_scale=math.radians(120) / 512), dict(max_subgrid_vis=2049),
                                  dict(max_subgrid_vis=-1), dict(center_lattice=-2), dict(w_fold=2),
-                                 dict(aterm_mode=2)])
+                                 dict(aterm_mode=2), dict(stokes_i=2)])
 def test_invalid_geometry_rejected(bad):
     kw = dict(grid_size=512, subgrid_size=32, kernel_support=8, pixel_scale=math.radians(10) / 512)
     kw.update(bad)
