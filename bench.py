@@ -109,6 +109,8 @@ def parse():
                     help="image mode: w_fold settings to run at max |w| > 0")
     ap.add_argument("--aterm-mode", type=int, choices=[0, 1], default=0,
                     help="A-term of gridding: 0 adjoint (A^H), 1 the paper's normalised A^-1")
+    ap.add_argument("--stokes-i", action="store_true",
+                    help="Stokes-I grids: one complex value per cell instead of four")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device-to-device 3 times (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -419,7 +421,8 @@ def image_bench(args):
         ha = synth.hour_angle_for_wmax(wmax) if wmax > 0 else 0.0
         wl = synth.config_mwa(seed=2, ha0_rad=ha)
         geo = aidg.Geometry(wl.grid_size, wl.subgrid_size, wl.kernel_support, wl.pixel_scale,
-                            aterm_interval=wl.aterm_interval, w_fold=fold, aterm_mode=args.aterm_mode)
+                            aterm_interval=wl.aterm_interval, w_fold=fold, aterm_mode=args.aterm_mode,
+                            stokes_i=int(args.stokes_i))
         A = torch.from_numpy(wl.aterms.astype(np.complex64)).cuda()
         with aidg.Plan(geo, wl.n_stations, wl.baselines, wl.uvw, wl.freqs, A) as plan:
             del A
@@ -449,15 +452,20 @@ def image_bench(args):
             t_pred = float(np.median([e[1].elapsed_time(e[2]) for e in ev]))
             del G, I, Io, Go
         P = N * N * 8
-        by = {"image_fft": reps * 16 * W * 2 * P,
-              "image_wstack": reps * ((4 * W * 2 + 4 * 2 + 4 * (W - 1) * 3) + 8 * W * 2) * P}
+        npol = geo.n_pol
+        # per polarisation plane: invert reads + writes a plane in each of 2 row passes and
+        # 1 transpose per layer, the first layer's w-stack pass reads 1 and writes 1, the
+        # others read 2 and write 1; predict reads + writes in 2 row passes and 2 transposes
+        by = {"image_fft": reps * npol * 4 * W * 2 * P,
+              "image_wstack": reps * npol * ((W * 2 + 2 + (W - 1) * 3) + 2 * W * 2) * P}
         cls = {k: {"ms_per_launch": round(kt[k]["ms"] / max(kt[k]["launches"], 1), 4),
                    "launches_per_call_pair": kt[k]["launches"] // reps,
                    "gb_s": round(by[k] / (kt[k]["ms"] * 1e-3) / 1e9, 1)} for k in by}
         dom = max(by, key=lambda k: kt[k]["ms"])
         print(json.dumps({
             "image_level": {"grid_size": N, "n_wlayers": W, "max_abs_w_lambda": wmax or "transit",
-                            "w_fold": fold, "aterm_mode": args.aterm_mode, "precision": "fp32",
+                            "w_fold": fold, "aterm_mode": args.aterm_mode,
+                            "grid_planes": 1 if args.stokes_i else 4, "precision": "fp32",
                             "plane_bytes": P},
             "invert_ms": round(t_inv, 3), "predict_ms": round(t_pred, 3),
             "classes": cls,
@@ -521,7 +529,8 @@ def main():
     torch.cuda.set_device(0)
     wl = synth.config_mwa(seed=2)
     geo = aidg.Geometry(wl.grid_size, wl.subgrid_size, wl.kernel_support, wl.pixel_scale,
-                        aterm_interval=wl.aterm_interval, aterm_mode=args.aterm_mode)
+                        aterm_interval=wl.aterm_interval, aterm_mode=args.aterm_mode,
+                        stokes_i=int(args.stokes_i))
     A = torch.from_numpy(wl.aterms.astype(np.complex64)).cuda()
     t0 = time.perf_counter()
     plan = aidg.Plan(geo, wl.n_stations, wl.baselines, wl.uvw, wl.freqs, A)
@@ -593,7 +602,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {**workload_description(wl, info),
-                   "aterm_mode": "inverse (normalised A^-1)" if args.aterm_mode else "adjoint (A^H)"},
+                   "aterm_mode": "inverse (normalised A^-1)" if args.aterm_mode else "adjoint (A^H)",
+                   "grid_planes": 1 if args.stokes_i else 4},
         "grid_mvis_s": round(n / (np.median(t_grid) * 1e-3) / 1e6, 3),
         "degrid_mvis_s": round(n / (np.median(t_degrid) * 1e-3) / 1e6, 3),
         "latency_ms": {"p50": round(float(np.percentile(t_job, 50)), 3),

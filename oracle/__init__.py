@@ -171,8 +171,8 @@ def grid(wl, vis: np.ndarray, table: np.ndarray, W: int | None = None, beta: flo
 
 
 def stokes_i_reduce(G: np.ndarray) -> np.ndarray:
-    """Stokes-I grid of a 4-polarisation grid (the master grid of Sec. 5: 1 complex value
-    per cell for Stokes I): I = (XX + YY) / 2.  [W][4][N][N] -> [W][1][N][N]."""
+    """Stokes-I grid of a 4-polarisation grid (Sec. 5.5: one complex value per pixel for
+    Stokes I): I = (XX + YY) / 2.  [W][4][N][N] -> [W][1][N][N]."""
     G = np.asarray(G)
     return 0.5 * (G[:, 0:1] + G[:, 3:4])
 
