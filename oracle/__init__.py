@@ -264,12 +264,12 @@ def direct_predict(wl, l, m, B, xs=None, ys=None, nthreads: int = 0) -> np.ndarr
 
 def layer_image_at(G_layer: np.ndarray, du: float, l, m, nthreads: int = 0) -> np.ndarray:
     G = _c128(G_layer)
-    N = G.shape[-1]
+    P, N = G.shape[0], G.shape[-1]
     l = np.ascontiguousarray(l, np.float64)
     m = np.ascontiguousarray(m, np.float64)
-    out = np.zeros((l.shape[0], 4), np.complex128)
-    lib().oracle_layer_image_at(_p(G), ctypes.c_int(N), ctypes.c_double(du), ctypes.c_int(l.shape[0]),
-                                _p(l), _p(m), _p(out), ctypes.c_int(nthreads))
+    out = np.zeros((l.shape[0], P), np.complex128)
+    lib().oracle_layer_image_at(_p(G), ctypes.c_int(P), ctypes.c_int(N), ctypes.c_double(du),
+                                ctypes.c_int(l.shape[0]), _p(l), _p(m), _p(out), ctypes.c_int(nthreads))
     return out
 
 

@@ -602,20 +602,20 @@ int oracle_aterm_norm(int N, int L, double dl, int n_st, int nbl, int nt, int nc
   Problem P = make_problem(N, L, 0, dl, 1.0, n_st, nbl, nt, nc, aterm_interval, n_int, baselines,
                            uvw, freqs, aterms);
   double total = 0.0;
-  for (size_t i = 0; i < (size_t)L * L; ++i) out[i] = 0.0;
-  for (int64_t i = 0; i < nsg; ++i) {
-    const Subgrid& s = sg[i];
-    const double nv = double(s.nt) * s.nc;
-    total += nv;
-    for (int y = 0; y < L; ++y)
-      for (int x = 0; x < L; ++x) {
+  for (int64_t i = 0; i < nsg; ++i) total += double(sg[i].nt) * sg[i].nc;
+  // each pixel sums over the subgrids in table order (rows of pixels in parallel)
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int y = 0; y < L; ++y)
+    for (int x = 0; x < L; ++x) {
+      double acc = 0.0;
+      for (int64_t i = 0; i < nsg; ++i) {
+        const Subgrid& s = sg[i];
         const Mat2 Ap = load_mat(P.aterm(s.aint, s.folded ? s.st2 : s.st1, x, y));
         const Mat2 Aq = load_mat(P.aterm(s.aint, s.folded ? s.st1 : s.st2, x, y));
-        out[(size_t)y * L + x] += nv * inverse_norm_factor(Ap, Aq);
+        acc += double(s.nt) * s.nc * inverse_norm_factor(Ap, Aq);
       }
-  }
-  if (total > 0.0)
-    for (size_t i = 0; i < (size_t)L * L; ++i) out[i] /= total;
+      out[(size_t)y * L + x] = total > 0.0 ? acc / total : 0.0;
+    }
   return 0;
 }
 
@@ -777,8 +777,8 @@ void oracle_direct_predict(int N, int L, double dl, int n_st, int nbl, int nt, i
 
 // Image of one w-layer grid at arbitrary directions (a non-uniform inverse DFT):
 //   I(l,m) = sum_{gu,gv} G[gv][gu] exp(+2 pi i [(gu - N/2) du l + (gv - N/2) du m]).
-// G: complex [4][N][N]; out: complex [n_dir][4].
-void oracle_layer_image_at(const double* G, int N, double du, int n_dir, const double* l,
+// G: complex [npol][N][N]; out: complex [n_dir][npol].
+void oracle_layer_image_at(const double* G, int npol, int N, double du, int n_dir, const double* l,
                            const double* m, double* out, int nthreads) {
 #ifdef _OPENMP
   if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -790,7 +790,7 @@ void oracle_layer_image_at(const double* G, int N, double du, int n_dir, const d
       eu[g] = turns_phasor((g - N / 2) * du * l[d]);
       ev[g] = turns_phasor((g - N / 2) * du * m[d]);
     }
-    for (int pol = 0; pol < 4; ++pol) {
+    for (int pol = 0; pol < npol; ++pol) {
       cd acc(0.0, 0.0);
       for (int gv = 0; gv < N; ++gv) {
         const double* row = G + 2 * (((size_t)pol * N + gv) * N);
@@ -798,8 +798,8 @@ void oracle_layer_image_at(const double* G, int N, double du, int n_dir, const d
         for (int gu = 0; gu < N; ++gu) r += cd(row[2 * gu], row[2 * gu + 1]) * eu[gu];
         acc += r * ev[gv];
       }
-      out[8 * (size_t)d + 2 * pol] = acc.real();
-      out[8 * (size_t)d + 2 * pol + 1] = acc.imag();
+      out[2 * ((size_t)d * npol + pol)] = acc.real();
+      out[2 * ((size_t)d * npol + pol) + 1] = acc.imag();
     }
   }
 }
