@@ -62,11 +62,12 @@ def workload(name):
     return wl
 
 
-def plan_for(aidg, wl, precision, w_step, fold=0, mode=1):
+def plan_for(aidg, wl, precision, w_step, fold=0, mode=1, table=None):
     geo = aidg.Geometry(wl.grid_size, wl.subgrid_size, wl.kernel_support, wl.pixel_scale,
                         aterm_interval=wl.aterm_interval, precision=precision, w_step=w_step,
                         w_fold=fold, aterm_mode=mode)
-    return aidg.Plan(geo, wl.n_stations, wl.baselines, wl.uvw, wl.freqs, dev(wl.aterms, precision))
+    return aidg.Plan(geo, wl.n_stations, wl.baselines, wl.uvw, wl.freqs, dev(wl.aterms, precision),
+                     table=table)
 
 
 CASES = {
@@ -157,3 +158,20 @@ def test_inverse_mode_image_of_a_lattice_source_is_its_brightness(aidg, orc, pre
     e = rel(I[:, Y, X], Kc * src["B"][0])
     print(f"lattice source {'FP64' if precision else 'FP32'}: {e:.2e}", flush=True)
     assert e <= TOL[precision]
+
+
+def test_inverse_mode_with_no_gridded_visibilities(aidg):
+    """An empty subgrid table: every visibility is excluded, the normalisation map is 0
+    everywhere, and gridding, invert and degridding give zeros (the image is set to 0
+    where the map is 0)."""
+    wl = workload("beam")
+    rng = np.random.default_rng(10)
+    V = dev(synth.random_vis((wl.n_baselines, wl.n_times, wl.n_chans), rng), 0)
+    with plan_for(aidg, wl, 0, 12.0, table=np.zeros(0, aidg.SUBGRID_DTYPE)) as p:
+        assert p.info["n_subgrids"] == 0 and p.info["n_excluded"] == p.info["n_vis"]
+        M = p.aterm_norm()
+        G = p.grid(V)
+        I = host(p.invert(G))
+        Vd = host(p.degrid(G, out=torch.full_like(V, 7.0 + 7.0j)))
+        Gh = host(G)
+    assert not M.any() and not Gh.any() and not I.any() and not Vd.any()
