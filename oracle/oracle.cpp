@@ -6,7 +6,8 @@
 // double precision, in the order the paper states it, with no FFT library and no
 // blocking beyond what the equations themselves allow.
 //
-// Conventions (paper Sec. 2; readings of silent points are listed in the design doc):
+// Conventions (paper Sec. 2; where the paper is silent, the choice is stated here or at
+// the function that makes it):
 //   grid of N x N cells, cell (gu, gv) at u = (gu - N/2) du, du = 1 / (N dl)
 //   subgrid of L x L cells centred on integer grid cell (U0, V0): u0 = (U0 - N/2) du
 //   subgrid image pixel (x, y) at l = (x - L/2) FOV / L, FOV = N dl
