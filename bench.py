@@ -79,7 +79,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-baselines", type=int, default=12)
+    ap.add_argument("--cpu-sample-baselines", type=int, default=48)
     ap.add_argument("--serve", action="store_true",
                     help="served mixed workload instead of the MWA-like job (separate JSON line)")
     ap.add_argument("--jobs", type=int, default=300)
