@@ -100,10 +100,16 @@ def job_footprint_estimate(job: Job) -> int:
     else:
         w_step = 0.0
     wmax = float(np.abs(job.uvw[..., 2]).max(initial=0.0)) * float(job.freqs.max()) / 299792458.0
-    W = 2 * int(math.ceil(wmax / w_step)) + 1 if w_step > 0 else 1
-    grid_b = W * 4 * g.grid_size ** 2 * elem
+    if w_step <= 0:
+        W = 1
+    elif g.w_fold:  # layers at (j + 1/2) w_step for w >= 0 only
+        W = int(math.ceil(wmax / w_step)) + 1
+    else:
+        W = 2 * int(math.ceil(wmax / w_step)) + 1
+    grid_b = W * g.n_pol * g.grid_size ** 2 * elem
     vis_b = n_vis * 4 * elem
-    aterm_b = n_int * job.n_stations * g.subgrid_size ** 2 * 4 * elem
+    # the inverse A-term mode keeps a second plane set, (A^-1)^H, for the gridder
+    aterm_b = (2 if g.aterm_mode else 1) * n_int * job.n_stations * g.subgrid_size ** 2 * 4 * elem
     meta_b = nbl * nt * 24 + n_vis * 80 // 4 + 4 * g.subgrid_size ** 2 * elem
     return int(grid_b + vis_b + aterm_b + meta_b)
 

@@ -221,3 +221,34 @@ def test_active_jobs_bounded():
     res = [f.result() for f in futs]
     adm = [r.admitted for r in res]
     assert adm == sorted(adm) and len(set(adm)) >= 3
+
+
+def test_footprint_follows_geometry_variants():
+    """The admission estimate bounds the plan's grid for every geometry variant: a
+    Stokes-I grid is a quarter of the four-plane one, the fold keeps only w >= 0 layers,
+    and the inverse A-term mode holds a second A-term plane set."""
+    import dataclasses
+    import paper_2502_17789_amd as aidg
+    wl = synth.config_tiny(301, ha0_deg=-60.0)
+    N, L, elem = wl.grid_size, wl.subgrid_size, 8
+
+    def job(**kw):
+        g = Geometry(N, L, wl.kernel_support, wl.pixel_scale, aterm_interval=wl.aterm_interval,
+                     w_step=12.0, **kw)
+        return Job("grid", g, wl.n_stations, wl.baselines, wl.uvw, wl.freqs, wl.aterms, None), g
+
+    def library_layers(g):
+        table, _ = aidg.partition(g, wl.n_stations, wl.baselines, wl.uvw, wl.freqs)
+        return int(table["wlayer"].max()) + 1
+
+    base_job, g0 = job()
+    base = job_footprint_estimate(base_job)
+    stokes = job_footprint_estimate(job(stokes_i=1)[0])
+    W = (base - stokes) // (3 * N * N * elem)
+    assert (base - stokes) == W * 3 * N * N * elem and W >= library_layers(g0)
+    fold_job, gf = job(w_fold=1)
+    fold = job_footprint_estimate(fold_job)
+    Wf = W - (base - fold) // (4 * N * N * elem)
+    assert library_layers(gf) <= Wf < W
+    inv = job_footprint_estimate(job(aterm_mode=1)[0])
+    assert inv - base == wl.aterms.size * elem
