@@ -175,3 +175,24 @@ def test_inverse_mode_with_no_gridded_visibilities(aidg):
         Vd = host(p.degrid(G, out=torch.full_like(V, 7.0 + 7.0j)))
         Gh = host(G)
     assert not M.any() and not Gh.any() and not I.any() and not Vd.any()
+
+
+def test_grouped_launch_mixes_inverse_and_adjoint_plans(aidg):
+    """Each plan's launch parameters carry its own A-term planes: a grouped launch of an
+    inverse-mode and an adjoint-mode plan gives each the result of its own calls."""
+    wl = workload("beam_w")
+    rng = np.random.default_rng(14)
+    V = dev(synth.random_vis((wl.n_baselines, wl.n_times, wl.n_chans), rng), 0)
+    with plan_for(aidg, wl, 0, 12.0, mode=1) as pi, plan_for(aidg, wl, 0, 12.0, mode=0) as pa:
+        ref = [host(pi.grid(V)), host(pa.grid(V))]
+        out = [torch.zeros(pi.grid_shape(), dtype=torch.complex64, device="cuda"),
+               torch.zeros(pa.grid_shape(), dtype=torch.complex64, device="cuda")]
+        ex = aidg.Executor()
+        try:
+            ex.execute([(pi, aidg.DIR_GRID, V, out[0], 0, pi.info["n_subgrids"]),
+                        (pa, aidg.DIR_GRID, V, out[1], 0, pa.info["n_subgrids"])])
+            got = [host(t) for t in out]
+        finally:
+            ex.close()
+    assert rel(got[0], ref[0]) <= 1e-6 and rel(got[1], ref[1]) <= 1e-6
+    assert rel(ref[0], ref[1]) > 1e-2  # the two modes differ on these Jones terms
