@@ -44,7 +44,8 @@ __device__ __forceinline__ float2 root_of_unity(int a, int M, float inv_m) {
 // earlier radices): butterfly j < N/R reads buf[j + i N/R], multiplies input i by
 // exp(DIR 2 pi i k i / (Ls R)) with k = j mod Ls, and writes its outputs to
 // buf[(j / Ls) Ls R + k + i Ls].  In place: every read, a barrier, every write.
-// FP32 twiddles are computed (root_of_unity); FP64 ones come from the table.
+// FP32 twiddles are computed (root_of_unity for the first, products for its powers);
+// FP64 ones come from the table.
 template <int R, int DIR, typename V2>
 __device__ __forceinline__ void row_pass(V2* buf, int N, int Ls, const V2* __restrict__ tw) {
   using Rt = decltype(V2{}.x);
@@ -65,15 +66,24 @@ __device__ __forceinline__ void row_pass(V2* buf, int N, int Ls, const V2* __res
 #pragma unroll
       for (int i = 0; i < R; ++i) y[b][i] = buf[j + i * m];
       if (Ls > 1) {  // the first pass has unit twiddles
+        if constexpr (std::is_same_v<Rt, float>) {
+          // exp(-2 pi i k / (Ls R)) from the polynomial, its powers i = 2 .. R-1 by
+          // complex products (at most R - 2 further roundings)
+          V2 w1 = root_of_unity(k, M, inv_m);
+          if (DIR > 0) w1.y = -w1.y;
+          V2 w = w1;
 #pragma unroll
-        for (int i = 1; i < R; ++i) {
-          V2 w;  // exp(-2 pi i k i / (Ls R))
-          if constexpr (std::is_same_v<Rt, float>)
-            w = root_of_unity(k * i, M, inv_m);
-          else
-            w = tw[k * i * tstep];
-          if (DIR > 0) w.y = -w.y;
-          y[b][i] = cmul<Rt>(y[b][i], w);
+          for (int i = 1; i < R; ++i) {
+            if (i > 1) w = cmul<Rt>(w, w1);
+            y[b][i] = cmul<Rt>(y[b][i], w);
+          }
+        } else {
+#pragma unroll
+          for (int i = 1; i < R; ++i) {
+            V2 w = tw[k * i * tstep];  // exp(-2 pi i k i / (Ls R))
+            if (DIR > 0) w.y = -w.y;
+            y[b][i] = cmul<Rt>(y[b][i], w);
+          }
         }
       }
       butterfly<V2, R, DIR>(y[b]);
