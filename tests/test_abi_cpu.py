@@ -133,3 +133,26 @@ def test_autograd_refuses_the_inverse_aterm_mode():
         autograd._adjoint_plan(types.SimpleNamespace(geometry=geo))
     ok = types.SimpleNamespace(geometry=aidg.Geometry(64, 32, 8, 1e-3))
     assert autograd._adjoint_plan(ok) is ok
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    """Without libaidg.so every entry point raises: there is no CPU fallback."""
+    monkeypatch.setattr(aidg, "LIB_PATH", "/nonexistent/libaidg.so")
+    monkeypatch.setattr(aidg, "_lib", None)
+    with pytest.raises(RuntimeError, match="not built"):
+        aidg.library()
+    wl = synth.config_tiny(1)
+    geo = aidg.Geometry(wl.grid_size, wl.subgrid_size, wl.kernel_support, wl.pixel_scale)
+    with pytest.raises(RuntimeError, match="not built"):
+        aidg.partition(geo, wl.n_stations, wl.baselines, wl.uvw, wl.freqs)
+
+
+def test_product_never_imports_the_oracle():
+    """The library package, its sources and the build script name no oracle module."""
+    root = os.path.dirname(aidg.__file__)
+    for dirpath, _, files in os.walk(root):
+        for f in files:
+            if f.endswith((".py", ".cpp", ".hip", ".h")):
+                text = open(os.path.join(dirpath, f), encoding="utf-8").read()
+                assert not re.search(r"^\s*(import|from)\s+oracle\b", text, re.M), f
+                assert "liboracle" not in text and "oracle.cpp" not in text, f
