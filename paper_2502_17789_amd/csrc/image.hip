@@ -124,6 +124,8 @@ template <typename R>
 __device__ __forceinline__ typename C2<R>::T wterm(int X, int Y, int N, double dl, double w0,
                                                    const double* __restrict__ itaper, double inv_l2,
                                                    double sign) {
+  const R sc = (R)(inv_l2 * itaper[X] * itaper[Y]);
+  if (w0 == 0.0) return {sc, (R)0};  // a layer at w = 0: the w-term is exactly 1
   const double l = (X - N / 2) * dl, m = (Y - N / 2) * dl;
   double n1;
   if constexpr (std::is_same_v<R, float>) {
@@ -135,7 +137,6 @@ __device__ __forceinline__ typename C2<R>::T wterm(int X, int Y, int N, double d
     n1 = -r2 / (1.0 + sqrt(1.0 - r2));
   }
   const auto ph = phasor(sign * w0 * n1, R());
-  const R sc = (R)(inv_l2 * itaper[X] * itaper[Y]);
   return {ph.x * sc, ph.y * sc};
 }
 
