@@ -28,3 +28,26 @@ def test_source_hash_ignores_comments(tmp_path, monkeypatch):
     assert bench.library_source_hash() == h0
     (csrc / "k.hip").write_text("int f() { return 2; }\n")
     assert bench.library_source_hash() != h0
+
+
+def test_committed_bench_line_keeps_the_contract():
+    """The committed bench line carries every field of the output contract, its roofline
+    fraction is achieved / peak, its value is the visibilities of one step over the step
+    time, and its traffic is the committed counter record's bytes for that kernel."""
+    import json
+    d = json.load(open(os.path.join(ROOT, "profiles", "bench_mwa_line.json")))
+    for key in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+                "higher_is_better", "scaling", "vs_baseline", "dtype", "data", "config",
+                "roofline", "cpu_baseline"):
+        assert key in d, key
+    assert d["n_gpus"] == 1 and d["higher_is_better"] is True and d["vs_baseline"] is None
+    assert "workload" in d["config"]
+    r = d["roofline"]
+    assert r["bound"] in ("hbm", "mfma", "alu") and r["unit"] in ("GB/s", "TFLOP/s")
+    assert abs(r["frac"] - r["achieved"] / r["peak"]) < 1e-3
+    n_vis = d["config"]["n_vis"]
+    assert abs(d["value"] - n_vis / (d["ms_per_step"] * 1e-3) / 1e6) < 1e-2 * d["value"]
+    rec = json.load(open(os.path.join(ROOT, "profiles", "hbm_traffic_mwa.json")))
+    assert r["traffic"] == round(rec["kernels"][r["kernel"]]["bytes_per_launch"])
+    c = d["cpu_baseline"]
+    assert c["kind"] == "oracle" and c["cores"] >= 1 and c["value"] > 0 and c["sample"]
