@@ -30,8 +30,12 @@ if ROOT not in sys.path:
 
 # Algorithmic work per (visibility, subgrid pixel): the 2x2 complex multiply-
 # accumulate is 16 FP32 FMAs, the phasor step ph <- ph * step is 4 FP32 ops
-# (2 mul + 2 FMA); each occupies one FMA issue slot, counted as 2 FLOP.
+# (2 mul + 2 FMA); each occupies one FMA issue slot, counted as 2 FLOP.  The
+# degridder executes exactly this form.  The gridder evaluates each row's channel
+# sum by Horner's rule (h <- h step + V_j: 16 FMA per pair, no separate phasor step),
+# so it executes 32 FLOP per pair; its rate is reported at both counts.
 FLOP_PER_VP = 40
+FLOP_PER_VP_EXECUTED = {"grid_dft": 32, "degrid_dft": 40}
 # FP32 vector peak of MI355X: 256 CUs x 4 SIMDs x 2.4 GHz, each SIMD issuing up to
 # two wave64 VALU instructions per 4 cycles (gfx950 VALU dual issue, counted by
 # SQ_ACTIVE_INST_VALU2) = 128 FMA per clock per CU = 157.3 TFLOP/s at 2 FLOP/FMA.
@@ -128,8 +132,24 @@ def workload_description(wl, info):
     }
 
 
-def cpu_baseline(wl, n_bl: int, aterm_mode: int = 0):
-    """FP64 oracle (test infrastructure) on a fixed random subset of baselines."""
+def sample_table(wl, table, sel):
+    """The plan's subgrids of baselines `sel`, renumbered for the sampled workload."""
+    pos = -np.ones(wl.n_baselines, np.int64)
+    pos[sel] = np.arange(len(sel))
+    t = table[pos[table["bl"]] >= 0].copy()
+    t["bl"] = pos[t["bl"]]
+    t["vis_offset"] = (t["bl"].astype(np.int64) * wl.n_times + t["t0"]) * wl.n_chans + t["c0"]
+    return t
+
+
+def cpu_baseline(wl, n_bl: int, plan_table, V, G, Vout, w0, aterm_mode: int = 0, stokes_i: bool = False):
+    """FP64 oracle (test infrastructure) on a fixed random subset of baselines, run on
+    the timed step's own data: it grids the sampled baselines' input visibilities V
+    with the plan's subgrids of those baselines (timed), and degrids the GPU's timed
+    grid G for the same subgrids (timed), which also checks the timed degridding output
+    Vout there visibility by visibility.  The timed grid itself is checked at 8 lattice
+    directions against L^2 T times the direct A-term image of all visibilities (exact
+    at lattice samples).  V, G, Vout: host arrays."""
     import oracle
     import synth
     rng = np.random.default_rng(2)
@@ -137,19 +157,44 @@ def cpu_baseline(wl, n_bl: int, aterm_mode: int = 0):
     sub = synth.Workload("mwa-sample", wl.n_stations, np.ascontiguousarray(wl.baselines[sel]),
                          np.ascontiguousarray(wl.uvw[sel]), wl.freqs, wl.grid_size, wl.subgrid_size,
                          wl.kernel_support, wl.pixel_scale, wl.aterm_interval, wl.aterms)
-    V = synth.random_vis((n_bl, wl.n_times, wl.n_chans), rng)
-    table = oracle.partition(sub, 0.0)
+    table = sample_table(wl, plan_table, sel)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    grid_fn = oracle.grid_stokes_i if stokes_i else oracle.grid
+    degrid_fn = oracle.degrid_stokes_i if stokes_i else oracle.degrid
     t0 = time.perf_counter()
-    G = oracle.grid(sub, V, table, nthreads=threads, aterm_mode=aterm_mode)
+    grid_fn(sub, V[sel], table, W=G.shape[0], nthreads=threads, aterm_mode=aterm_mode)
     t1 = time.perf_counter()
-    oracle.degrid(sub, G, table, nthreads=threads)
+    Vo = degrid_fn(sub, G, table, nthreads=threads)
     t2 = time.perf_counter()
     n = sub.n_vis
-    return {"value": round(n / (t2 - t0) / 1e6, 6), "unit": "Mvis/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n_bl} random baselines (seed 2) of the same observation, all 60 x 96 "
-                      f"visibilities each ({n} vis, {table.shape[0]} subgrids), grid then degrid at "
-                      f"full N, L, K; grid {t1 - t0:.2f} s, degrid {t2 - t1:.2f} s"}
+    out = {"value": round(n / (t2 - t0) / 1e6, 6), "unit": "Mvis/s", "cores": threads, "kind": "oracle",
+           "sample": f"{n_bl} random baselines (seed 2) of the timed observation, all 60 x 96 "
+                     f"visibilities each ({n} vis, the plan's {table.shape[0]} subgrids of them), grid "
+                     f"of the timed input then degrid of the GPU's timed grid at full N, L, K; "
+                     f"grid {t1 - t0:.2f} s, degrid {t2 - t1:.2f} s"}
+    # the timed degridding output at the sampled baselines, every visibility
+    d = np.linalg.norm(Vout[sel].astype(np.complex128) - Vo, axis=-1).ravel()
+    r = np.linalg.norm(Vo, axis=-1).ravel()
+    check = {"degrid_sampled": {"baselines": n_bl, "visibilities": int(d.size),
+                                "normwise": float(np.linalg.norm(d) / np.linalg.norm(r)),
+                                "max_over_rms": float(d.max() / np.sqrt(np.mean(r * r)))}}
+    # the timed grid at 8 lattice directions: sum_w exp(2 pi i w0 n1) layer image = L^2 T direct image
+    if aterm_mode == 0 and not stokes_i:
+        L = wl.subgrid_size
+        xs = rng.integers(0, L, 8).astype(np.int32)
+        ys = rng.integers(0, L, 8).astype(np.int32)
+        l, m = oracle.lattice_dirs(wl, xs, ys)
+        n1 = -(l * l + m * m) / (1 + np.sqrt(1 - l * l - m * m))
+        lhs = sum(oracle.layer_image_at(G[j], 1.0 / wl.fov, l, m, nthreads=threads)
+                  * np.exp(2j * np.pi * w0[j] * n1)[:, None] for j in range(G.shape[0]))
+        mask = oracle.coverage_mask(wl, plan_table)
+        T = oracle.taper(L, wl.kernel_support)
+        rhs = L * L * T[ys, xs][:, None] * oracle.direct_image(wl, V, l, m, xs, ys, mask=mask, nthreads=threads)
+        check["grid_lattice"] = {"directions": 8,
+                                 "normwise": float(np.linalg.norm(lhs - rhs) / np.linalg.norm(rhs)),
+                                 "max_over_max": float(np.abs(lhs - rhs).max() / np.abs(rhs).max())}
+    out["parity_of_timed_output"] = check
+    return out
 
 
 def serve_bench(args):
@@ -480,14 +525,38 @@ def dataclasses_replace(obj, **kw):
 
 
 def path_roofline(kt, wall_s):
-    """Sustained rate of the whole timed step: both DFT kernels' algorithmic FLOP
-    (40 per vp) over the wall time, which also covers the FFTs, the adder, the
-    splitter and the zeroing kernels."""
-    vp = sum(kt[k]["vis_pixels"] for k in ("grid_dft", "degrid_dft"))
-    achieved = vp * FLOP_PER_VP / wall_s / 1e12
+    """Sustained rate of the whole timed step: both DFT kernels' executed FLOP (32 per
+    vp for the Horner gridder, 40 for the degridder) over the wall time, which also
+    covers the FFTs, the adder, the splitter and the zeroing kernels."""
+    flop = sum(kt[k]["vis_pixels"] * FLOP_PER_VP_EXECUTED[k] for k in ("grid_dft", "degrid_dft"))
+    achieved = flop / wall_s / 1e12
     return {"achieved": round(achieved, 3), "peak": round(PEAK_FP32_TFLOPS, 1), "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-            "scope": "grid_dft + degrid_dft FLOP over the wall time of the timed steps"}
+            "scope": "grid_dft (32 FLOP per vp) + degrid_dft (40) executed FLOP over the wall time of the "
+                     "timed steps"}
+
+
+# Rates of the survey's roofline definition: FP32 FMA at the dual-issue peak, FP64 FMA at
+# the FP64 vector peak, and transcendental sin/cos at a quarter of the single-issue FP32
+# rate (an assumed figure: the phasor seeds here are FMA polynomials, not TRANS).
+R_PK_FMA = PEAK_FP32_TFLOPS * 1e12 / 2
+R_F64_FMA = 78.6e12 / 2
+R_TRANS = PEAK_FP32_SINGLE_ISSUE_TFLOPS * 1e12 / 2 / 4
+
+
+def rdef_roofline(table, L: int, R: int, ms: float) -> dict:
+    """The survey's roofline time of one DFT kernel launch over a plan's table,
+    T_roof = N_vp 20 / R_pk + N_seed (2 / R_trans + 8 / R_f64) + N_sg L^2 72 / R_pk,
+    with N_seed = sum over subgrids of nt L^2 (1 + ceil(nc / R)) phasor seeds (one step
+    phasor and one origin per R channels, per row and pixel), against the measured
+    launch time: frac = T_roof / T_meas."""
+    nt = table["nt"].astype(np.int64)
+    nc = table["nc"].astype(np.int64)
+    n_vp = int((nt * nc).sum()) * L * L
+    n_seed = int((nt * (1 + (nc + R - 1) // R)).sum()) * L * L
+    t = n_vp * 20 / R_PK_FMA + n_seed * (2 / R_TRANS + 8 / R_F64_FMA) + len(table) * L * L * 72 / R_PK_FMA
+    return {"t_roof_ms": round(t * 1e3, 3), "frac": round(t * 1e3 / ms, 4), "n_seed": n_seed,
+            "seeds_per_vp": round(n_seed / max(n_vp, 1), 5)}
 
 
 def main():
@@ -588,9 +657,14 @@ def main():
     else:
         roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": 8000.0, "unit": "GB/s",
                 "frac": None, "traffic": None}
+    table = plan.subgrids()
+    if dom in ("grid_dft", "degrid_dft"):
+        roof["rdef"] = rdef_roofline(table, wl.subgrid_size, 32, roof["avg_launch_ms"])
     kernels = {name: {"ms_per_step": round(v["ms"] / args.steps, 3),
                       "launches_per_step": v["launches"] / args.steps,
-                      **({"tflops": round(v["vis_pixels"] * FLOP_PER_VP / (v["ms"] * 1e-3) / 1e12, 3)}
+                      **({"tflops": round(v["vis_pixels"] * FLOP_PER_VP / (v["ms"] * 1e-3) / 1e12, 3),
+                          "tflops_executed": round(v["vis_pixels"] * FLOP_PER_VP_EXECUTED[name]
+                                                   / (v["ms"] * 1e-3) / 1e12, 3)}
                          if name in ("grid_dft", "degrid_dft") and v["ms"] > 0 else {})}
                for name, v in kt.items()}
     out = {
@@ -614,10 +688,16 @@ def main():
         "path_roofline": path_roofline(kt, wall),
         "kernels": kernels,
     }
-    plan.close()
-    del V, G, Vout, A
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_baselines, args.aterm_mode)
+        torch.cuda.synchronize()
+        w0 = plan.wlayers()
+        Vh, Gh, Vo = V.cpu().numpy(), G.cpu().numpy(), Vout.cpu().numpy()
+        plan.close()
+        del V, G, Vout, A
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_baselines, table, Vh, Gh, Vo, w0,
+                                           args.aterm_mode, bool(args.stokes_i))
+    else:
+        plan.close()
     print(json.dumps(out), flush=True)
 
 

@@ -313,6 +313,22 @@ aidg_status aidg_execute(aidg_executor* ex, const aidg_work* items, int32_t n_it
 
 void aidg_executor_destroy(aidg_executor* ex);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): aidg_execute without an executor.
+ * The group images live in a library-owned static device array of
+ * AIDG_STATIC_WORKSPACE_BYTES (128 MiB), one per device the library runs on, held
+ * until the process ends; its address is looked up on the first call on a device.
+ * workspace_bytes: how much of it the call may use (0 = all of it; a smaller budget
+ * makes more, smaller launches); AIDG_E_INVALID beyond AIDG_STATIC_WORKSPACE_BYTES.
+ * Items, ranges, ordering and errors as aidg_execute (every named plan waits for its
+ * earlier work, AIDG_E_BUSY if a plan is in use by another host thread).  The call
+ * allocates nothing and never synchronises the host.  All calls on one device share
+ * the array: calls whose work overlaps on the device race (queue them on one stream,
+ * or order them by events); no call needs the array cleared. */
+#define AIDG_STATIC_WORKSPACE_BYTES ((int64_t)128 << 20)
+aidg_status aidg_execute_static(const aidg_work* items, int32_t n_items, int64_t workspace_bytes,
+                                void* hip_stream);
+
 /* Thread-local description of the last non-OK status ("" if none). */
 const char* aidg_last_error(void);
 

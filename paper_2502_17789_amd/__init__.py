@@ -137,6 +137,7 @@ def library() -> ctypes.CDLL:
         "aidg_executor_create": (I32, [I64, P]),
         "aidg_execute": (I32, [P, P, I32, P]),
         "aidg_executor_destroy": (None, [P]),
+        "aidg_execute_static": (I32, [P, I32, I64, P]),
         "aidg_image_workspace_bytes": (I32, [P, P]),
         "aidg_invert": (I32, [P, P, P, P, I64, P]),
         "aidg_predict": (I32, [P, P, P, P, I64, P]),
@@ -348,6 +349,26 @@ class Plan:
         self.close()
 
 
+STATIC_WORKSPACE_BYTES = 128 << 20   # AIDG_STATIC_WORKSPACE_BYTES
+
+
+def _work_array(items):
+    items = list(items)
+    arr = (_Work * max(len(items), 1))()
+    for i, (plan, direction, tin, tout, b, e) in enumerate(items):
+        arr[i] = _Work(plan._h.value, int(direction), 0, tin.data_ptr(), tout.data_ptr(), int(b), int(e))
+    return arr, len(items)
+
+
+def execute_static(items, workspace_bytes: int = 0, stream=None):
+    """Grouped execution without an executor (``aidg_execute_static``): the group images
+    go to the library's static device workspace, so the call allocates nothing.
+    items as for ``Executor.execute``; workspace_bytes: budget within the static
+    workspace (0 = all of it)."""
+    arr, n = _work_array(items)
+    _check(library().aidg_execute_static(arr, n, int(workspace_bytes), _stream_handle(stream)))
+
+
 class Executor:
     """Grouped execution of subgrid ranges from many plans (``aidg_execute``)."""
 
@@ -358,11 +379,8 @@ class Executor:
 
     def execute(self, items, stream=None):
         """items: iterable of (plan, direction, in_tensor, out_tensor, sg_begin, sg_end)."""
-        items = list(items)
-        arr = (_Work * max(len(items), 1))()
-        for i, (plan, direction, tin, tout, b, e) in enumerate(items):
-            arr[i] = _Work(plan._h.value, int(direction), 0, tin.data_ptr(), tout.data_ptr(), int(b), int(e))
-        _check(library().aidg_execute(self._h, arr, len(items), _stream_handle(stream)))
+        arr, n = _work_array(items)
+        _check(library().aidg_execute(self._h, arr, n, _stream_handle(stream)))
 
     def close(self):
         if getattr(self, "_h", None):

@@ -16,6 +16,8 @@ constexpr int kMaxSubgridVisDefault = 1024;
 constexpr int kMaxSubgridVisLimit = 2048;
 constexpr int kReseedDefault = 32;
 constexpr int64_t kWorkspaceDefault = int64_t(2) << 30;
+// Size of the static subgrid workspace of aidg_execute_static (AIDG_STATIC_WORKSPACE_BYTES).
+constexpr int64_t kStaticWorkspaceBytes = int64_t(128) << 20;
 // A group of same-centre subgrids holds at most this many times the mean
 // visibilities per centre (and at least one subgrid).
 constexpr int64_t kGroupVisFactor = 8;
@@ -135,6 +137,11 @@ int launch_image_fft_rows(int precision, int dir, bool predict, const void* src,
 int launch_image_transpose(int precision, const void* src, void* dst, int N, void* stream);
 int launch_image_wstack(int precision, const void* B, void* img, int N, const double* itaper, double dl,
                         double w0, double inv_l2, int assign, const double* nmap, int L, void* stream);
+
+// Device address of the static workspace (kStaticWorkspaceBytes) on `device`, which
+// must be the current device; looked up on the first call per device, then cached.
+// Null with a message in *err on failure (static_workspace.hip).
+void* static_workspace(int device, std::string* err);
 
 // Inverse A-term mode (aterm.hip): (A^-1)^H of n 2x2 matrices, and the weighted-average
 // normalisation map [L2] from (A_p plane, A_q plane) pairs [n_pairs][2] with their

@@ -292,6 +292,107 @@ aidg_status image_step(aidg_plan* p, hipStream_t st, KernelClass k, F&& launch) 
   return AIDG_OK;
 }
 
+// Shared body of aidg_execute and aidg_execute_static: pack the items' ranges into
+// grouped launches whose group images fit in `scratch` (scratch_bytes), after the
+// named plans' earlier work and, when `last` is given, after the event's; record the
+// plans' events and `last` behind the launches.
+aidg_status execute_items(void* scratch, int64_t scratch_bytes, hipEvent_t last, const aidg_work* items,
+                          int32_t n_items, void* hip_stream) {
+  if ((n_items > 0 && !items) || n_items < 0) return fail(AIDG_E_INVALID, "bad items");
+  for (int32_t i = 0; i < n_items; ++i) {
+    const aidg_work& w = items[i];
+    if (!w.plan || !w.in || !w.out || (w.direction != AIDG_DIR_GRID && w.direction != AIDG_DIR_DEGRID) ||
+        w.sg_begin < 0 || w.sg_end < w.sg_begin || w.sg_end > (int64_t)w.plan->table.size())
+      return fail(AIDG_E_INVALID, "work item " + std::to_string(i) + ": bad plan, buffers, direction or range");
+  }
+  std::vector<aidg_plan*> plans;
+  for (int32_t i = 0; i < n_items; ++i)
+    if (std::find(plans.begin(), plans.end(), items[i].plan) == plans.end()) plans.push_back(items[i].plan);
+  size_t held = 0;
+  for (; held < plans.size(); ++held) {
+    bool ex2 = false;
+    if (!plans[held]->busy.compare_exchange_strong(ex2, true)) break;
+  }
+  auto release = [&]() {
+    for (size_t k = 0; k < held; ++k) plans[k]->busy.store(false);
+  };
+  if (held < plans.size()) {
+    release();
+    return fail(AIDG_E_BUSY, "a plan is in use by another thread");
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  aidg_status r = AIDG_OK;
+  hipError_t e = last ? hipStreamWaitEvent(st, last, 0) : hipSuccess;
+  for (aidg_plan* p : plans)
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, p->last, 0);
+  if (e != hipSuccess) r = hip_fail(e, "hipStreamWaitEvent");
+  // degridding ranges that start the table also clear the excluded visibilities
+  for (int32_t i = 0; i < n_items && r == AIDG_OK; ++i) {
+    const aidg_work& w = items[i];
+    if (w.direction == AIDG_DIR_DEGRID && w.sg_begin == 0 && w.plan->n_excluded > 0) {
+      const int rc = launch_zero_vis(w.plan->g.precision, w.plan->d_excl, w.plan->n_excluded, w.out,
+                                     hip_stream);
+      if (rc != 0) r = hip_fail((hipError_t)rc, "zeroing excluded visibilities");
+    }
+  }
+  // group by (direction, L, precision); pack ranges into launches
+  std::vector<bool> done(n_items, false);
+  for (int32_t i0 = 0; i0 < n_items && r == AIDG_OK; ++i0) {
+    if (done[i0]) continue;
+    const int dir = items[i0].direction, L = items[i0].plan->g.L, prec = items[i0].plan->g.precision;
+    const int64_t per_sg = (int64_t)4 * L * L * (prec == AIDG_FP32 ? 8 : 16);
+    const int64_t cap = std::min<int64_t>(scratch_bytes / per_sg, 65535);
+    if (cap < 1) {
+      r = fail(AIDG_E_INVALID, "workspace smaller than one subgrid image");
+      break;
+    }
+    Group g;
+    std::memset(&g, 0, sizeof(g));
+    g.scratch = scratch;
+    int max_nv = 1;
+    auto flush = [&]() -> aidg_status {
+      if (g.total_sg == 0) return AIDG_OK;
+      const KernelClass k0 = dir == AIDG_DIR_GRID ? kGridDft : kSplitIfft;
+      const KernelClass k1 = dir == AIDG_DIR_GRID ? kFftAdd : kDegridDft;
+      int rc = launch_group(k0, L, prec, g, hip_stream, max_nv);
+      if (rc == 0) rc = launch_group(k1, L, prec, g, hip_stream, max_nv);
+      std::memset(&g, 0, sizeof(g));
+      g.scratch = scratch;
+      max_nv = 1;
+      return rc == 0 ? AIDG_OK : hip_fail((hipError_t)rc, "grouped kernel launch");
+    };
+    for (int32_t i = i0; i < n_items && r == AIDG_OK; ++i) {
+      const aidg_work& w = items[i];
+      if (done[i] || w.direction != dir || w.plan->g.L != L || w.plan->g.precision != prec) continue;
+      done[i] = true;
+      // a launch takes whole or partial groups until `cap` group images
+      const aidg_plan* p = w.plan;
+      for (int64_t b = w.sg_begin; b < w.sg_end && r == AIDG_OK;) {
+        if (g.n == kMaxGroup || g.total_grp == cap) r = flush();
+        if (r != AIDG_OK) break;
+        const int64_t g0 = p->sg_group[b], room = cap - g.total_grp;
+        const int64_t gn = (int64_t)p->grp_begin.size() - 1;
+        const int64_t e = g0 + room < gn ? std::min(w.sg_end, p->grp_begin[g0 + room]) : w.sg_end;
+        g.job[g.n] = {p->d_args, w.in, w.out, b, e, g0, g.total_sg, g.total_grp};
+        g.n += 1;
+        g.total_sg += e - b;
+        g.total_grp += p->sg_group[e - 1] - g0 + 1;
+        max_nv = std::max(max_nv, p->max_nv);
+        b = e;
+      }
+    }
+    if (r == AIDG_OK) r = flush();
+  }
+  if (r == AIDG_OK) {
+    e = last ? hipEventRecord(last, st) : hipSuccess;
+    for (aidg_plan* p : plans)
+      if (e == hipSuccess) e = hipEventRecord(p->last, st);
+    if (e != hipSuccess) r = hip_fail(e, "hipEventRecord");
+  }
+  release();
+  return r;
+}
+
 }  // namespace
 
 extern "C" {
@@ -893,102 +994,30 @@ aidg_status aidg_executor_create(int64_t workspace_bytes, aidg_executor** out) {
 }
 
 aidg_status aidg_execute(aidg_executor* ex, const aidg_work* items, int32_t n_items, void* hip_stream) {
-  if (!ex || (n_items > 0 && !items) || n_items < 0) return fail(AIDG_E_INVALID, "bad executor or items");
-  for (int32_t i = 0; i < n_items; ++i) {
-    const aidg_work& w = items[i];
-    if (!w.plan || !w.in || !w.out || (w.direction != AIDG_DIR_GRID && w.direction != AIDG_DIR_DEGRID) ||
-        w.sg_begin < 0 || w.sg_end < w.sg_begin || w.sg_end > (int64_t)w.plan->table.size())
-      return fail(AIDG_E_INVALID, "work item " + std::to_string(i) + ": bad plan, buffers, direction or range");
-  }
+  if (!ex) return fail(AIDG_E_INVALID, "NULL executor");
   bool expected = false;
   if (!ex->busy.compare_exchange_strong(expected, true)) return fail(AIDG_E_BUSY, "executor in use");
-  std::vector<aidg_plan*> plans;
-  for (int32_t i = 0; i < n_items; ++i)
-    if (std::find(plans.begin(), plans.end(), items[i].plan) == plans.end()) plans.push_back(items[i].plan);
-  size_t held = 0;
-  for (; held < plans.size(); ++held) {
-    bool ex2 = false;
-    if (!plans[held]->busy.compare_exchange_strong(ex2, true)) break;
-  }
-  auto release = [&]() {
-    for (size_t k = 0; k < held; ++k) plans[k]->busy.store(false);
-    ex->busy.store(false);
-  };
-  if (held < plans.size()) {
-    release();
-    return fail(AIDG_E_BUSY, "a plan is in use by another thread");
-  }
-  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
-  aidg_status r = AIDG_OK;
-  hipError_t e = hipStreamWaitEvent(st, ex->last, 0);
-  for (aidg_plan* p : plans)
-    if (e == hipSuccess) e = hipStreamWaitEvent(st, p->last, 0);
-  if (e != hipSuccess) r = hip_fail(e, "hipStreamWaitEvent");
-  // degridding ranges that start the table also clear the excluded visibilities
-  for (int32_t i = 0; i < n_items && r == AIDG_OK; ++i) {
-    const aidg_work& w = items[i];
-    if (w.direction == AIDG_DIR_DEGRID && w.sg_begin == 0 && w.plan->n_excluded > 0) {
-      const int rc = launch_zero_vis(w.plan->g.precision, w.plan->d_excl, w.plan->n_excluded, w.out,
-                                     hip_stream);
-      if (rc != 0) r = hip_fail((hipError_t)rc, "zeroing excluded visibilities");
-    }
-  }
-  // group by (direction, L, precision); pack ranges into launches
-  std::vector<bool> done(n_items, false);
-  for (int32_t i0 = 0; i0 < n_items && r == AIDG_OK; ++i0) {
-    if (done[i0]) continue;
-    const int dir = items[i0].direction, L = items[i0].plan->g.L, prec = items[i0].plan->g.precision;
-    const int64_t per_sg = (int64_t)4 * L * L * (prec == AIDG_FP32 ? 8 : 16);
-    const int64_t cap = std::min<int64_t>(ex->bytes / per_sg, 65535);
-    if (cap < 1) {
-      r = fail(AIDG_E_INVALID, "executor workspace smaller than one subgrid");
-      break;
-    }
-    Group g;
-    std::memset(&g, 0, sizeof(g));
-    g.scratch = ex->d_scratch;
-    int max_nv = 1;
-    auto flush = [&]() -> aidg_status {
-      if (g.total_sg == 0) return AIDG_OK;
-      const KernelClass k0 = dir == AIDG_DIR_GRID ? kGridDft : kSplitIfft;
-      const KernelClass k1 = dir == AIDG_DIR_GRID ? kFftAdd : kDegridDft;
-      int rc = launch_group(k0, L, prec, g, hip_stream, max_nv);
-      if (rc == 0) rc = launch_group(k1, L, prec, g, hip_stream, max_nv);
-      std::memset(&g, 0, sizeof(g));
-      g.scratch = ex->d_scratch;
-      max_nv = 1;
-      return rc == 0 ? AIDG_OK : hip_fail((hipError_t)rc, "grouped kernel launch");
-    };
-    for (int32_t i = i0; i < n_items && r == AIDG_OK; ++i) {
-      const aidg_work& w = items[i];
-      if (done[i] || w.direction != dir || w.plan->g.L != L || w.plan->g.precision != prec) continue;
-      done[i] = true;
-      // a launch takes whole or partial groups until `cap` group images
-      const aidg_plan* p = w.plan;
-      for (int64_t b = w.sg_begin; b < w.sg_end && r == AIDG_OK;) {
-        if (g.n == kMaxGroup || g.total_grp == cap) r = flush();
-        if (r != AIDG_OK) break;
-        const int64_t g0 = p->sg_group[b], room = cap - g.total_grp;
-        const int64_t gn = (int64_t)p->grp_begin.size() - 1;
-        const int64_t e = g0 + room < gn ? std::min(w.sg_end, p->grp_begin[g0 + room]) : w.sg_end;
-        g.job[g.n] = {p->d_args, w.in, w.out, b, e, g0, g.total_sg, g.total_grp};
-        g.n += 1;
-        g.total_sg += e - b;
-        g.total_grp += p->sg_group[e - 1] - g0 + 1;
-        max_nv = std::max(max_nv, p->max_nv);
-        b = e;
-      }
-    }
-    if (r == AIDG_OK) r = flush();
-  }
-  if (r == AIDG_OK) {
-    e = hipEventRecord(ex->last, st);
-    for (aidg_plan* p : plans)
-      if (e == hipSuccess) e = hipEventRecord(p->last, st);
-    if (e != hipSuccess) r = hip_fail(e, "hipEventRecord");
-  }
-  release();
+  const aidg_status r = execute_items(ex->d_scratch, ex->bytes, ex->last, items, n_items, hip_stream);
+  ex->busy.store(false);
   return r;
+}
+
+aidg_status aidg_execute_static(const aidg_work* items, int32_t n_items, int64_t workspace_bytes,
+                                void* hip_stream) {
+  if (workspace_bytes < 0 || workspace_bytes > kStaticWorkspaceBytes)
+    return fail(AIDG_E_INVALID, "workspace_bytes " + std::to_string(workspace_bytes) +
+                                    " outside 0.." + std::to_string(kStaticWorkspaceBytes) +
+                                    " (the static workspace's size, AIDG_STATIC_WORKSPACE_BYTES)");
+  if ((n_items > 0 && !items) || n_items < 0) return fail(AIDG_E_INVALID, "bad items");
+  if (n_items == 0) return AIDG_OK;
+  int device = 0;
+  const hipError_t e = hipGetDevice(&device);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  std::string err;
+  void* ws = static_workspace(device, &err);
+  if (!ws) return fail(AIDG_E_DEVICE, err);
+  return execute_items(ws, workspace_bytes ? workspace_bytes : kStaticWorkspaceBytes, nullptr, items, n_items,
+                       hip_stream);
 }
 
 void aidg_executor_destroy(aidg_executor* ex) {

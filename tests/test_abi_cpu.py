@@ -156,3 +156,19 @@ def test_product_never_imports_the_oracle():
                 text = open(os.path.join(dirpath, f), encoding="utf-8").read()
                 assert not re.search(r"^\s*(import|from)\s+oracle\b", text, re.M), f
                 assert "liboracle" not in text and "oracle.cpp" not in text, f
+
+
+def test_execute_static_rejects_budgets_beyond_its_workspace():
+    """aidg_execute_static checks its workspace budget before any device call: beyond
+    AIDG_STATIC_WORKSPACE_BYTES (and below 0) it returns AIDG_E_INVALID with a message;
+    an empty item list within the budget is a no-op."""
+    lib = aidg.library()
+    header = open(os.path.join(ROOT, "include", "aidg.h")).read()
+    assert "#define AIDG_STATIC_WORKSPACE_BYTES ((int64_t)128 << 20)" in header
+    assert aidg.STATIC_WORKSPACE_BYTES == 128 << 20
+    for bad in (aidg.STATIC_WORKSPACE_BYTES + 1, -1, 1 << 40):
+        assert lib.aidg_execute_static(None, 0, bad, None) == aidg.AIDG_E_INVALID
+        assert b"AIDG_STATIC_WORKSPACE_BYTES" in lib.aidg_last_error()
+    assert lib.aidg_execute_static(None, 0, 0, None) == aidg.AIDG_OK
+    assert lib.aidg_execute_static(None, 0, aidg.STATIC_WORKSPACE_BYTES, None) == aidg.AIDG_OK
+    assert lib.aidg_execute_static(None, -1, 0, None) == aidg.AIDG_E_INVALID

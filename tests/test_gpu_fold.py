@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 
 import synth
+from gates import check_grid, check_vis
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -73,10 +74,9 @@ def test_fold_matches_oracle(aidg, orc, name, precision):
         G = synth.random_grid(W, wl.grid_size, rng)
         Gg = host(p.grid(dev(V, precision)))
         Vg = host(p.degrid(dev(G, precision)))
-    eg = rel(Gg, orc.grid(wl, V, table, W=W))
-    ev = rel(Vg, orc.degrid(wl, G, table))
-    print(f"fold {name} {'FP64' if precision else 'FP32'} W={W}: grid {eg:.2e} degrid {ev:.2e}", flush=True)
-    assert eg <= TOL[precision] and ev <= TOL[precision]
+    tag = f"fold {name} {'FP64' if precision else 'FP32'} W={W}"
+    check_grid(Gg, orc.grid(wl, V, table, W=W), TOL[precision], tag + " grid")
+    check_vis(Vg, orc.degrid(wl, G, table), TOL[precision], tag + " degrid")
 
 
 def lattice(wl, rng, n):
@@ -104,8 +104,6 @@ def test_fold_image_and_prediction_are_exact_at_lattice_points(aidg, orc, name):
     l, m = orc.lattice_dirs(wl, xs, ys)
     mask = orc.coverage_mask(wl, table)
     ref = orc.direct_image(wl, V, l, m, xs, ys, mask=mask)
-    ei = rel(herm_part(img[:, Y, X].T), herm_part(ref))
+    check_grid(herm_part(img[:, Y, X].T), herm_part(ref), 1e-5, f"fold {name} Hermitian image")
     Vd = orc.direct_predict(wl, src["l"], src["m"], src["B"], src["xs"], src["ys"])
-    ev = rel(Vp[mask.astype(bool)], Vd[mask.astype(bool)])
-    print(f"fold {name}: Hermitian image {ei:.2e}, prediction {ev:.2e}", flush=True)
-    assert ei <= 1e-5 and ev <= 1e-5
+    check_vis(Vp[mask.astype(bool)], Vd[mask.astype(bool)], 1e-5, f"fold {name} prediction")

@@ -22,6 +22,7 @@ import numpy as np
 import pytest
 
 import synth
+from gates import check_grid, check_vis
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -100,10 +101,10 @@ def test_inverse_mode_matches_oracle(aidg, orc, name, precision):
     Mo = orc.aterm_norm(wl, table)
     Io = orc.invert(Go, w0, L, K, wl.pixel_scale, norm=Mo)
     q = wl.grid_size // 4
-    eg, em, ei = rel(Gg, Go), rel(M, Mo), rel(I[:, q:3 * q, q:3 * q], Io[:, q:3 * q, q:3 * q])
-    print(f"inverse {name} {'FP64' if precision else 'FP32'} W={W}: grid {eg:.2e} map {em:.2e} "
-          f"image {ei:.2e}", flush=True)
-    assert eg <= TOL[precision] and em <= TOL[precision] and ei <= TOL[precision]
+    tag = f"inverse {name} {'FP64' if precision else 'FP32'} W={W}"
+    check_grid(Gg, Go, TOL[precision], tag + " grid")
+    check_grid(M, Mo, TOL[precision], tag + " normalisation map")
+    check_grid(I[:, q:3 * q, q:3 * q], Io[:, q:3 * q, q:3 * q], TOL[precision], tag + " image")
     if c.get("blind"):
         assert Mo.min() > 0  # other baselines still see the corner
     # the normalisation is not trivial here
@@ -117,7 +118,7 @@ def test_inverse_mode_degrid_is_the_adjoint_modes(aidg):
         G = dev(synth.random_grid(pa.n_wlayers, wl.grid_size, rng), 0)
         va = host(pa.degrid(G))
         vi = host(pi.degrid(G))
-    assert rel(vi, va) <= 1e-6
+    check_vis(vi, va, 1e-6, "inverse-mode degrid vs adjoint-mode degrid")
 
 
 def test_set_aterms_recomputes_the_inverse(aidg, orc):
@@ -130,8 +131,8 @@ def test_set_aterms_recomputes_the_inverse(aidg, orc):
         table = p.subgrids()
         Gg = host(p.grid(dev(V, 0)))
         M = p.aterm_norm()
-    assert rel(Gg, orc.grid(wl2, V, table, W=1, aterm_mode=1)) <= TOL[0]
-    assert rel(M, orc.aterm_norm(wl2, table)) <= TOL[0]
+    check_grid(Gg, orc.grid(wl2, V, table, W=1, aterm_mode=1), TOL[0], "new A-terms grid")
+    check_grid(M, orc.aterm_norm(wl2, table), TOL[0], "new A-terms normalisation map")
 
 
 def test_adjoint_mode_has_no_normalisation_map(aidg):
@@ -155,9 +156,7 @@ def test_inverse_mode_image_of_a_lattice_source_is_its_brightness(aidg, orc, pre
         Kc = p.info["n_vis"] - p.info["n_excluded"]
     X = N // 2 + (int(src["xs"][0]) - L // 2) * (N // L)
     Y = N // 2 + (int(src["ys"][0]) - L // 2) * (N // L)
-    e = rel(I[:, Y, X], Kc * src["B"][0])
-    print(f"lattice source {'FP64' if precision else 'FP32'}: {e:.2e}", flush=True)
-    assert e <= TOL[precision]
+    check_grid(I[:, Y, X], Kc * src["B"][0], TOL[precision], f"lattice source {'FP64' if precision else 'FP32'}")
 
 
 def test_inverse_mode_with_no_gridded_visibilities(aidg):
@@ -194,5 +193,6 @@ def test_grouped_launch_mixes_inverse_and_adjoint_plans(aidg):
             got = [host(t) for t in out]
         finally:
             ex.close()
-    assert rel(got[0], ref[0]) <= 1e-6 and rel(got[1], ref[1]) <= 1e-6
+    check_grid(got[0], ref[0], 1e-6, "grouped inverse-mode grid")
+    check_grid(got[1], ref[1], 1e-6, "grouped adjoint-mode grid")
     assert rel(ref[0], ref[1]) > 1e-2  # the two modes differ on these Jones terms
