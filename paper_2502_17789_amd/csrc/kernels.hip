@@ -78,21 +78,14 @@ __device__ __forceinline__ int64_t degrid_slot(int64_t b, int64_t n) {
 #endif
 constexpr int kPix = GRID_PIX;              // pixels per lane in the gridder
 constexpr int kChunk = kThreads * kPix;     // pixels per workgroup pass
-#ifndef DEGRID_LDS_REDUCE
-#define DEGRID_LDS_REDUCE 1
-#endif
-#ifndef DEGRID_GROUP
-#define DEGRID_GROUP 4  // compile-time tile parameter; 4 measured faster than 2
-#endif
-constexpr int kVisGroup = DEGRID_GROUP;     // channels per degridder reduction (2 or 4)
-static_assert(kVisGroup == 2 || kVisGroup == 4, "even group: phasor ping-pong restarts in the first set");
-
-// Degridder tiling: P pixels per lane (more pixels amortise the per-visibility
-// cross-lane reduction; 256 * P must divide L^2) and the waves per SIMD the
-// register allocation aims at (W; 1 leaves it to the compiler).  At L = 96 in
-// FP32, P = 6 at 3 waves per SIMD measured faster than P = 9 at 2 and P = 4 at 4.
-template <int L, typename R> struct DegridTune { static constexpr int P = L == 32 ? 4 : L == 64 ? 8 : 6, W = 1; };
-template <> struct DegridTune<96, float> { static constexpr int P = 6, W = 3; };
+// Degridder tiling: NT threads per workgroup (one subgrid), P pixels per lane (NT P
+// divides L^2; more pixels amortise the cross-lane reduction per visibility over more
+// work) and the waves per SIMD the register allocation aims at (W).
+template <int L, typename R> struct DegridTune;
+template <> struct DegridTune<32, float> { static constexpr int NT = 128, P = 8, W = 3; };
+template <> struct DegridTune<64, float> { static constexpr int NT = 256, P = 8, W = 3; };
+template <> struct DegridTune<96, float> { static constexpr int NT = 256, P = 9, W = 3; };
+template <int L> struct DegridTune<L, double> { static constexpr int NT = 256, P = 4, W = 2; };
 
 struct Pixel {
   int pix, x, y;
@@ -535,151 +528,107 @@ __device__ __forceinline__ double dpp(double x) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-constexpr int kDppRowRor8 = 0x128, kDppHalfMirror = 0x141, kDppXor2 = 0x4E, kDppXor1 = 0xB1;
+constexpr int kDppXor2 = 0x4E, kDppXor1 = 0xB1;  // quad_perm [2,3,0,1] and [1,0,3,2]
 
-// Sum 32 per-lane values over the 64 lanes of a wave.  On return lane `ln` holds
-// the full sum of value index (ln >> 1) (both lanes of a pair hold it).
-template <typename R>
-__device__ __forceinline__ R transpose_reduce32(R (&a)[32], int ln) {
-  // lanes ln, ln^32: halves of a wave (permlane32 swap)
-#pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    swap32(a[i], a[i + 16]);
-    a[i] = a[i] + a[i + 16];  // lanes 0-31: value i, lanes 32-63: value i+16
-  }
-  // lanes ln, ln^16: rows of 16 (permlane16 swap)
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    swap16(a[i], a[i + 8]);
-    a[i] = a[i] + a[i + 8];  // row r holds value i + 8r
-  }
-  // lanes ln, ln^8 (row rotate by 8)
-  const bool b3 = ln & 8, b2 = ln & 4, b1 = ln & 2;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const R keep = b3 ? a[i + 4] : a[i], send = b3 ? a[i] : a[i + 4];
-    a[i] = keep + dpp<kDppRowRor8>(send);  // value i + 4 b3 + 8 row
-  }
-  // lanes ln, ln^7 (half-row mirror)
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const R keep = b2 ? a[i + 2] : a[i], send = b2 ? a[i] : a[i + 2];
-    a[i] = keep + dpp<kDppHalfMirror>(send);  // value i + 2 b2 + 4 b3 + 8 row
-  }
-  // lanes ln, ln^2
-  {
-    const R keep = b1 ? a[1] : a[0], send = b1 ? a[0] : a[1];
-    a[0] = keep + dpp<kDppXor2>(send);  // value b1 + 2 b2 + 4 b3 + 8 row = ln >> 1
-  }
-  // lanes ln, ln^1 hold the same value index: add
-  return a[0] + dpp<kDppXor1>(a[0]);
+// Degridder channel blocks: the waves' reduced values of up to kChanBlock channels of a
+// row meet in LDS and are added to the output in a fixed order once per block.
+constexpr int kChanBlock = 32;
+// LDS row pitch (elements) of the reduction area: 68 puts the four rows of 16 lanes on
+// different banks for both the 16-byte stores and the strided loads.
+constexpr int kRedPitch = 68;
+
+// What a phasor seed needs of a subgrid pixel, kept in LDS (one entry per pixel of the
+// chunk, each read only by the lane that owns the pixel) rather than in registers.
+struct alignas(16) SeedPixel {
+  double n1;     // n - 1
+  float dx, dy;  // x - L/2, y - L/2
+};
+
+template <int L, typename R>
+constexpr size_t degrid_lds_bytes() {
+  using D = DegridTune<L, R>;
+  return (size_t)D::NT * D::P * sizeof(SeedPixel)               // the lanes' pixels
+         + (size_t)(D::NT / 64) * 4 * kRedPitch * sizeof(R)     // per-wave reduction areas
+         + (size_t)2 * (D::NT / 64) * kChanBlock * 8 * sizeof(R);  // double-buffered stage
 }
 
-// Sum 16 per-lane values over the 64 lanes of a wave.  On return lane `ln` holds
-// the full sum of value index (ln >> 2).
+// Sum 16 per-lane values over the 64 lanes of a wave.  Two permlane swap levels in
+// registers leave lane (r, c) = (ln >> 4, ln & 15) with partials of values 4 r + i,
+// i < 4, each over the four lanes c + 16 k; the 16 partials of each value then meet in
+// the wave's LDS area (private to the wave, whose LDS operations complete in issue
+// order; the wave barriers keep the compiler from moving this call's stores above the
+// previous call's loads, or its loads above its stores), four per lane, and a quad DPP
+// sum finishes.  On return lane ln holds the full sum of value 4 (ln >> 4) + ((ln & 15) >> 2)
+// (the four lanes of a quad agree).
 template <typename R>
-__device__ __forceinline__ R transpose_reduce16(R (&a)[16], int ln) {
+__device__ __forceinline__ R reduce16(R (&a)[16], int ln, R* area) {
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
     swap32(a[i], a[i + 8]);
-    a[i] = a[i] + a[i + 8];  // lanes 0-31: value i, lanes 32-63: value i+8
+    a[i] = a[i] + a[i + 8];  // lanes 0-31: value i, lanes 32-63: value i + 8
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     swap16(a[i], a[i + 4]);
-    a[i] = a[i] + a[i + 4];  // row r holds value i + 4r
+    a[i] = a[i] + a[i + 4];  // row r of 16 lanes: value i + 4 r
   }
-  const bool b3 = ln & 8, b2 = ln & 4;
+  const int r = ln >> 4, c = ln & 15;
+  __builtin_amdgcn_wave_barrier();
+  R* w = area + r * kRedPitch + 4 * c;
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const R keep = b3 ? a[i + 2] : a[i], send = b3 ? a[i] : a[i + 2];
-    a[i] = keep + dpp<kDppRowRor8>(send);  // value i + 2 b3 + 4 row
-  }
-  {
-    const R keep = b2 ? a[1] : a[0], send = b2 ? a[0] : a[1];
-    a[0] = keep + dpp<kDppHalfMirror>(send);  // value b2 + 2 b3 + 4 row = ln >> 2
-  }
-  // lanes ln, ln^2, ln^1 (and the mirror partner above) share the value index
-  a[0] = a[0] + dpp<kDppXor2>(a[0]);
-  return a[0] + dpp<kDppXor1>(a[0]);
+  for (int i = 0; i < 4; ++i) w[i] = a[i];
+  __builtin_amdgcn_wave_barrier();
+  const R* src = area + r * kRedPitch + 16 * (c & 3) + (c >> 2);
+  R v = (src[0] + src[4]) + (src[8] + src[12]);
+  v = v + dpp<kDppXor1>(v);
+  return v + dpp<kDppXor2>(v);
 }
 
-// Per-wave LDS area of the staged reduction below: 32 values x 16 partials at a
-// pitch of 18 floats, which puts the 4 rows of 16 lanes on disjoint banks.
-constexpr int kStagePitch = 18, kStageFloats = 32 * kStagePitch;
-constexpr int kStageBytes = (kThreads / 64) * kStageFloats * 4;
-
-// FP32 variant of transpose_reduce32: the two permlane levels in registers leave
-// lane ln with partials of values i + 8 (ln >> 4) over 4 lanes; the 16 partials
-// of each value then meet in the wave's LDS area (8 stores, 8 loads, 8 adds per
-// lane instead of 22 select/DPP instructions).  On return lane ln holds the full
-// sum of value (ln >> 1) (both lanes of a pair).  The area is private to the
-// wave, whose LDS accesses complete in order, so no barrier is needed.
-__device__ __forceinline__ float transpose_reduce32_lds(float (&a)[32], int ln, float* st) {
-#pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    swap32(a[i], a[i + 16]);
-    a[i] = a[i] + a[i + 16];
-  }
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    swap16(a[i], a[i + 8]);
-    a[i] = a[i] + a[i + 8];
-  }
-  const int row = ln >> 4, c = ln & 15;
-  // The area is private to this wave, whose LDS operations complete in issue order;
-  // the wave barriers keep the compiler from moving this call's stores above the
-  // previous call's loads, or its loads above its stores.
-  __builtin_amdgcn_wave_barrier();
-#pragma unroll
-  for (int i = 0; i < 8; ++i) st[(i + 8 * row) * kStagePitch + c] = a[i];
-  __builtin_amdgcn_wave_barrier();
-  const float* src = st + (ln >> 1) * kStagePitch + 8 * (ln & 1);
-  float s = ((src[0] + src[1]) + (src[2] + src[3])) + ((src[4] + src[5]) + (src[6] + src[7]));
-  return s + dpp<kDppXor1>(s);
-}
+// Phasors of the degridder: exp(-2 pi i theta) with theta given through quarter-turn
+// coefficients (the caller passes -4 theta).
+__device__ __forceinline__ float2 dphasor(double theta4, float) { return phasor4(theta4); }
+__device__ __forceinline__ double2 dphasor(double theta4, double) { return phasor4_f64(theta4); }
 
 template <int L, typename R>
-__global__ __launch_bounds__(kThreads)
+__global__ __launch_bounds__((DegridTune<L, R>::NT))
 __attribute__((amdgpu_waves_per_eu(DegridTune<L, R>::W))) void degrid_dft(const Group g) {
   using V2 = typename C2<R>::T;
-  constexpr int P = DegridTune<L, R>::P, CH = kThreads * P;
+  constexpr int NT = DegridTune<L, R>::NT, P = DegridTune<L, R>::P, CH = NT * P, NW = NT / 64;
   static_assert((L * L) % CH == 0, "pixel chunks must tile the subgrid");
   extern __shared__ unsigned char smem_raw[];
-  float* stage = reinterpret_cast<float*>(smem_raw) + (threadIdx.x >> 6) * kStageFloats;
-  R* accs = reinterpret_cast<R*>(smem_raw + kStageBytes);
+  SeedPixel* pxt = reinterpret_cast<SeedPixel*>(smem_raw);           // [CH]
+  R* red = reinterpret_cast<R*>(smem_raw + CH * sizeof(SeedPixel));  // [NW][4][kRedPitch]
+  R* stage = red + NW * 4 * kRedPitch;                               // [2][NW][kChanBlock][8]
+  const int wave = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  R* area = red + wave * 4 * kRedPitch;
   const int64_t local = degrid_slot(blockIdx.x, g.total_sg);
   const Slot sl = resolve(g, local);
   const KernelArgs& a = sl.a;
   const SubgridDev& s = sl.s;
   const R* __restrict__ scratch = reinterpret_cast<const R*>(g.scratch);
   R* __restrict__ vis = reinterpret_cast<R*>(sl.out);
-  const int nv = s.nt * s.nc;
-  for (int i = threadIdx.x; i < nv * 8; i += kThreads) accs[i] = 0;
-  __syncthreads();
-  const int ln = threadIdx.x & 63;
   const V2* At = reinterpret_cast<const V2*>(a.aterms);
   const R* taper = reinterpret_cast<const R*>(a.taper);
   const V2* img = reinterpret_cast<const V2*>(scratch) + sl.img_slot * 4 * L * L;
   const double u0 = (s.U0 - a.N / 2) * a.du, v0 = (s.V0 - a.N / 2) * a.du;
+  // channels per FP32 recurrence run: even (runs start at even channel offsets); 1 means
+  // every channel is seeded (irregular channel spacing)
+  const int Rs = s.R <= 1 ? 1 : (s.R & ~1);
+  // the value this lane owns after reduce16: channel offset (0 or 1) and component
+  const int vidx = 4 * (ln >> 4) + ((ln & 15) >> 2);
+  const bool owner = (ln & 3) == 0;
+  int buf = 0;
 
   for (int chunk = 0; chunk < (L * L) / CH; ++chunk) {
-    // Pixel offsets from the centre, (x - L/2) in the low and (y - L/2) in the high
-    // half-word: (l, m) are rebuilt from them at every phasor seed without a division.
-    int xy[P];
-    double n1[P];
+    // the pixels' offsets from the centre and n - 1 go to the lane's own LDS entries
     V2 sp[P][4];
-    auto lm = [&](int p) {
-      const int dx = (int)(short)(xy[p] & 0xffff), dy = xy[p] >> 16;
-      return double2{dx * a.lstep, dy * a.lstep};
-    };
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-      const int pix = chunk * CH + p * kThreads + threadIdx.x;
-      xy[p] = ((pix % L - L / 2) & 0xffff) | ((pix / L - L / 2) * 65536);
-      const double l = lm(p).x, m = lm(p).y;
+      const int pix = chunk * CH + p * NT + threadIdx.x;
+      const int x = pix % L, y = pix / L;
+      const double l = (x - L / 2) * a.lstep, m = (y - L / 2) * a.lstep;
       const double r2 = l * l + m * m;
-      n1[p] = -r2 / (1.0 + sqrt(1.0 - r2));
+      pxt[p * NT + threadIdx.x] = {-r2 / (1.0 + sqrt(1.0 - r2)), (float)(x - L / 2), (float)(y - L / 2)};
       // prologue: S' = T (-1)^(x+y) A_p S A_q^H
       const V2* Ap = At + ((int64_t)s.ap * L * L + pix) * 4;
       const V2* Aq = At + ((int64_t)s.aq * L * L + pix) * 4;
@@ -699,88 +648,110 @@ __attribute__((amdgpu_waves_per_eu(DegridTune<L, R>::W))) void degrid_dft(const 
       sp[p][2] = (cmul<R>(t2, b0) + cmul<R>(t3, b1)) * w;
       sp[p][3] = (cmul<R>(t2, b2) + cmul<R>(t3, b3)) * w;
     }
+    // -4 (c_u dx lstep + c_v dy lstep + c_w n1): the phase of exp(-2 pi i phi) in quarter turns
+    auto seed = [&](V2 (&ph)[P], double cu, double cv, double cw) {
+      const double ku = -4.0 * cu * a.lstep, kv = -4.0 * cv * a.lstep, kw = -4.0 * cw;
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        // an opaque index keeps the compiler from hoisting the load and conversions out
+        // of the row loop (which would hold 6 registers per pixel across it)
+        int e = p * NT + threadIdx.x;
+        asm volatile("" : "+v"(e));
+        const SeedPixel q = pxt[e];
+        ph[p] = dphasor(fma(ku, (double)q.dx, fma(kv, (double)q.dy, kw * q.n1)), R());
+      }
+    };
     for (int t = 0; t < s.nt; ++t) {
       const_view<double> uvw = as_const(a.uvw + 3 * (s.uvw0 + t));
       const double um = uvw[0], vm = uvw[1], wm = uvw[2];
-      // Phasors along the channels: ph_{j+1} = ph_j * step, in two ping-pong
-      // register sets (pa for even channel offsets inside a group, pb for odd).
-      V2 st[P], pa[P], pb[P];
-      {
-        const double su = um * s.dfc, sv = vm * s.dfc, sw = wm * s.dfc;
-#pragma unroll
-        for (int p = 0; p < P; ++p) {
-          const double l = lm(p).x, m = lm(p).y;
-          st[p] = phasor(-(su * l + sv * m + sw * n1[p]), R());
-        }
-      }
-      int since_seed = s.R;  // channels since the last FP64 re-seed
-      for (int g0 = 0; g0 < s.nc; g0 += kVisGroup) {
-        R part[8 * kVisGroup];
-#pragma unroll
-        for (int v = 0; v < kVisGroup; ++v) {
-          const int j = g0 + v;
-          V2 (&cur)[P] = (v & 1) ? pb : pa;
-          V2 (&nxt)[P] = (v & 1) ? pa : pb;
-#pragma unroll
-          for (int i = 0; i < 8; ++i) part[8 * v + i] = 0;
-          if (j < s.nc) {
-            if (since_seed == s.R) {
-              since_seed = 0;
-              const double fc = as_const(a.fc)[s.c0 + j];
-              const double cu = um * fc - u0, cv = vm * fc - v0, cw = wm * fc - s.w0;
-#pragma unroll
-              for (int p = 0; p < P; ++p) {
-                const double l = lm(p).x, m = lm(p).y;
-                cur[p] = phasor(-(cu * l + cv * m + cw * n1[p]), R());
-              }
+      // per-channel step exp(-2 pi i dfc (um l + vm m + wm n1)) and the running phasor
+      V2 st[P], cur[P];
+      seed(st, um * s.dfc, vm * s.dfc, wm * s.dfc);
+      auto origin = [&](V2 (&ph)[P], int j) {
+        const double fc = as_const(a.fc)[s.c0 + j];
+        seed(ph, um * fc - u0, vm * fc - v0, wm * fc - s.w0);
+      };
+      // The row's channels in blocks of kChanBlock, two per step (a row of odd length
+      // ends on a second channel whose result is dropped).  IRREGULAR: every channel is
+      // seeded from FP64 (irregular channel spacing); otherwise the phasor steps along
+      // the channels and is re-seeded every Rs of them.  One loop per case keeps the
+      // phasor registers in place (no copies between the two ways of forming them).
+      auto channels = [&](auto irregular, int cb0, int cbn, int& since, R* stg) {
+        for (int j = cb0; j < cb0 + cbn; j += 2) {
+          V2 nxt[P];
+          if constexpr (decltype(irregular)::value) {
+            origin(cur, j);
+            origin(nxt, min(j + 1, s.nc - 1));
+          } else {
+            if (since >= Rs) {
+              origin(cur, j);
+              since = 0;
             }
-            ++since_seed;
+            since += 2;
 #pragma unroll
-            for (int p = 0; p < P; ++p) {
+            for (int p = 0; p < P; ++p) nxt[p] = cmul<R>(cur[p], st[p]);
+          }
+          R part[16];
 #pragma unroll
-              for (int q = 0; q < 4; ++q) {
-                R re = part[8 * v + 2 * q], im = part[8 * v + 2 * q + 1];
-                re = fma(sp[p][q].x, cur[p].x, re);
-                re = fma(-sp[p][q].y, cur[p].y, re);
-                im = fma(sp[p][q].x, cur[p].y, im);
-                im = fma(sp[p][q].y, cur[p].x, im);
-                part[8 * v + 2 * q] = re;
-                part[8 * v + 2 * q + 1] = im;
-              }
-              nxt[p] = cmul<R>(cur[p], st[p]);
+          for (int q = 0; q < 4; ++q) {
+            part[2 * q] = sp[0][q].x * cur[0].x - sp[0][q].y * cur[0].y;
+            part[2 * q + 1] = sp[0][q].x * cur[0].y + sp[0][q].y * cur[0].x;
+            part[8 + 2 * q] = sp[0][q].x * nxt[0].x - sp[0][q].y * nxt[0].y;
+            part[8 + 2 * q + 1] = sp[0][q].x * nxt[0].y + sp[0][q].y * nxt[0].x;
+          }
+#pragma unroll
+          for (int p = 1; p < P; ++p) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              part[2 * q] = fma(sp[p][q].x, cur[p].x, part[2 * q]);
+              part[2 * q] = fma(-sp[p][q].y, cur[p].y, part[2 * q]);
+              part[2 * q + 1] = fma(sp[p][q].x, cur[p].y, part[2 * q + 1]);
+              part[2 * q + 1] = fma(sp[p][q].y, cur[p].x, part[2 * q + 1]);
+              part[8 + 2 * q] = fma(sp[p][q].x, nxt[p].x, part[8 + 2 * q]);
+              part[8 + 2 * q] = fma(-sp[p][q].y, nxt[p].y, part[8 + 2 * q]);
+              part[8 + 2 * q + 1] = fma(sp[p][q].x, nxt[p].y, part[8 + 2 * q + 1]);
+              part[8 + 2 * q + 1] = fma(sp[p][q].y, nxt[p].x, part[8 + 2 * q + 1]);
             }
           }
+          if constexpr (!decltype(irregular)::value) {
+#pragma unroll
+            for (int p = 0; p < P; ++p) cur[p] = cmul<R>(nxt[p], st[p]);
+          }
+          const R val = reduce16<R>(part, ln, area);
+          const int jc = j - cb0 + (vidx >> 3);
+          if (owner && j + (vidx >> 3) < s.nc) stg[jc * 8 + (vidx & 7)] = val;
         }
-        R val;
-        int idx, lead;
-        if constexpr (kVisGroup == 4) {
-          if constexpr (DEGRID_LDS_REDUCE && std::is_same_v<R, float>)
-            val = transpose_reduce32_lds(part, ln, stage);
-          else
-            val = transpose_reduce32<R>(part, ln);
-          idx = ln >> 1;
-          lead = !(ln & 1);
-        } else {
-          val = transpose_reduce16<R>(part, ln);
-          idx = ln >> 2;
-          lead = !(ln & 3);
+      };
+      int since = Rs;  // channels since the last FP64 seed: seed at the row's first channel
+      for (int cb0 = 0; cb0 < s.nc; cb0 += kChanBlock) {
+        const int cbn = min(kChanBlock, s.nc - cb0);
+        R* stg = stage + (buf * NW + wave) * kChanBlock * 8;
+        if (Rs == 1)
+          channels(std::true_type(), cb0, cbn, since, stg);
+        else
+          channels(std::false_type(), cb0, cbn, since, stg);
+        __syncthreads();
+        // the waves' values of the block, summed in wave order and added to the output
+        // (assigned by the first pixel chunk); each output element has one owner thread,
+        // the same in every chunk
+        const R* sb = stage + buf * NW * kChanBlock * 8;
+        R* vrow = vis + (s.vis0 + (int64_t)t * a.nc_total + cb0) * 8;
+        for (int i = threadIdx.x; i < cbn * 8; i += NT) {
+          R v = sb[i];
+#pragma unroll
+          for (int w = 1; w < NW; ++w) v = v + sb[w * kChanBlock * 8 + i];
+          int d = i;
+          if (s.fold) {
+            // folded sub-table: the conjugate transpose of the prediction at -uvw
+            const int comp = i & 7, pol = comp >> 1;
+            d = i - comp + (pol == 1 ? 2 : pol == 2 ? 1 : pol) * 2 + (comp & 1);
+            if (comp & 1) v = -v;
+          }
+          vrow[d] = chunk == 0 ? v : vrow[d] + v;
         }
-        const int v = idx >> 3, comp = idx & 7;
-        if (lead && g0 + v < s.nc) atomicAdd(&accs[(t * s.nc + g0 + v) * 8 + comp], val);
+        buf ^= 1;
       }
     }
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < nv * 8; i += kThreads) {
-    const int r = i / (s.nc * 8), rem = i % (s.nc * 8);
-    R val = accs[i];
-    if (s.fold) {
-      // folded sub-table: write the conjugate transpose of the prediction at -uvw
-      const int comp = rem & 7, pol = comp >> 1, src = (pol == 1 ? 2 : pol == 2 ? 1 : pol) * 2 + (comp & 1);
-      val = accs[i - comp + src];
-      if (comp & 1) val = -val;
-    }
-    vis[(s.vis0 + (int64_t)r * a.nc_total) * 8 + rem] = val;
   }
 }
 
@@ -804,10 +775,12 @@ int launch_one(KernelClass k, const Group& g, hipStream_t st, int max_nv) {
     case kSplitIfft:
       hipLaunchKernelGGL((split_ifft<L, R>), dim3(4, n), dim3(kThreads), 0, st, g);
       break;
-    case kDegridDft:
-      hipLaunchKernelGGL((degrid_dft<L, R>), dim3(n), dim3(kThreads),
-                         (size_t)kStageBytes + (size_t)max_nv * 8 * sizeof(R), st, g);
+    case kDegridDft: {
+      constexpr int nt = DegridTune<L, R>::NT;
+      constexpr size_t lds = degrid_lds_bytes<L, R>();
+      hipLaunchKernelGGL((degrid_dft<L, R>), dim3(n), dim3(nt), lds, st, g);
       break;
+    }
     default:
       return (int)hipErrorInvalidValue;
   }
