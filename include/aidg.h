@@ -63,7 +63,7 @@
 extern "C" {
 #endif
 
-#define AIDG_ABI_VERSION 5
+#define AIDG_ABI_VERSION 6
 
 typedef enum {
   AIDG_OK = 0,
@@ -215,12 +215,62 @@ aidg_status aidg_plan_set_aterms(aidg_plan* plan, const void* aterms, void* hip_
  * queued work.  AIDG_E_INVALID for a plan in the adjoint mode. */
 aidg_status aidg_plan_aterm_norm(aidg_plan* plan, double* out, int64_t cap);
 
-/* Gridding: ACCUMULATE the plan's visibilities into grid (both device). */
+/* Gridding (Sec. 2.5, imaging steps 1-2): for every subgrid of the plan, the direct
+ * sum of its visibilities times exp(+2 pi i phi_k(x,y)) (Sec. 2.4, Eq. withw), the
+ * A-term and taper correction (Sec. 3.3; A_p^H S A_q, or the normalised inverse of
+ * aterm_mode = 1), the centred forward DFT (Sec. 2.3) and the add onto its window of
+ * its w-layer (Eq. shiftback).  vis: device [nbl][nt][nc][4]; grid: device
+ * [W][P][N][N], ACCUMULATED into (zero it for a fresh grid).  Visibilities in no
+ * subgrid are ignored.  Never allocates or synchronises the host; AIDG_E_INVALID for
+ * NULL buffers, AIDG_E_BUSY if the plan is in use, AIDG_E_DEVICE if a launch fails. */
 aidg_status aidg_grid(aidg_plan* plan, const void* vis, void* grid, void* hip_stream);
 
-/* Degridding: OVERWRITE vis_out with the prediction from grid (both device);
- * visibilities that belong to no subgrid are set to zero. */
+/* Degridding (Sec. 2.5, prediction step 3), the adjoint chain: for every subgrid the
+ * window of its w-layer (the splitter), the centred inverse DFT, the A-term and taper
+ * (T A_p S A_q^H) and the direct sum over the subgrid's pixels times exp(-2 pi i phi_k)
+ * for each of its visibilities (Eq. degridder).  grid: device [W][P][N][N]; vis_out:
+ * device [nbl][nt][nc][4], OVERWRITTEN; visibilities that belong to no subgrid are set
+ * to zero.  Deterministic: the same grid gives bitwise the same visibilities.  Errors
+ * as aidg_grid. */
 aidg_status aidg_degrid(aidg_plan* plan, const void* grid, void* vis_out, void* hip_stream);
+
+/* The exact adjoints of the pair above, for differentiation (reverse mode needs the
+ * adjoint of each forward map).  aidg_grid_adjoint ACCUMULATES D^H(vis) into grid, where
+ * D is aidg_degrid; aidg_degrid_adjoint OVERWRITES vis_out with G^H(grid), where G is
+ * aidg_grid (visibilities in no subgrid are set to zero).  With four grid planes they
+ * are aidg_grid and aidg_degrid themselves (the gridder applies A_p^H . A_q, the forward
+ * FFT and exp(+2 pi i phi) where the degridder applies A_p . A_q^H, the inverse FFT and
+ * exp(-2 pi i phi)).  On a stokes_i plan the reduction I = (XX + YY) / 2 has the adjoint
+ * I -> diag(I, I) / 2, so these two differ from aidg_grid / aidg_degrid by a factor 2
+ * and 1/2, applied inside the kernels.  A plan in the inverse A-term mode
+ * (aterm_mode = 1) has no such pair: AIDG_E_INVALID. */
+aidg_status aidg_grid_adjoint(aidg_plan* plan, const void* vis, void* grid, void* hip_stream);
+aidg_status aidg_degrid_adjoint(aidg_plan* plan, const void* grid, void* vis_out, void* hip_stream);
+
+/* Device memory a plan and its data would take, estimated on the host without building
+ * the plan or partitioning (for admission by device footprint).  n_wlayers is exact
+ * for the library's own partition: the layers of the visibilities that can be placed
+ * on the grid at the layer spacing the plan would use (geometry's w_step, or the
+ * automatic one).  plan_bytes estimates everything aidg_plan_create allocates: the
+ * A-term copy (two plane sets in the inverse A-term mode), uvw and channel tables, the
+ * subgrid records (their count estimated from each row's uv extent over the channels,
+ * its gaps and layer changes), the excluded-visibility list, the batch workspace
+ * (workspace_bytes, capped at what the estimated subgrids fill) and the image-level
+ * tables.  All host arrays as in aidg_plan_create; nothing is allocated on the device. */
+typedef struct {
+  int32_t n_wlayers;      /* layers of the plan's grid */
+  int32_t n_pol;          /* grid planes: 4, or 1 with stokes_i */
+  double w_step;          /* layer spacing the plan would use (0: one layer) */
+  int64_t n_subgrids;     /* estimate */
+  int64_t n_excluded;     /* visibilities no subgrid can hold (outside the grid) */
+  int64_t grid_bytes;     /* one grid, n_wlayers x n_pol x N x N complex */
+  int64_t vis_bytes;      /* one visibility array */
+  int64_t aterm_bytes;    /* the plan's A-term planes */
+  int64_t plan_bytes;     /* estimate of the plan's own device memory (A-terms included) */
+} aidg_footprint;
+aidg_status aidg_footprint_estimate(const aidg_geometry* geo, int32_t n_stations, int32_t n_baselines,
+                                    int32_t n_times, int32_t n_chans, const double* uvw_m,
+                                    const double* freqs_hz, aidg_footprint* out);
 
 /* Per-kernel device timing (the paper's per-subroutine breakdown, Sec. 5.4).
  * Kernel classes: 0 gridder DFT + Jones/taper epilogue, 1 FFT + adder,

@@ -56,6 +56,12 @@ class _PlanInfo(ctypes.Structure):
                 ("n_groups", ctypes.c_int64)]
 
 
+class _Footprint(ctypes.Structure):
+    _fields_ = [("n_wlayers", ctypes.c_int32), ("n_pol", ctypes.c_int32), ("w_step", ctypes.c_double),
+                ("n_subgrids", ctypes.c_int64), ("n_excluded", ctypes.c_int64), ("grid_bytes", ctypes.c_int64),
+                ("vis_bytes", ctypes.c_int64), ("aterm_bytes", ctypes.c_int64), ("plan_bytes", ctypes.c_int64)]
+
+
 KERNEL_CLASSES = ("grid_dft", "fft_add", "split_ifft", "degrid_dft", "zero_vis", "image_fft",
                   "image_wstack")
 DIR_GRID, DIR_DEGRID = 0, 1
@@ -107,7 +113,7 @@ class Geometry:
 
 
 _lib = None
-ABI_VERSION = 5  # the structure layouts above follow include/aidg.h at this version
+ABI_VERSION = 6  # the structure layouts above follow include/aidg.h at this version
 
 
 def library() -> ctypes.CDLL:
@@ -131,6 +137,9 @@ def library() -> ctypes.CDLL:
         "aidg_plan_aterm_norm": (I32, [P, P, I64]),
         "aidg_grid": (I32, [P, P, P, P]),
         "aidg_degrid": (I32, [P, P, P, P]),
+        "aidg_grid_adjoint": (I32, [P, P, P, P]),
+        "aidg_degrid_adjoint": (I32, [P, P, P, P]),
+        "aidg_footprint_estimate": (I32, [P, I32, I32, I32, I32, P, P, P]),
         "aidg_plan_set_profiling": (I32, [P, I32]),
         "aidg_plan_kernel_times": (I32, [P, P]),
         "aidg_plan_destroy": (None, [P]),
@@ -180,6 +189,20 @@ def partition(geometry: Geometry, n_stations: int, baselines, uvw, freqs):
     out = np.zeros(max(n.value, 1), SUBGRID_DTYPE)
     _check(lib.aidg_partition(*args, _ptr(out), out.shape[0], ctypes.byref(n), ctypes.byref(w)))
     return out[:n.value].copy(), w.value
+
+
+def footprint(geometry: Geometry, n_stations: int, baselines, uvw, freqs) -> dict:
+    """Device memory a plan of this observation and its data would take, estimated on the
+    host without building the plan (``aidg_footprint_estimate``): n_wlayers, grid_bytes,
+    vis_bytes, aterm_bytes, plan_bytes and the estimated subgrid count."""
+    lib = library()
+    u, f = _host(uvw, np.float64), _host(freqs, np.float64)
+    nbl = int(np.asarray(baselines).shape[0])
+    g = geometry.to_c()
+    out = _Footprint()
+    _check(lib.aidg_footprint_estimate(ctypes.byref(g), int(n_stations), nbl, u.shape[1], f.shape[0],
+                                       _ptr(u), _ptr(f), ctypes.byref(out)))
+    return {name: getattr(out, name) for name, _ in _Footprint._fields_}
 
 
 def _stream_handle(stream):
@@ -281,6 +304,28 @@ class Plan:
             out = torch.empty(self.vis_shape(), dtype=self._cdtype, device=grid.device)
         self._check_tensor(out, self.vis_shape(), "vis")
         _check(library().aidg_degrid(self._h, _dptr(grid), _dptr(out), _stream_handle(stream)))
+        return out
+
+    def grid_adjoint(self, vis, out=None, stream=None):
+        """The exact adjoint of ``degrid`` applied to ``vis`` (aidg_grid_adjoint), accumulated
+        into ``out`` (zeros if None); equal to ``grid`` except on Stokes-I plans."""
+        import torch
+        self._check_tensor(vis, self.vis_shape(), "vis")
+        if out is None:
+            out = torch.zeros(self.grid_shape(), dtype=self._cdtype, device=vis.device)
+        self._check_tensor(out, self.grid_shape(), "grid")
+        _check(library().aidg_grid_adjoint(self._h, _dptr(vis), _dptr(out), _stream_handle(stream)))
+        return out
+
+    def degrid_adjoint(self, grid, out=None, stream=None):
+        """The exact adjoint of ``grid`` applied to ``grid`` (aidg_degrid_adjoint), written to
+        ``out``; equal to ``degrid`` except on Stokes-I plans."""
+        import torch
+        self._check_tensor(grid, self.grid_shape(), "grid")
+        if out is None:
+            out = torch.empty(self.vis_shape(), dtype=self._cdtype, device=grid.device)
+        self._check_tensor(out, self.vis_shape(), "vis")
+        _check(library().aidg_degrid_adjoint(self._h, _dptr(grid), _dptr(out), _stream_handle(stream)))
         return out
 
     def image_shape(self):

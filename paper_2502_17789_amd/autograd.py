@@ -16,13 +16,14 @@ adjoint of imaging I = P^H(G) (Eq. wstack), so
 and ``predict_vis`` (image -> visibilities, degrid after predict) is differentiable
 end to end.
 
-On a Stokes-I plan, gridding reduces to I = (XX + YY) / 2 and degridding expands I to
-[[I, 0], [0, I]]; the reduction's adjoint is half the expansion, so there
-    DegridFn.backward(gV) = 2 grid(gV)     GridFn.backward(gG) = degrid(gG) / 2.
+The backward passes call the library's adjoint pair (aidg_grid_adjoint,
+aidg_degrid_adjoint), which equals gridding and degridding except on Stokes-I plans:
+there gridding reduces to I = (XX + YY) / 2 and degridding expands I to [[I, 0], [0, I]],
+and the library applies the adjoints' factors 2 and 1/2 itself.
 
 A plan in the inverse A-term mode grids with normalised A^-1 and divides its image by
 the normalisation map: neither is the adjoint of degridding or prediction, so these
-functions refuse such plans.
+functions refuse such plans (the library refuses its adjoint pair for them as well).
 """
 from __future__ import annotations
 
@@ -49,9 +50,7 @@ class DegridFn(torch.autograd.Function):
         plan = ctx.plan
         g_grid = None
         if ctx.needs_input_grad[0]:
-            g_grid = plan.grid(g_vis.contiguous())
-            if plan.geometry.stokes_i:
-                g_grid = g_grid * 2
+            g_grid = plan.grid_adjoint(g_vis.contiguous())
         return g_grid, None
 
 
@@ -68,9 +67,7 @@ class GridFn(torch.autograd.Function):
         plan = ctx.plan
         g_vis = None
         if ctx.needs_input_grad[0]:
-            g_vis = plan.degrid(g_grid.contiguous())
-            if plan.geometry.stokes_i:
-                g_vis = g_vis * 0.5
+            g_vis = plan.degrid_adjoint(g_grid.contiguous())
         return g_vis, None
 
 

@@ -59,6 +59,15 @@ aidg_status validate_geometry(const aidg_geometry* g, Geometry* out, std::string
 double auto_w_step(const Geometry& g);
 aidg_status partition(const Geometry& g, int n_st, int nbl, int nt, int nc, const int32_t* baselines,
                       const double* uvw, const double* freqs, PartitionResult* out, std::string* err);
+// Host estimate of a partition's shape without building it: the w-layer range of the
+// placeable visibilities, the unplaceable count, and an estimate of the number of
+// subgrids (per row: the channel runs its uv extent needs, plus one per gap or layer
+// change, plus the splits at max_sg_vis).
+struct ShapeEstimate {
+  int64_t jmin = 0, jmax = 0, n_excluded = 0, n_subgrids = 0;
+};
+void estimate_shape(const Geometry& g, int nbl, int nt, int nc, const double* uvw, const double* freqs,
+                    ShapeEstimate* out);
 aidg_status adopt_table(const Geometry& g, int n_st, int nbl, int nt, int nc,
                         const int32_t* baselines, const aidg_subgrid* table, int64_t n_table,
                         PartitionResult* out, std::string* err);
@@ -97,6 +106,9 @@ struct JobRef {
   int64_t g_first;          // group of subgrid sg_begin
   int64_t slot_begin;       // first per-subgrid slot of the range in this launch
   int64_t gslot_begin;      // first per-group slot of the range in this launch
+  int32_t adjoint;          // 1: the exact adjoint of the other direction (Stokes-I plans
+                            // grid XX + YY and split into diag(I, I) / 2)
+  int32_t pad;
 };
 struct Group {
   int32_t n, pad;

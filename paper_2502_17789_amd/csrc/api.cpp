@@ -217,7 +217,7 @@ struct TimedLaunch {
 
 // Launch one kernel class over subgrids [b0, b0 + n) of one plan.
 aidg_status run(aidg_plan* p, KernelClass k, int64_t b0, int64_t n, const void* in, void* out,
-                void* stream) {
+                void* stream, int adjoint = 0) {
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   TimedLaunch tl(p, st);
   int rc;
@@ -230,7 +230,7 @@ aidg_status run(aidg_plan* p, KernelClass k, int64_t b0, int64_t n, const void* 
     g.total_sg = n;
     g.total_grp = p->sg_group[b0 + n - 1] - p->sg_group[b0] + 1;
     g.scratch = p->d_scratch;
-    g.job[0] = {p->d_args, in, out, b0, b0 + n, p->sg_group[b0], 0, 0};
+    g.job[0] = {p->d_args, in, out, b0, b0 + n, p->sg_group[b0], 0, 0, adjoint, 0};
     rc = launch_group(k, p->g.L, p->g.precision, g, stream, p->max_nv);
   }
   if (rc != 0) return hip_fail((hipError_t)rc, "kernel launch");
@@ -290,6 +290,45 @@ aidg_status image_step(aidg_plan* p, hipStream_t st, KernelClass k, F&& launch) 
   if (rc != 0) return hip_fail((hipError_t)rc, "image kernel launch");
   tl.done(k, 0, 0);
   return AIDG_OK;
+}
+
+// Gridding and degridding of a whole plan, batch by batch; adjoint = 1 selects the
+// exact adjoint of the other direction (differs on Stokes-I plans only).
+aidg_status grid_calls(aidg_plan* plan, const void* vis, void* grid, void* hip_stream, int adjoint) {
+  if (!plan || !vis || !grid) return fail(AIDG_E_INVALID, "NULL plan, vis or grid");
+  BusyGuard guard(plan);
+  if (!guard.ok) return fail(AIDG_E_BUSY, "plan in use by another thread");
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  hipError_t e = hipStreamWaitEvent(st, plan->last, 0);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
+  for (size_t b = 0; b + 1 < plan->batch_begin.size(); ++b) {
+    const int64_t b0 = plan->batch_begin[b], nb = plan->batch_begin[b + 1] - b0;
+    aidg_status r = run(plan, kGridDft, b0, nb, vis, nullptr, hip_stream, adjoint);
+    if (r == AIDG_OK) r = run(plan, kFftAdd, b0, nb, nullptr, grid, hip_stream, adjoint);
+    if (r != AIDG_OK) return r;
+  }
+  e = hipEventRecord(plan->last, st);
+  return e == hipSuccess ? AIDG_OK : hip_fail(e, "hipEventRecord");
+}
+
+aidg_status degrid_calls(aidg_plan* plan, const void* grid, void* vis_out, void* hip_stream, int adjoint) {
+  if (!plan || !vis_out || !grid) return fail(AIDG_E_INVALID, "NULL plan, grid or vis");
+  BusyGuard guard(plan);
+  if (!guard.ok) return fail(AIDG_E_BUSY, "plan in use by another thread");
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  hipError_t e = hipStreamWaitEvent(st, plan->last, 0);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
+  aidg_status r = AIDG_OK;
+  if (plan->n_excluded > 0) r = run(plan, kZeroVis, 0, 0, nullptr, vis_out, hip_stream);
+  if (r != AIDG_OK) return r;
+  for (size_t b = 0; b + 1 < plan->batch_begin.size(); ++b) {
+    const int64_t b0 = plan->batch_begin[b], nb = plan->batch_begin[b + 1] - b0;
+    r = run(plan, kSplitIfft, b0, nb, grid, nullptr, hip_stream, adjoint);
+    if (r == AIDG_OK) r = run(plan, kDegridDft, b0, nb, nullptr, vis_out, hip_stream, adjoint);
+    if (r != AIDG_OK) return r;
+  }
+  e = hipEventRecord(plan->last, st);
+  return e == hipSuccess ? AIDG_OK : hip_fail(e, "hipEventRecord");
 }
 
 // Shared body of aidg_execute and aidg_execute_static: pack the items' ranges into
@@ -373,7 +412,7 @@ aidg_status execute_items(void* scratch, int64_t scratch_bytes, hipEvent_t last,
         const int64_t g0 = p->sg_group[b], room = cap - g.total_grp;
         const int64_t gn = (int64_t)p->grp_begin.size() - 1;
         const int64_t e = g0 + room < gn ? std::min(w.sg_end, p->grp_begin[g0 + room]) : w.sg_end;
-        g.job[g.n] = {p->d_args, w.in, w.out, b, e, g0, g.total_sg, g.total_grp};
+        g.job[g.n] = {p->d_args, w.in, w.out, b, e, g0, g.total_sg, g.total_grp, 0, 0};
         g.n += 1;
         g.total_sg += e - b;
         g.total_grp += p->sg_group[e - 1] - g0 + 1;
@@ -808,40 +847,70 @@ aidg_status aidg_plan_aterm_norm(aidg_plan* plan, double* out, int64_t cap) {
 }
 
 aidg_status aidg_grid(aidg_plan* plan, const void* vis, void* grid, void* hip_stream) {
-  if (!plan || !vis || !grid) return fail(AIDG_E_INVALID, "NULL plan, vis or grid");
-  BusyGuard guard(plan);
-  if (!guard.ok) return fail(AIDG_E_BUSY, "plan in use by another thread");
-  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
-  hipError_t e = hipStreamWaitEvent(st, plan->last, 0);
-  if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
-  for (size_t b = 0; b + 1 < plan->batch_begin.size(); ++b) {
-    const int64_t b0 = plan->batch_begin[b], nb = plan->batch_begin[b + 1] - b0;
-    aidg_status r = run(plan, kGridDft, b0, nb, vis, nullptr, hip_stream);
-    if (r == AIDG_OK) r = run(plan, kFftAdd, b0, nb, nullptr, grid, hip_stream);
-    if (r != AIDG_OK) return r;
-  }
-  e = hipEventRecord(plan->last, st);
-  return e == hipSuccess ? AIDG_OK : hip_fail(e, "hipEventRecord");
+  return grid_calls(plan, vis, grid, hip_stream, 0);
+}
+
+aidg_status aidg_grid_adjoint(aidg_plan* plan, const void* vis, void* grid, void* hip_stream) {
+  if (plan && plan->g.amode) return fail(AIDG_E_INVALID, "inverse A-term mode: gridding has no adjoint pair");
+  return grid_calls(plan, vis, grid, hip_stream, 1);
 }
 
 aidg_status aidg_degrid(aidg_plan* plan, const void* grid, void* vis_out, void* hip_stream) {
-  if (!plan || !vis_out || !grid) return fail(AIDG_E_INVALID, "NULL plan, grid or vis");
-  BusyGuard guard(plan);
-  if (!guard.ok) return fail(AIDG_E_BUSY, "plan in use by another thread");
-  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
-  hipError_t e = hipStreamWaitEvent(st, plan->last, 0);
-  if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
-  aidg_status r = AIDG_OK;
-  if (plan->n_excluded > 0) r = run(plan, kZeroVis, 0, 0, nullptr, vis_out, hip_stream);
-  if (r != AIDG_OK) return r;
-  for (size_t b = 0; b + 1 < plan->batch_begin.size(); ++b) {
-    const int64_t b0 = plan->batch_begin[b], nb = plan->batch_begin[b + 1] - b0;
-    r = run(plan, kSplitIfft, b0, nb, grid, nullptr, hip_stream);
-    if (r == AIDG_OK) r = run(plan, kDegridDft, b0, nb, nullptr, vis_out, hip_stream);
-    if (r != AIDG_OK) return r;
+  return degrid_calls(plan, grid, vis_out, hip_stream, 0);
+}
+
+aidg_status aidg_degrid_adjoint(aidg_plan* plan, const void* grid, void* vis_out, void* hip_stream) {
+  if (plan && plan->g.amode) return fail(AIDG_E_INVALID, "inverse A-term mode: gridding has no adjoint pair");
+  return degrid_calls(plan, grid, vis_out, hip_stream, 1);
+}
+
+aidg_status aidg_footprint_estimate(const aidg_geometry* geo, int32_t n_stations, int32_t n_baselines,
+                                    int32_t n_times, int32_t n_chans, const double* uvw_m,
+                                    const double* freqs_hz, aidg_footprint* out) {
+  if (!out) return fail(AIDG_E_INVALID, "out is NULL");
+  std::memset(out, 0, sizeof(*out));
+  try {
+    Geometry g;
+    std::string err;
+    aidg_status st = validate_geometry(geo, &g, &err);
+    if (st != AIDG_OK) return fail(st, err);
+    if (n_stations < 1 || n_baselines < 0 || n_times < 0 || n_chans < 0 ||
+        (n_baselines && n_times && !uvw_m) || (n_chans && !freqs_hz))
+      return fail(AIDG_E_INVALID, "bad observation sizes or NULL host arrays");
+    for (int c = 1; c < n_chans; ++c)
+      if (!(freqs_hz[c] > freqs_hz[c - 1])) return fail(AIDG_E_INVALID, "frequencies must be strictly increasing");
+    ShapeEstimate se;
+    estimate_shape(g, n_baselines, n_times, n_chans, uvw_m, freqs_hz, &se);
+    const int64_t elem = g.precision == AIDG_FP32 ? 8 : 16;
+    const int64_t L = g.L, N = g.N;
+    const int64_t n_vis = (int64_t)n_baselines * n_times * n_chans;
+    const int64_t n_int = n_times ? (n_times + g.aterm_interval - 1) / g.aterm_interval : 0;
+    const int64_t n_sg = se.n_subgrids;
+    out->n_wlayers = (int32_t)(se.jmax - se.jmin + 1);
+    out->n_pol = g.npol;
+    out->w_step = g.w_step > 0 ? g.w_step : 0.0;
+    out->n_subgrids = n_sg;
+    out->n_excluded = se.n_excluded;
+    out->grid_bytes = (int64_t)out->n_wlayers * g.npol * N * N * elem;
+    out->vis_bytes = n_vis * 4 * elem;
+    out->aterm_bytes = n_int * n_stations * L * L * 4 * elem * (g.amode ? 2 : 1);
+    // what aidg_plan_create allocates, each allocation at least 256 bytes
+    auto al = [](int64_t b) { return std::max<int64_t>(b, 256); };
+    const int64_t per_image = 4 * L * L * elem;
+    const int64_t batch = std::max<int64_t>(1, std::min<int64_t>({g.workspace / per_image, 65535, n_sg}));
+    int64_t b = al(n_sg * (int64_t)sizeof(SubgridDev)) + al((int64_t)n_baselines * n_times * 24 * (g.fold ? 2 : 1)) +
+                al((int64_t)n_chans * 8) + out->aterm_bytes + al(L * L * elem / 2) + al(L * elem) +
+                al(se.n_excluded * 8) + al((n_sg + 1) * 8) + al(batch * per_image) + al(sizeof(KernelArgs));
+    if (N <= kMaxImageN) b += al(N * elem) + al(N * 8);
+    if (g.amode) {
+      const int64_t pairs = std::min<int64_t>(n_sg, (int64_t)n_int * n_baselines);
+      b += al(pairs * 8) + al(pairs * 8) + al(64 * L * L * 8) + al(L * L * 8);
+    }
+    out->plan_bytes = b;
+    return AIDG_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(AIDG_E_NOMEM, "host allocation failed");
   }
-  e = hipEventRecord(plan->last, st);
-  return e == hipSuccess ? AIDG_OK : hip_fail(e, "hipEventRecord");
 }
 
 aidg_status aidg_image_workspace_bytes(const aidg_plan* plan, int64_t* bytes) {

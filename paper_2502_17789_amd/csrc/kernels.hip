@@ -148,6 +148,7 @@ struct GroupSlot {
   int64_t sb, se;  // subgrids [sb, se) of the group within the job's range
   const void* in;
   void* out;
+  int adjoint;
 };
 __device__ __forceinline__ GroupSlot resolve_group(const Group& g, int64_t slot) {
   int j = 0;
@@ -161,6 +162,7 @@ __device__ __forceinline__ GroupSlot resolve_group(const Group& g, int64_t slot)
   r.se = min(gb[grp + 1], g.job[j].sg_end);
   r.in = uniform(g.job[j].in);
   r.out = uniform(g.job[j].out);
+  r.adjoint = uniform(g.job[j].adjoint);
   return r;
 }
 
@@ -342,7 +344,7 @@ __global__ __launch_bounds__(kThreads) void grid_dft(const Group g) {
       V2 c[4] = {(cmul<R>(t0, b0) + cmul<R>(t1, b2)) * w, (cmul<R>(t0, b1) + cmul<R>(t1, b3)) * w,
                  (cmul<R>(t2, b0) + cmul<R>(t3, b2)) * w, (cmul<R>(t2, b1) + cmul<R>(t3, b3)) * w};
       if (a.npol == 1) {  // Stokes-I grid: I = (XX + YY) / 2 of the corrected image
-        V2 ci = (c[0] + c[3]) * (R)0.5;
+        V2 ci = (c[0] + c[3]) * (gs.adjoint ? (R)1 : (R)0.5);
         if (si != gs.sb) ci += out[pix];
         out[pix] = ci;
       } else {
@@ -481,7 +483,9 @@ __global__ __launch_bounds__(kThreads) void split_ifft(const Group g) {
   __syncthreads();
   fft_lines<L, +1, true>(buf, tw);
   fft_lines<L, +1, false>(buf, tw);
-  for (int e = threadIdx.x; e < L * L; e += kThreads) out[e] = buf[(e / L) * pitch(L) + e % L];
+  // the adjoint of the Stokes-I reduction (XX + YY) / 2 expands I to diag(I, I) / 2
+  const R scale = stokes && gs.adjoint ? (R)0.5 : (R)1;
+  for (int e = threadIdx.x; e < L * L; e += kThreads) out[e] = buf[(e / L) * pitch(L) + e % L] * scale;
 }
 
 // ------------------------------------------------------------------ degridder

@@ -259,6 +259,73 @@ void tile(const Ctx& x, int bl, int ts, int te, int c_lo, int c_hi, PartitionRes
 
 }  // namespace
 
+void estimate_shape(const Geometry& g, int nbl, int nt, int nc, const double* uvw, const double* freqs,
+                    ShapeEstimate* out) {
+  Ctx x{g, nbl, nt, nc, uvw, freqs};
+  const double comfy = 0.75 * (g.L - g.K);
+  *out = ShapeEstimate{};
+  bool any = false;
+  int64_t placed = 0;
+  auto take = [&](int64_t lay) {
+    out->jmin = any ? std::min(out->jmin, lay) : lay;
+    out->jmax = any ? std::max(out->jmax, lay) : lay;
+    any = true;
+  };
+  // One A-term interval of one baseline at a time: a row's channels split into about
+  // 1 + extent / (3/4 window) runs, which the partition extends in time until the track
+  // has drifted by the quarter window the runs leave free.
+  for (int bl = 0; bl < nbl; ++bl)
+    for (int ta = 0; ta < nt && nc > 0; ta += g.aterm_interval) {
+      const int te = std::min(nt, ta + g.aterm_interval);
+      int64_t runs = 0, layers = 0;
+      bool whole = true;
+      for (int t = ta; t < te && whole; ++t) whole = x.placeable(bl, t, 0) && x.placeable(bl, t, nc - 1);
+      if (whole) {
+        // Along a row u, v and w scale with frequency: the cells move on a straight
+        // line, so all channels of a row whose two ends are placeable are placeable (the
+        // placeable region is a box), its extent is that of the ends and its layers run
+        // monotonically from one end's to the other's.
+        double drift = 0.0;
+        const int cm = nc / 2;
+        for (int t = ta; t < te; ++t) {
+          const int64_t j0 = x.layer(bl, t, 0), j1 = x.layer(bl, t, nc - 1);
+          take(j0);
+          take(j1);
+          const double ext = std::max(std::fabs(x.cell(bl, t, nc - 1, 0) - x.cell(bl, t, 0, 0)),
+                                      std::fabs(x.cell(bl, t, nc - 1, 1) - x.cell(bl, t, 0, 1)));
+          runs = std::max<int64_t>(runs, 1 + (int64_t)std::floor(ext / comfy));
+          layers = std::max<int64_t>(layers, std::llabs(j1 - j0));
+          drift = std::max({drift, std::fabs(x.cell(bl, t, cm, 0) - x.cell(bl, ta, cm, 0)),
+                            std::fabs(x.cell(bl, t, cm, 1) - x.cell(bl, ta, cm, 1))});
+        }
+        out->n_subgrids += (runs + layers) * (1 + (int64_t)std::floor(drift / (0.25 * (g.L - g.K))));
+        placed += (int64_t)(te - ta) * nc;
+        continue;
+      }
+      for (int t = ta; t < te; ++t) {
+      Box b;
+      int64_t prev_layer = 0, pieces = 0;
+      bool prev_ok = false;
+      for (int c = 0; c < nc; ++c) {
+        if (!x.placeable(bl, t, c)) {
+          ++out->n_excluded;
+          prev_ok = false;
+          continue;
+        }
+        const int64_t lay = x.layer(bl, t, c);
+        if (!prev_ok || lay != prev_layer) ++pieces;  // a gap or a layer change starts a piece
+        prev_ok = true;
+        prev_layer = lay;
+        b.add(x.cell(bl, t, c, 0), x.cell(bl, t, c, 1));
+        take(lay);
+        ++placed;
+      }
+      if (pieces) out->n_subgrids += pieces + (int64_t)std::floor(std::max(b.uhi - b.ulo, b.vhi - b.vlo) / comfy);
+      }
+    }
+  out->n_subgrids += (placed + g.max_sg_vis - 1) / g.max_sg_vis;
+}
+
 aidg_status partition(const Geometry& g, int n_st, int nbl, int nt, int nc, const int32_t* baselines,
                       const double* uvw, const double* freqs, PartitionResult* out,
                       std::string* err) {

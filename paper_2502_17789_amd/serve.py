@@ -27,13 +27,12 @@ from __future__ import annotations
 import collections
 import concurrent.futures
 import dataclasses
-import math
 import threading
 import time
 
 import numpy as np
 
-from . import DIR_DEGRID, DIR_GRID, FP32, Executor, Geometry, Plan
+from . import DIR_DEGRID, DIR_GRID, FP32, Executor, Geometry, Plan, footprint
 
 
 @dataclasses.dataclass
@@ -83,35 +82,21 @@ class _Active:
         self.last_token = None
 
 
-def job_footprint_estimate(job: Job) -> int:
-    """Device bytes a job holds while admitted: grid, visibilities, A-term copy,
-    uvw and subgrid records (upper bound on the number of w-layers)."""
-    g = job.geometry
+def plan_geometry(job: Job) -> Geometry:
+    """The geometry a served job's plan is built with: the executor holds the group
+    images, so the plan itself keeps a workspace of one image."""
+    g = dataclasses.replace(job.geometry)
     elem = 8 if g.precision == FP32 else 16
-    nbl, nt, nc = job.baselines.shape[0], job.uvw.shape[1], job.freqs.shape[0]
-    n_vis = nbl * nt * nc
-    n_int = (nt + g.aterm_interval - 1) // g.aterm_interval
-    fov = g.grid_size * g.pixel_scale
-    if g.w_step > 0:
-        w_step = g.w_step
-    elif g.w_step == 0 and g.kernel_support > 0:
-        r = fov / math.sqrt(2.0)
-        w_step = 2 * g.kernel_support / (4 * fov * r / math.sqrt(1 - r * r))
-    else:
-        w_step = 0.0
-    wmax = float(np.abs(job.uvw[..., 2]).max(initial=0.0)) * float(job.freqs.max()) / 299792458.0
-    if w_step <= 0:
-        W = 1
-    elif g.w_fold:  # layers at (j + 1/2) w_step for w >= 0 only
-        W = int(math.ceil(wmax / w_step)) + 1
-    else:
-        W = 2 * int(math.ceil(wmax / w_step)) + 1
-    grid_b = W * g.n_pol * g.grid_size ** 2 * elem
-    vis_b = n_vis * 4 * elem
-    # the inverse A-term mode keeps a second plane set, (A^-1)^H, for the gridder
-    aterm_b = (2 if g.aterm_mode else 1) * n_int * job.n_stations * g.subgrid_size ** 2 * 4 * elem
-    meta_b = nbl * nt * 24 + n_vis * 80 // 4 + 4 * g.subgrid_size ** 2 * elem
-    return int(grid_b + vis_b + aterm_b + meta_b)
+    g.workspace_bytes = 4 * g.subgrid_size ** 2 * elem
+    return g
+
+
+def job_footprint_estimate(job: Job) -> int:
+    """Device bytes a job holds while admitted: its plan (the library's host estimate,
+    aidg_footprint_estimate: A-terms, tables, subgrid records, workspace), its grid and
+    its visibilities (one is the input, the other the output)."""
+    f = footprint(plan_geometry(job), job.n_stations, job.baselines, job.uvw, job.freqs)
+    return int(f["plan_bytes"] + f["grid_bytes"] + f["vis_bytes"])
 
 
 class GpuBackend:
@@ -130,9 +115,7 @@ class GpuBackend:
 
     def prepare(self, job: Job):
         torch = self.torch
-        g = dataclasses.replace(job.geometry)
-        elem = 8 if g.precision == FP32 else 16
-        g.workspace_bytes = 4 * g.subgrid_size ** 2 * elem   # the executor holds the workspace
+        g = plan_geometry(job)
         cdt = torch.complex64 if g.precision == FP32 else torch.complex128
 
         def device(x):

@@ -80,3 +80,32 @@ def test_served_results_equal_alone(orc):
             ref = (orc.grid(wl, job.data, job.table) if job.direction == "grid"
                    else orc.degrid(wl, job.data, job.table))
             check(got, ref, 1e-5, f"job {job.tag} ({job.direction}) vs oracle")
+
+
+@pytest.mark.parametrize("kind", ["mwa", "tiny_fold_inverse", "diff_stokes"])
+def test_footprint_estimate_bounds_the_plan(kind):
+    """The host estimate the admission uses (aidg_footprint_estimate) against the device
+    memory plans actually take: within 0.9 and 1.5 times the plan's device bytes (the
+    subgrid count is estimated), and exactly its grid size and layer count."""
+    import paper_2502_17789_amd as aidg
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    if kind == "mwa":
+        wl, kw = synth.config_mwa(seed=2), {}
+    elif kind == "tiny_fold_inverse":
+        wl, kw = synth.config_tiny(71, ha0_deg=-60.0, beam_fwhm_deg=15.0), dict(w_step=12.0, w_fold=1, aterm_mode=1)
+    else:
+        wl, kw = synth.config_diff(seed=4), dict(stokes_i=1)
+    for ws in (0, 4 * wl.subgrid_size ** 2 * 8):
+        geo = aidg.Geometry(wl.grid_size, wl.subgrid_size, wl.kernel_support, wl.pixel_scale,
+                            aterm_interval=wl.aterm_interval, workspace_bytes=ws, **kw)
+        f = aidg.footprint(geo, wl.n_stations, wl.baselines, wl.uvw, wl.freqs)
+        A = torch.from_numpy(wl.aterms.astype(np.complex64)).cuda()
+        with aidg.Plan(geo, wl.n_stations, wl.baselines, wl.uvw, wl.freqs, A) as p:
+            info = p.info
+        del A
+        print(f"{kind} workspace {ws}: estimate {f['plan_bytes']} B ({f['n_subgrids']} subgrids), plan "
+              f"{info['device_bytes']} B ({info['n_subgrids']} subgrids)", flush=True)
+        assert f["n_wlayers"] == info["n_wlayers"] and f["grid_bytes"] == info["grid_bytes"]
+        assert f["vis_bytes"] == info["vis_bytes"]
+        assert 0.9 * info["device_bytes"] <= f["plan_bytes"] <= 1.5 * info["device_bytes"]

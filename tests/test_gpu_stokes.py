@@ -143,3 +143,33 @@ def test_grouped_launch_mixes_stokes_i_and_four_plane_plans(aidg):
             ex.close()
     for i, (r, o) in enumerate(zip(ref, got)):
         (check_grid if i < 2 else check_vis)(o, r, 1e-6, f"grouped launch output {i}")
+
+
+def test_library_adjoint_pair_on_stokes_i_plans(aidg):
+    """aidg_grid_adjoint / aidg_degrid_adjoint are the exact adjoints of degridding and
+    gridding also on a Stokes-I plan (the factors 2 and 1/2 inside the library), equal
+    aidg_grid / aidg_degrid on a four-plane plan, and are refused in the inverse A-term
+    mode."""
+    wl = synth.config_tiny(108)
+    rng = np.random.default_rng(14)
+    with plan_for(aidg, wl, 1, 12.0) as p:
+        V = dev(synth.random_vis((wl.n_baselines, wl.n_times, wl.n_chans), rng), 1)
+        G = dev(synth.random_grid(p.n_wlayers, wl.grid_size, rng)[:, :1], 1)
+        a = torch.vdot(p.grid_adjoint(V).flatten(), G.flatten()).item()
+        b = torch.vdot(V.flatten(), p.degrid(G).flatten()).item()
+        assert abs(a - b) <= 1e-12 * abs(b)
+        a = torch.vdot(p.grid(V).flatten(), G.flatten()).item()
+        b = torch.vdot(V.flatten(), p.degrid_adjoint(G).flatten()).item()
+        assert abs(a - b) <= 1e-12 * abs(b)
+        check_grid(host(p.grid_adjoint(V)), 2 * host(p.grid(V)), 1e-14, "Stokes-I grid_adjoint = 2 grid")
+        check_vis(host(p.degrid_adjoint(G)), 0.5 * host(p.degrid(G)), 1e-14, "Stokes-I degrid_adjoint = degrid / 2")
+    with plan_for(aidg, wl, 0, 12.0, stokes=0) as p:
+        V = dev(synth.random_vis((wl.n_baselines, wl.n_times, wl.n_chans), rng), 0)
+        G = dev(synth.random_grid(p.n_wlayers, wl.grid_size, rng), 0)
+        assert torch.equal(p.degrid_adjoint(G), p.degrid(G))
+        check_grid(host(p.grid_adjoint(V)), host(p.grid(V)), 1e-6, "four planes: grid_adjoint = grid")
+    with plan_for(aidg, wl, 0, 12.0, mode=1) as p:
+        V = dev(synth.random_vis((wl.n_baselines, wl.n_times, wl.n_chans), rng), 0)
+        with pytest.raises(aidg.AidgError) as e:
+            p.grid_adjoint(V)
+        assert e.value.status == aidg.AIDG_E_INVALID

@@ -146,7 +146,9 @@ def test_oversized_and_invalid_jobs_refused():
     fb, fx, fo = srv.submit(big), srv.submit(bad), srv.submit(ok)
     drive(srv, clock)
     assert isinstance(fb.exception(), MemoryError)
-    assert isinstance(fx.exception(), ValueError)
+    # the library's footprint estimate validates the geometry before admission
+    import paper_2502_17789_amd as aidg
+    assert isinstance(fx.exception(), aidg.AidgError) and fx.exception().status == aidg.AIDG_E_INVALID
     assert fo.result().output.shape[-1] == 4
 
 
@@ -224,11 +226,12 @@ def test_active_jobs_bounded():
 
 
 def test_footprint_follows_geometry_variants():
-    """The admission estimate bounds the plan's grid for every geometry variant: a
-    Stokes-I grid is a quarter of the four-plane one, the fold keeps only w >= 0 layers,
-    and the inverse A-term mode holds a second A-term plane set."""
-    import dataclasses
+    """The library's host estimate (aidg_footprint_estimate), which the admission uses,
+    gives the layer count of the library's own partition for every geometry variant, a
+    Stokes-I grid of a quarter of the four-plane one, a second A-term plane set in the
+    inverse A-term mode, and a job footprint of plan + grid + visibilities."""
     import paper_2502_17789_amd as aidg
+    from paper_2502_17789_amd.serve import plan_geometry
     wl = synth.config_tiny(301, ha0_deg=-60.0)
     N, L, elem = wl.grid_size, wl.subgrid_size, 8
 
@@ -241,14 +244,43 @@ def test_footprint_follows_geometry_variants():
         table, _ = aidg.partition(g, wl.n_stations, wl.baselines, wl.uvw, wl.freqs)
         return int(table["wlayer"].max()) + 1
 
-    base_job, g0 = job()
-    base = job_footprint_estimate(base_job)
-    stokes = job_footprint_estimate(job(stokes_i=1)[0])
-    W = (base - stokes) // (3 * N * N * elem)
-    assert (base - stokes) == W * 3 * N * N * elem and W >= library_layers(g0)
-    fold_job, gf = job(w_fold=1)
-    fold = job_footprint_estimate(fold_job)
-    Wf = W - (base - fold) // (4 * N * N * elem)
-    assert library_layers(gf) <= Wf < W
-    inv = job_footprint_estimate(job(aterm_mode=1)[0])
-    assert inv - base == wl.aterms.size * elem
+    def fp(**kw):
+        j, g = job(**kw)
+        f = aidg.footprint(g, wl.n_stations, wl.baselines, wl.uvw, wl.freqs)
+        assert f["n_wlayers"] == library_layers(g)
+        assert f["grid_bytes"] == f["n_wlayers"] * f["n_pol"] * N * N * elem
+        assert f["vis_bytes"] == wl.n_vis * 4 * elem
+        fs = aidg.footprint(plan_geometry(j), wl.n_stations, wl.baselines, wl.uvw, wl.freqs)
+        assert job_footprint_estimate(j) == fs["plan_bytes"] + fs["grid_bytes"] + fs["vis_bytes"]
+        return f
+
+    base = fp()
+    assert base["n_pol"] == 4 and base["n_wlayers"] > 1
+    stokes = fp(stokes_i=1)
+    assert stokes["n_pol"] == 1 and stokes["grid_bytes"] * 4 == base["grid_bytes"]
+    fold = fp(w_fold=1)
+    assert fold["n_wlayers"] < base["n_wlayers"]
+    inv = fp(aterm_mode=1)
+    assert inv["aterm_bytes"] == 2 * base["aterm_bytes"] == 2 * wl.aterms.size * elem
+    assert inv["plan_bytes"] > base["plan_bytes"] + base["aterm_bytes"]
+
+
+@pytest.mark.parametrize("L,K", [(32, 8), (64, 16), (96, 24)])
+def test_footprint_layers_and_subgrids_on_the_mwa_observation(L, K):
+    """At the MWA-like size the estimate's layer count is the partition's (at transit and
+    at max |w| of 250 wavelengths), its subgrid count within a factor 2 of it, and the
+    estimate takes milliseconds where the partition takes about a second."""
+    import time
+    import paper_2502_17789_amd as aidg
+    for ha in (0.0, synth.hour_angle_for_wmax(250.0)):
+        wl = synth.config_mwa(seed=2, ha0_rad=ha)
+        g = Geometry(wl.grid_size, L, K, wl.pixel_scale, aterm_interval=wl.aterm_interval)
+        t0 = time.perf_counter()
+        f = aidg.footprint(g, wl.n_stations, wl.baselines, wl.uvw, wl.freqs)
+        t1 = time.perf_counter()
+        table, _ = aidg.partition(g, wl.n_stations, wl.baselines, wl.uvw, wl.freqs)
+        t2 = time.perf_counter()
+        assert f["n_wlayers"] == int(table["wlayer"].max()) + 1
+        assert 0.5 <= f["n_subgrids"] / table.shape[0] <= 2.0, (f["n_subgrids"], table.shape[0])
+        assert f["n_excluded"] == 0
+        assert t1 - t0 < 0.2 * (t2 - t1)
