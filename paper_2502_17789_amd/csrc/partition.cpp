@@ -179,14 +179,35 @@ bool centre(double lo, double hi, double half, int L, int N, int lattice, int* c
   return false;
 }
 
+// Along one row (baseline, timestep) u, v and w are one vector scaled by frequency, and
+// the channels' frequencies increase: a channel's cell coordinates and layer are
+// monotonic in the channel index (with rounding, weakly).  So the channels of a row that
+// can be placed form one interval (the placeable region is a box), a channel range's
+// bounding box is spanned by its two end channels, and its layers are all equal when
+// those of its ends are.  The partitioner below relies on this to look at the ends of
+// ranges only.
+
+// First channel in (c, e) for which pred is false, e if none; pred must be true at c
+// and, over (c, e), true up to some channel and false after it.
+template <typename F>
+int first_false(int c, int e, F pred) {
+  int lo = c, hi = e;  // pred(lo) true; the answer is in (lo, hi]
+  while (hi - lo > 1) {
+    const int mid = lo + (hi - lo) / 2;
+    if (pred(mid)) lo = mid;
+    else hi = mid;
+  }
+  return hi;
+}
+
 // Add row t, channels [c0, c1), to box b; false if the row has another fold state
 // than sgn, or a visibility is unplaceable or in another layer.
 bool add_row(const Ctx& x, int bl, int t, int c0, int c1, int64_t layer, double sgn, Box* b) {
   if (x.sign(bl, t) != sgn) return false;
-  for (int c = c0; c < c1; ++c) {
-    if (!x.placeable(bl, t, c) || x.layer(bl, t, c) != layer) return false;
-    b->add(x.cell(bl, t, c, 0), x.cell(bl, t, c, 1));
-  }
+  if (!x.placeable(bl, t, c0) || !x.placeable(bl, t, c1 - 1)) return false;
+  if (x.layer(bl, t, c0) != layer || x.layer(bl, t, c1 - 1) != layer) return false;
+  b->add(x.cell(bl, t, c0, 0), x.cell(bl, t, c0, 1));
+  b->add(x.cell(bl, t, c1 - 1, 0), x.cell(bl, t, c1 - 1, 1));
   return true;
 }
 
@@ -210,19 +231,30 @@ void tile(const Ctx& x, int bl, int ts, int te, int c_lo, int c_hi, PartitionRes
       continue;
     }
     const int64_t lay = x.layer(bl, ts, c);
+    // the run [c, e): placeable, one layer, at most max_sg_vis channels, and its box
+    // within 3/4 of the window and centred on a lattice cell
+    int e_lim = (int)std::min<int64_t>(c_hi, (int64_t)c + g.max_sg_vis);
+    e_lim = first_false(c, e_lim, [&](int k) { return x.placeable(bl, ts, k) && x.layer(bl, ts, k) == lay; });
+    auto fits = [&](int e) {
+      Box q;
+      q.add(x.cell(bl, ts, c, 0), x.cell(bl, ts, c, 1));
+      q.add(x.cell(bl, ts, e - 1, 0), x.cell(bl, ts, e - 1, 1));
+      int cu, cv;
+      return q.uhi - q.ulo <= comfy && q.vhi - q.vlo <= comfy && centre(q.ulo, q.uhi, half, g.L, g.N, g.lattice, &cu) &&
+             centre(q.vlo, q.vhi, half, g.L, g.N, g.lattice, &cv);
+    };
+    // largest e in [c + 1, e_lim] that fits (a single channel always does)
+    int lo = c + 1, hi = e_lim + 1;
+    while (hi - lo > 1) {
+      const int mid = lo + (hi - lo) / 2;
+      if (fits(mid)) lo = mid;
+      else hi = mid;
+    }
+    const int e = lo;
     Box b;
     b.add(x.cell(bl, ts, c, 0), x.cell(bl, ts, c, 1));
-    int e = c + 1, cu, cv;
-    while (e < c_hi && e - c < g.max_sg_vis) {
-      if (!x.placeable(bl, ts, e) || x.layer(bl, ts, e) != lay) break;
-      Box q = b;
-      q.add(x.cell(bl, ts, e, 0), x.cell(bl, ts, e, 1));
-      if (q.uhi - q.ulo > comfy || q.vhi - q.vlo > comfy) break;
-      if (!centre(q.ulo, q.uhi, half, g.L, g.N, g.lattice, &cu) || !centre(q.vlo, q.vhi, half, g.L, g.N, g.lattice, &cv))
-        break;
-      b = q;
-      ++e;
-    }
+    b.add(x.cell(bl, ts, e - 1, 0), x.cell(bl, ts, e - 1, 1));
+    int cu, cv;
     int t1 = ts + 1;
     while (t1 < te && (int64_t)(t1 - ts + 1) * (e - c) <= g.max_sg_vis) {
       Box q = b;
