@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "aidg_internal.h"
 
@@ -115,32 +116,6 @@ double auto_w_step(const Geometry& g) {
 
 namespace {
 
-struct Ctx {
-  const Geometry& g;
-  int nbl, nt, nc;
-  const double* uvw;
-  const double* freqs;
-  // -1 for a row the fold moves to -uvw (fold mode and w < 0), else +1
-  double sign(int bl, int t) const { return g.fold && uvw[3 * ((size_t)bl * nt + t) + 2] < 0 ? -1.0 : 1.0; }
-  double cell(int bl, int t, int c, int axis) const {
-    return sign(bl, t) * uvw[3 * ((size_t)bl * nt + t) + axis] * freqs[c] / kSpeedOfLight / g.du + g.N / 2;
-  }
-  double wl(int bl, int t, int c) const {
-    return sign(bl, t) * uvw[3 * ((size_t)bl * nt + t) + 2] * freqs[c] / kSpeedOfLight;
-  }
-  bool placeable(int bl, int t, int c) const {
-    const double gu = cell(bl, t, c, 0), gv = cell(bl, t, c, 1);
-    const double lo = g.K / 2.0, hi = g.N - g.K / 2.0;
-    return gu >= lo && gu <= hi && gv >= lo && gv <= hi && std::isfinite(gu) && std::isfinite(gv);
-  }
-  // nearest layer j w_step; with the fold (w >= 0) layers at (j + 1/2) w_step
-  int64_t layer(int bl, int t, int c) const {
-    if (!(g.w_step > 0)) return 0;
-    const double j = wl(bl, t, c) / g.w_step;
-    return (int64_t)(g.fold ? std::floor(j) : std::nearbyint(j));
-  }
-};
-
 struct Box {
   double ulo = 1e300, uhi = -1e300, vlo = 1e300, vhi = -1e300;
   void add(double u, double v) {
@@ -150,6 +125,37 @@ struct Box {
     vhi = std::max(vhi, v);
   }
 };
+
+struct Ctx {
+  const Geometry& g;
+  int nbl, nt, nc;
+  const double* uvw;
+  const double* freqs;
+  std::vector<Box>* boxes = nullptr;  // scratch of the time extension
+  // metres x Hz to grid cells, metres x Hz to wavelengths, wavelengths to layers
+  double k_cell = 1.0 / (kSpeedOfLight * g.du), k_w = 1.0 / kSpeedOfLight,
+         k_layer = g.w_step > 0 ? 1.0 / g.w_step : 0.0;
+  // -1 for a row the fold moves to -uvw (fold mode and w < 0), else +1
+  double sign(int bl, int t) const { return g.fold && uvw[3 * ((size_t)bl * nt + t) + 2] < 0 ? -1.0 : 1.0; }
+  double cell(int bl, int t, int c, int axis) const {
+    return sign(bl, t) * uvw[3 * ((size_t)bl * nt + t) + axis] * freqs[c] * k_cell + g.N / 2;
+  }
+  double wl(int bl, int t, int c) const {
+    return sign(bl, t) * uvw[3 * ((size_t)bl * nt + t) + 2] * freqs[c] * k_w;
+  }
+  bool inside(double gu, double gv) const {
+    const double lo = g.K / 2.0, hi = g.N - g.K / 2.0;
+    return gu >= lo && gu <= hi && gv >= lo && gv <= hi && std::isfinite(gu) && std::isfinite(gv);
+  }
+  bool placeable(int bl, int t, int c) const { return inside(cell(bl, t, c, 0), cell(bl, t, c, 1)); }
+  // nearest layer j w_step; with the fold (w >= 0) layers at (j + 1/2) w_step
+  int64_t layer(int bl, int t, int c) const {
+    if (!(g.w_step > 0)) return 0;
+    const double j = wl(bl, t, c) * k_layer;
+    return (int64_t)(g.fold ? std::floor(j) : std::nearbyint(j));
+  }
+};
+
 
 // Centre cell for a span [lo, hi]: a cell of the lattice N/2 + k * lattice near the
 // middle of the span (clamped so that the L-cell window stays on the grid); true
@@ -204,10 +210,12 @@ int first_false(int c, int e, F pred) {
 // than sgn, or a visibility is unplaceable or in another layer.
 bool add_row(const Ctx& x, int bl, int t, int c0, int c1, int64_t layer, double sgn, Box* b) {
   if (x.sign(bl, t) != sgn) return false;
-  if (!x.placeable(bl, t, c0) || !x.placeable(bl, t, c1 - 1)) return false;
+  const double u0 = x.cell(bl, t, c0, 0), v0 = x.cell(bl, t, c0, 1);
+  const double u1 = x.cell(bl, t, c1 - 1, 0), v1 = x.cell(bl, t, c1 - 1, 1);
+  if (!x.inside(u0, v0) || !x.inside(u1, v1)) return false;
   if (x.layer(bl, t, c0) != layer || x.layer(bl, t, c1 - 1) != layer) return false;
-  b->add(x.cell(bl, t, c0, 0), x.cell(bl, t, c0, 1));
-  b->add(x.cell(bl, t, c1 - 1, 0), x.cell(bl, t, c1 - 1, 1));
+  b->add(u0, v0);
+  b->add(u1, v1);
   return true;
 }
 
@@ -254,16 +262,31 @@ void tile(const Ctx& x, int bl, int ts, int te, int c_lo, int c_hi, PartitionRes
     Box b;
     b.add(x.cell(bl, ts, c, 0), x.cell(bl, ts, c, 1));
     b.add(x.cell(bl, ts, e - 1, 0), x.cell(bl, ts, e - 1, 1));
-    int cu, cv;
-    int t1 = ts + 1;
-    while (t1 < te && (int64_t)(t1 - ts + 1) * (e - c) <= g.max_sg_vis) {
-      Box q = b;
-      if (!add_row(x, bl, t1, c, e, lay, x.sign(bl, ts), &q)) break;
-      if (!centre(q.ulo, q.uhi, half, g.L, g.N, g.lattice, &cu) || !centre(q.vlo, q.vhi, half, g.L, g.N, g.lattice, &cv))
-        break;
-      b = q;
-      ++t1;
+    // extend the run over the rows below while they are placeable in the same layer
+    // and fold state, the visibilities stay under max_sg_vis and the rows' joint box
+    // keeps a lattice centre: prefix boxes of the rows that qualify, then the largest
+    // prefix whose box has a centre (binary search; a box that grows keeps none once it
+    // has lost it)
+    const int t_cap = (int)std::min<int64_t>(te, (int64_t)ts + g.max_sg_vis / (e - c));
+    std::vector<Box>& pre = *x.boxes;
+    pre.assign(1, b);
+    for (int t = ts + 1; t < t_cap; ++t) {
+      Box q = pre.back();
+      if (!add_row(x, bl, t, c, e, lay, x.sign(bl, ts), &q)) break;
+      pre.push_back(q);
     }
+    int cu, cv;
+    auto has_centre = [&](const Box& q) {
+      return centre(q.ulo, q.uhi, half, g.L, g.N, g.lattice, &cu) && centre(q.vlo, q.vhi, half, g.L, g.N, g.lattice, &cv);
+    };
+    int klo = 0, khi = (int)pre.size();  // prefix klo (rows ts..ts+klo) qualifies
+    while (khi - klo > 1) {
+      const int mid = klo + (khi - klo) / 2;
+      if (has_centre(pre[mid])) klo = mid;
+      else khi = mid;
+    }
+    b = pre[klo];
+    const int t1 = ts + 1 + klo;
     int U0, V0;
     centre(b.ulo, b.uhi, half, g.L, g.N, g.lattice, &U0);
     centre(b.vlo, b.vhi, half, g.L, g.N, g.lattice, &V0);
@@ -383,6 +406,8 @@ aidg_status partition(const Geometry& g, int n_st, int nbl, int nt, int nc, cons
       return AIDG_E_INVALID;
     }
   Ctx x{g, nbl, nt, nc, uvw, freqs};
+  std::vector<Box> boxes;
+  x.boxes = &boxes;
   out->table.clear();
   out->excluded.clear();
   out->w_step = g.w_step;
