@@ -253,7 +253,8 @@ def serve_bench(args):
         return np.array(lat), np.array(service), time.perf_counter() - t0
 
     def run_served(arrivals):
-        srv = Server(GpuBackend(workspace_bytes=1 << 30), range_subgrids=args.range_subgrids,
+        backend = GpuBackend(workspace_bytes=1 << 30, timing=True)
+        srv = Server(backend, range_subgrids=args.range_subgrids,
                      rounds_in_flight=args.rounds_in_flight, prepare_workers=args.prepare_workers,
                      max_active=args.max_active)
         futs = []
@@ -276,7 +277,8 @@ def serve_bench(args):
         lat = np.array([r.latency for r in res])
         span = max(r.finished for r in res) - min(r.arrival for r in res)
         stats = srv.stats()
-        del res, futs, srv
+        stats["busy_s"] = backend.busy_seconds()
+        del res, futs, srv, backend
         torch.cuda.synchronize()
         torch.cuda.empty_cache()   # the next run starts from the same free memory
         return lat, span, stats
@@ -291,11 +293,14 @@ def serve_bench(args):
                       "prepare_workers": args.prepare_workers, "max_active": args.max_active},
            "sequential_back_to_back": {"mvis_s": round(total / span0 / 1e6, 3)}, "loads": []}
     rng = np.random.default_rng(6)
-    for rho in args.rho:
-        gaps = rng.exponential(es / rho, len(mix))
-        arrivals = np.concatenate([[0.0], np.cumsum(gaps)[:-1]])
+    for rho in list(args.rho) + ["saturated"]:
+        if rho == "saturated":   # every job submitted at once: the server's own throughput
+            arrivals = np.zeros(len(mix))
+        else:
+            gaps = rng.exponential(es / rho, len(mix))
+            arrivals = np.concatenate([[0.0], np.cumsum(gaps)[:-1]])
         ls, span_s, st = run_served(arrivals)
-        lq, _, span_q = run_sequential(arrivals)
+        lq, _, span_q = (lat0, None, span0) if rho == "saturated" else run_sequential(arrivals)
         out["loads"].append({
             "rho": rho,
             "served": {"p50_ms": round(float(np.percentile(ls, 50)) * 1e3, 3),
@@ -303,7 +308,9 @@ def serve_bench(args):
                        "mvis_s": round(total / span_s / 1e6, 3), "rounds": st["rounds"],
                        "ranges_per_round": round(st["ranges_per_round"], 2),
                        "loop_wait_s": round(st["wait_s"], 3), "prepare_s": round(st["prepare_s"], 3),
-                       "makespan_s": round(span_s, 3), "peak_admitted_bytes": st["peak_bytes"]},
+                       "makespan_s": round(span_s, 3), "peak_admitted_bytes": st["peak_bytes"],
+                       "gpu_busy_s": round(st["busy_s"], 3), "gpu_busy_frac": round(st["busy_s"] / span_s, 4),
+                       "kernel_mvis_s": round(total / st["busy_s"] / 1e6, 3)},
             "sequential": {"p50_ms": round(float(np.percentile(lq, 50)) * 1e3, 3),
                            "p99_ms": round(float(np.percentile(lq, 99)) * 1e3, 3),
                            "mvis_s": round(total / span_q / 1e6, 3)}})

@@ -190,6 +190,11 @@ __device__ __forceinline__ Slot resolve(const Group& g, int64_t slot) {
 
 // ------------------------------------------------------------------ gridder
 
+// Phasors of the gridder: exp(+2 pi i theta) with the phase given in quarter turns,
+// 4 theta.
+__device__ __forceinline__ float2 gphasor(double theta4, float) { return phasor4(theta4); }
+__device__ __forceinline__ double2 gphasor(double theta4, double) { return phasor4_f64(theta4); }
+
 template <int L, typename R>
 __global__ __launch_bounds__(kThreads) void grid_dft(const Group g) {
   using V2 = typename C2<R>::T;
@@ -255,29 +260,30 @@ __global__ __launch_bounds__(kThreads) void grid_dft(const Group g) {
       const double um = uvw[0], vm = uvw[1], wm = uvw[2];
       const V4* vrow = vlds + 2 * t * s.nc;
       V2 st[kPix];  // per-channel step exp(2 pi i dfc (um l + vm m + wm n1))
-      {
-        const double su = um * s.dfc, sv = vm * s.dfc, sw = wm * s.dfc;
+      // the phasors' phases in quarter turns: 4 (cu l + cv m + cw n1)
+      auto seed = [&](V2 (&ph)[kPix], double cu, double cv, double cw) {
+        const double ku = 4.0 * cu, kv = 4.0 * cv, kw = 4.0 * cw;
 #pragma unroll
-        for (int p = 0; p < kPix; ++p) st[p] = phasor(su * px[p].l + sv * px[p].m + sw * px[p].n1, R());
-      }
+        for (int p = 0; p < kPix; ++p) ph[p] = gphasor(fma(ku, px[p].l, fma(kv, px[p].m, kw * px[p].n1)), R());
+      };
+      seed(st, um * s.dfc, vm * s.dfc, wm * s.dfc);
       for (int j0 = 0; j0 < s.nc; j0 += s.R) {
         const int jn = min(s.nc, j0 + s.R);
         // Channels j0..jn-1 of the row contribute ph_{j0} * H with
         // H = sum_k V_{j0+k} st^k, evaluated by Horner's rule from the last channel
-        // back (h <- h st + V_j: 4 FMA per polarisation, no phasor update), in two
-        // ping-pong register sets; ph_{j0} is the FP64-seeded phasor of the block.
-        V2 ha[kPix][4];
-        {
-          const V4 va = vrow[2 * (jn - 1)], vb = vrow[2 * (jn - 1) + 1];
-          const R vv[8] = {va.x, va.y, va.z, va.w, vb.x, vb.y, vb.z, vb.w};
-#pragma unroll
-          for (int p = 0; p < kPix; ++p)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) ha[p][q] = V2{vv[2 * q], vv[2 * q + 1]};
-        }
-        auto step = [&](int j, V2 (&h)[kPix][4]) {
+        // back (h <- h st + V_j: 4 FMA per polarisation, no phasor update), two
+        // channels per step; ph_{j0} is the FP64-seeded phasor of the block.  An even
+        // block starts with h = V_{jn-1} st + V_{jn-2} straight from the staged values,
+        // an odd one with h = V_{jn-1} (the only copies into per-pixel registers).
+        V2 h[kPix][4];
+        auto load = [&](int j, R (&vv)[8]) {
           const V4 va = vrow[2 * j], vb = vrow[2 * j + 1];
-          const R vv[8] = {va.x, va.y, va.z, va.w, vb.x, vb.y, vb.z, vb.w};
+          vv[0] = va.x; vv[1] = va.y; vv[2] = va.z; vv[3] = va.w;
+          vv[4] = vb.x; vv[5] = vb.y; vv[6] = vb.z; vv[7] = vb.w;
+        };
+        auto step = [&](int j) {
+          R vv[8];
+          load(j, vv);
 #pragma unroll
           for (int p = 0; p < kPix; ++p) {
 #pragma unroll
@@ -290,28 +296,50 @@ __global__ __launch_bounds__(kThreads) void grid_dft(const Group g) {
             }
           }
         };
-        auto finish = [&](const V2 (&h)[kPix][4]) {
-          const double fc = as_const(a.fc)[s.c0 + j0];
-          const double cu = um * fc - u0, cv = vm * fc - v0, cw = wm * fc - s.w0;
+        int j;
+        {
+          R vt[8];
+          load(jn - 1, vt);
+          if ((jn - j0) & 1) {
 #pragma unroll
-          for (int p = 0; p < kPix; ++p) {
-            const V2 ph = phasor(cu * px[p].l + cv * px[p].m + cw * px[p].n1, R());
+            for (int p = 0; p < kPix; ++p)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              acc[p][2 * q] = fma(h[p][q].x, ph.x, acc[p][2 * q]);
-              acc[p][2 * q] = fma(-h[p][q].y, ph.y, acc[p][2 * q]);
-              acc[p][2 * q + 1] = fma(h[p][q].x, ph.y, acc[p][2 * q + 1]);
-              acc[p][2 * q + 1] = fma(h[p][q].y, ph.x, acc[p][2 * q + 1]);
+              for (int q = 0; q < 4; ++q) h[p][q] = V2{vt[2 * q], vt[2 * q + 1]};
+            j = jn - 2;
+          } else {
+            R vv[8];
+            load(jn - 2, vv);
+#pragma unroll
+            for (int p = 0; p < kPix; ++p) {
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                R re = fma(vt[2 * q], st[p].x, vv[2 * q]);
+                re = fma(-vt[2 * q + 1], st[p].y, re);
+                R im = fma(vt[2 * q], st[p].y, vv[2 * q + 1]);
+                im = fma(vt[2 * q + 1], st[p].x, im);
+                h[p][q] = V2{re, im};
+              }
             }
+            j = jn - 3;
           }
-        };
-        int j = jn - 2;
-        for (; j > j0; j -= 2) {
-          step(j, ha);
-          step(j - 1, ha);
         }
-        if (j == j0) step(j, ha);
-        finish(ha);
+        for (; j > j0; j -= 2) {
+          step(j);
+          step(j - 1);
+        }
+        const double fc = as_const(a.fc)[s.c0 + j0];
+        V2 ph[kPix];
+        seed(ph, um * fc - u0, vm * fc - v0, wm * fc - s.w0);
+#pragma unroll
+        for (int p = 0; p < kPix; ++p) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            acc[p][2 * q] = fma(h[p][q].x, ph[p].x, acc[p][2 * q]);
+            acc[p][2 * q] = fma(-h[p][q].y, ph[p].y, acc[p][2 * q]);
+            acc[p][2 * q + 1] = fma(h[p][q].x, ph[p].y, acc[p][2 * q + 1]);
+            acc[p][2 * q + 1] = fma(h[p][q].y, ph[p].x, acc[p][2 * q + 1]);
+          }
+        }
       }
     }
 

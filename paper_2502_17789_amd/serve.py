@@ -103,12 +103,15 @@ class GpuBackend:
     """Device side of the server: plans, buffers and grouped execution.  Plans and
     inputs are uploaded on their own stream; the compute stream waits for them."""
 
-    def __init__(self, workspace_bytes: int = 1 << 30, stream=None):
+    def __init__(self, workspace_bytes: int = 1 << 30, stream=None, timing: bool = False):
         import torch
         self.torch = torch
         self.compute = stream if stream is not None else torch.cuda.current_stream()
         self.upload = torch.cuda.Stream()
         self.executor = Executor(workspace_bytes)
+        # with timing, every round is bracketed by timing events on the compute stream
+        self.timing = timing
+        self._timed = []
 
     def footprint(self, job: Job) -> int:
         return job_footprint_estimate(job)
@@ -151,11 +154,27 @@ class GpuBackend:
     def execute(self, ranges):
         """ranges: list of (handle, sg_begin, sg_end); returns a completion token."""
         torch = self.torch
+        start = None
+        if self.timing:
+            start = torch.cuda.Event(enable_timing=True)
+            start.record(self.compute)
         self.executor.execute([(h["plan"], h["dir"], h["in"], h["out"], b, e) for h, b, e in ranges],
                               stream=self.compute)
-        ev = torch.cuda.Event()
+        ev = torch.cuda.Event(enable_timing=self.timing)
         ev.record(self.compute)
+        if self.timing:
+            self._timed.append((start, ev))
         return ev
+
+    def busy_seconds(self) -> float:
+        """Device time of the timed rounds: the sum over rounds of the time between the
+        round's first and last kernel on the compute stream (a round that waits for its
+        plans' uploads counts that wait too)."""
+        total = 0.0
+        for a, b in self._timed:
+            b.synchronize()
+            total += a.elapsed_time(b) * 1e-3
+        return total
 
     def done(self, token) -> bool:
         return token.query()

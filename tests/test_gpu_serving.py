@@ -109,3 +109,77 @@ def test_footprint_estimate_bounds_the_plan(kind):
         assert f["n_wlayers"] == info["n_wlayers"] and f["grid_bytes"] == info["grid_bytes"]
         assert f["vis_bytes"] == info["vis_bytes"]
         assert 0.9 * info["device_bytes"] <= f["plan_bytes"] <= 1.5 * info["device_bytes"]
+
+
+def test_served_config5_jobs_equal_alone():
+    """Jobs of the served mixed workload's own sizes (synth.served_job_mix, seed 5): two
+    8000^2, L = 96 jobs of more than 3M visibilities (one gridding, one degridding), four
+    more of other grid and subgrid sizes, and 18 small gridding jobs of one class (L = 32,
+    FP32) that are active together, so that a round holds more than the 16 ranges of one
+    launch.  The executor's workspace holds 6 group images of L = 96, so launches are
+    flushed when it fills, also in the middle of a job's range.  Every served result must
+    equal the job run alone through its own plan: degridding bitwise (the same kernels on
+    the same subgrids, deterministic), gridding within 1e-6 element-wise (the order of the
+    FP32 atomic additions onto the grid differs)."""
+    import paper_2502_17789_amd as aidg
+    from paper_2502_17789_amd.serve import GpuBackend, Job, Server
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    mix = synth.served_job_mix(2000, seed=5)
+
+    def n_vis(d):
+        return d["baselines"].shape[0] * d["uvw"].shape[1] * d["freqs"].shape[0]
+
+    big = [31, 301]
+    assert all(mix[i]["N"] == 8000 and mix[i]["L"] == 96 and n_vis(mix[i]) >= 1e6 for i in big)
+    assert {mix[i]["direction"] for i in big} == {"grid", "degrid"}
+    others = []
+    for N, L in ((4096, 64), (2048, 32), (1024, 96), (8000, 64)):
+        others.append(next(i for i, d in enumerate(mix) if d["N"] == N and d["L"] == L and 2e4 <= n_vis(d) <= 1e6
+                           and i not in others))
+    small = [i for i, d in enumerate(mix) if d["L"] == 32 and d["direction"] == "grid" and n_vis(d) <= 3e4][:18]
+    assert len(small) == 18
+    picks = big + others + small
+
+    def job_of(i):
+        d = mix[i]
+        geo = aidg.Geometry(d["N"], d["L"], d["K"], d["dl"], aterm_interval=max(d["n_t"], 1))
+
+        def aterms():
+            return synth.device_phase_screen_aterms(d["n_stations"], d["L"], d["screen_rms"], d["seed"])
+
+        def data(shape):
+            g = torch.Generator(device="cuda")
+            g.manual_seed(d["seed"] + 1)
+            return torch.randn(shape, dtype=torch.complex64, device="cuda", generator=g)
+
+        return Job(d["direction"], geo, d["n_stations"], d["baselines"], d["uvw"], d["freqs"], aterms, data, tag=i)
+
+    srv = Server(GpuBackend(workspace_bytes=6 * 4 * 96 * 96 * 8), hbm_budget=64 << 30, range_subgrids=256,
+                 max_active=32)
+    with srv:
+        futs = [srv.submit(job_of(i)) for i in picks]
+        results = {f.result(timeout=300).tag: f.result().output for f in futs}
+    st = srv.stats()
+    print(f"served {st}", flush=True)
+    assert st["ranges_per_round"] > 2
+    for i in picks:
+        job = job_of(i)
+        A = job.aterms()
+        with aidg.Plan(job.geometry, job.n_stations, job.baselines, job.uvw, job.freqs, A) as p:
+            del A
+            if job.direction == "grid":
+                alone = p.grid(job.data(p.vis_shape()))
+            else:
+                alone = p.degrid(job.data(p.grid_shape()))
+            torch.cuda.synchronize()
+        got = results.pop(i)
+        tag = f"job {i} ({job.direction}, N={job.geometry.grid_size}, L={job.geometry.subgrid_size}, " \
+              f"{n_vis(mix[i])} vis) served vs alone"
+        if job.direction == "degrid":
+            assert torch.equal(got, alone), tag
+            print(tag + ": bitwise equal", flush=True)
+        else:
+            for j in range(alone.shape[0]):
+                check_grid(got[j].cpu().numpy(), alone[j].cpu().numpy(), 1e-6, f"{tag}, layer {j}")
+        del got, alone
