@@ -72,6 +72,22 @@ def check_vis(x, ref, tol: float, label: str = "vis") -> dict:
     return e
 
 
+def check_image(x, ref, T, tol: float, label: str = "image", untapered: bool = False) -> dict:
+    """Gate for an image made by the image level (invert), which divides the sum of the
+    layers' transforms by the taper T.  That division is exact scaling, but it lifts the
+    transform's FP32 rounding by up to 1 / min T at the field's edge, so the element-wise
+    gate applies to T x and T ref, the quantity the transform produces (T broadcast over
+    the trailing polarisation axis).  The untapered error is printed; untapered=True
+    (the FP64 path) gates it too."""
+    Tc = np.asarray(T, np.float64)[..., None]
+    e = check_grid(_c128(x) * Tc, _c128(ref) * Tc, tol, "T x " + label)
+    u = grid_errors(x, ref)
+    print(_fmt(label + " (untapered)", u), flush=True)
+    if untapered:
+        assert u["normwise"] <= tol and u["max_over_max"] <= tol, (label, u)
+    return e
+
+
 def check_inner(lhs: complex, rhs: complex, tol: float, label: str = "adjoint") -> float:
     """Relative residual of an inner-product identity, |lhs - rhs| / |lhs|.  The
     callers pick their inputs so that |lhs| is of the order of the product of the

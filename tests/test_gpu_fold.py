@@ -6,14 +6,15 @@ stations' A-terms swapped, and the w-layers sit at odd multiples of w_step / 2.
     degridding on it match the oracle element by element (FP32 <= 1e-5,
     FP64 <= 1e-10, normwise);
   * through the library alone: the Hermitian part of invert(grid(V)) at lattice
-    pixels is that of the direct A-term image, and degrid(predict(I)) of lattice
+    pixels is that of the direct A-term image (gated on the tapered image, the
+    quantity the FP32 transform produces), and degrid(predict(I)) of lattice
     point sources with Hermitian brightness is their direct prediction.
 """
 import numpy as np
 import pytest
 
 import synth
-from gates import check_grid, check_vis
+from gates import check_grid, check_image, check_vis
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -104,6 +105,7 @@ def test_fold_image_and_prediction_are_exact_at_lattice_points(aidg, orc, name):
     l, m = orc.lattice_dirs(wl, xs, ys)
     mask = orc.coverage_mask(wl, table)
     ref = orc.direct_image(wl, V, l, m, xs, ys, mask=mask)
-    check_grid(herm_part(img[:, Y, X].T), herm_part(ref), 1e-5, f"fold {name} Hermitian image")
+    T = orc.taper(L, wl.kernel_support)[ys, xs]
+    check_image(herm_part(img[:, Y, X].T), herm_part(ref), T, 1e-5, f"fold {name} Hermitian image")
     Vd = orc.direct_predict(wl, src["l"], src["m"], src["B"], src["xs"], src["ys"])
     check_vis(Vp[mask.astype(bool)], Vd[mask.astype(bool)], 1e-5, f"fold {name} prediction")

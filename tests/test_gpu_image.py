@@ -16,7 +16,7 @@ import numpy as np
 import pytest
 
 import synth
-from gates import check_grid, check_inner, check_vis
+from gates import check_grid, check_image, check_inner, check_vis
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -124,7 +124,8 @@ def test_invert_of_gridded_visibilities_is_the_direct_image(aidg, orc, precision
     xs, ys, X, Y = lattice_pixels(wl, rng, 80)
     l, m = orc.lattice_dirs(wl, xs, ys)
     ref = orc.direct_image(wl, V, l, m, xs, ys, mask=orc.coverage_mask(wl, table))
-    check_grid(I[:, Y, X].T, ref, TOL[precision], "invert(grid(V)) at lattice pixels vs direct image")
+    check_image(I[:, Y, X].T, ref, orc.taper(wl.subgrid_size, wl.kernel_support)[ys, xs], TOL[precision],
+                "invert(grid(V)) at lattice pixels vs direct image", untapered=precision == 1)
 
 
 @pytest.mark.parametrize("precision", [0, 1])
