@@ -63,7 +63,7 @@
 extern "C" {
 #endif
 
-#define AIDG_ABI_VERSION 6
+#define AIDG_ABI_VERSION 7
 
 typedef enum {
   AIDG_OK = 0,
@@ -255,7 +255,9 @@ aidg_status aidg_degrid_adjoint(aidg_plan* plan, const void* grid, void* vis_out
  * A-term copy (two plane sets in the inverse A-term mode), uvw and channel tables, the
  * subgrid records (their count estimated from each row's uv extent over the channels,
  * its gaps and layer changes), the excluded-visibility list, the batch workspace
- * (workspace_bytes, capped at what the estimated subgrids fill) and the image-level
+ * (workspace_bytes, capped at one group image per estimated same-centre group: the
+ * distinct (layer, lattice centre) pairs of the rows' channel runs, plus a quarter for
+ * groups the plan splits and centres the sample misses) and the image-level
  * tables.  All host arrays as in aidg_plan_create; nothing is allocated on the device. */
 typedef struct {
   int32_t n_wlayers;      /* layers of the plan's grid */
@@ -267,6 +269,7 @@ typedef struct {
   int64_t vis_bytes;      /* one visibility array */
   int64_t aterm_bytes;    /* the plan's A-term planes */
   int64_t plan_bytes;     /* estimate of the plan's own device memory (A-terms included) */
+  int64_t n_groups;       /* estimate of the same-centre groups (subgrid images per batch) */
 } aidg_footprint;
 aidg_status aidg_footprint_estimate(const aidg_geometry* geo, int32_t n_stations, int32_t n_baselines,
                                     int32_t n_times, int32_t n_chans, const double* uvw_m,

@@ -59,7 +59,8 @@ class _PlanInfo(ctypes.Structure):
 class _Footprint(ctypes.Structure):
     _fields_ = [("n_wlayers", ctypes.c_int32), ("n_pol", ctypes.c_int32), ("w_step", ctypes.c_double),
                 ("n_subgrids", ctypes.c_int64), ("n_excluded", ctypes.c_int64), ("grid_bytes", ctypes.c_int64),
-                ("vis_bytes", ctypes.c_int64), ("aterm_bytes", ctypes.c_int64), ("plan_bytes", ctypes.c_int64)]
+                ("vis_bytes", ctypes.c_int64), ("aterm_bytes", ctypes.c_int64), ("plan_bytes", ctypes.c_int64),
+                ("n_groups", ctypes.c_int64)]
 
 
 KERNEL_CLASSES = ("grid_dft", "fft_add", "split_ifft", "degrid_dft", "zero_vis", "image_fft",
@@ -113,7 +114,7 @@ class Geometry:
 
 
 _lib = None
-ABI_VERSION = 6  # the structure layouts above follow include/aidg.h at this version
+ABI_VERSION = 7  # the structure layouts above follow include/aidg.h at this version
 
 
 def library() -> ctypes.CDLL:
@@ -194,7 +195,8 @@ def partition(geometry: Geometry, n_stations: int, baselines, uvw, freqs):
 def footprint(geometry: Geometry, n_stations: int, baselines, uvw, freqs) -> dict:
     """Device memory a plan of this observation and its data would take, estimated on the
     host without building the plan (``aidg_footprint_estimate``): n_wlayers, grid_bytes,
-    vis_bytes, aterm_bytes, plan_bytes and the estimated subgrid count."""
+    vis_bytes, aterm_bytes, plan_bytes and the estimated subgrid and same-centre group
+    counts."""
     lib = library()
     u, f = _host(uvw, np.float64), _host(freqs, np.float64)
     nbl = int(np.asarray(baselines).shape[0])

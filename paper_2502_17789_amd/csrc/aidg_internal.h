@@ -62,9 +62,10 @@ aidg_status partition(const Geometry& g, int n_st, int nbl, int nt, int nc, cons
 // Host estimate of a partition's shape without building it: the w-layer range of the
 // placeable visibilities, the unplaceable count, and an estimate of the number of
 // subgrids (per row: the channel runs its uv extent needs, plus one per gap or layer
-// change, plus the splits at max_sg_vis).
+// change, plus the splits at max_sg_vis), and of the number of same-centre groups (the
+// distinct (layer, lattice centre) pairs of the runs' midpoints, plus a quarter).
 struct ShapeEstimate {
-  int64_t jmin = 0, jmax = 0, n_excluded = 0, n_subgrids = 0;
+  int64_t jmin = 0, jmax = 0, n_excluded = 0, n_subgrids = 0, n_groups = 0;
 };
 void estimate_shape(const Geometry& g, int nbl, int nt, int nc, const double* uvw, const double* freqs,
                     ShapeEstimate* out);

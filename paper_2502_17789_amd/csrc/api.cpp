@@ -890,6 +890,7 @@ aidg_status aidg_footprint_estimate(const aidg_geometry* geo, int32_t n_stations
     out->n_pol = g.npol;
     out->w_step = g.w_step > 0 ? g.w_step : 0.0;
     out->n_subgrids = n_sg;
+    out->n_groups = se.n_groups;
     out->n_excluded = se.n_excluded;
     out->grid_bytes = (int64_t)out->n_wlayers * g.npol * N * N * elem;
     out->vis_bytes = n_vis * 4 * elem;
@@ -897,7 +898,7 @@ aidg_status aidg_footprint_estimate(const aidg_geometry* geo, int32_t n_stations
     // what aidg_plan_create allocates, each allocation at least 256 bytes
     auto al = [](int64_t b) { return std::max<int64_t>(b, 256); };
     const int64_t per_image = 4 * L * L * elem;
-    const int64_t batch = std::max<int64_t>(1, std::min<int64_t>({g.workspace / per_image, 65535, n_sg}));
+    const int64_t batch = std::max<int64_t>(1, std::min<int64_t>({g.workspace / per_image, 65535, se.n_groups}));
     int64_t b = al(n_sg * (int64_t)sizeof(SubgridDev)) + al((int64_t)n_baselines * n_times * 24 * (g.fold ? 2 : 1)) +
                 al((int64_t)n_chans * 8) + out->aterm_bytes + al(L * L * elem / 2) + al(L * elem) +
                 al(se.n_excluded * 8) + al((n_sg + 1) * 8) + al(batch * per_image) + al(sizeof(KernelArgs));

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <unordered_set>
 #include <vector>
 
 #include "aidg_internal.h"
@@ -321,6 +322,19 @@ void estimate_shape(const Geometry& g, int nbl, int nt, int nc, const double* uv
   *out = ShapeEstimate{};
   bool any = false;
   int64_t placed = 0;
+  // Same-centre groups: the partition centres a run near the middle of its uv span on
+  // the lattice N/2 + k lattice (clamped so that the window stays on the grid), so the
+  // distinct (layer, nearest lattice cell) pairs of the runs' midpoints count them.
+  std::unordered_set<uint64_t> centres;
+  auto lattice_cell = [&](double c) {
+    const double k = std::nearbyint((c - g.N / 2) / g.lattice);
+    const double lo = std::ceil((g.L / 2 - g.N / 2) / (double)g.lattice),
+                 hi = std::floor((g.N - g.L / 2 - g.N / 2) / (double)g.lattice);
+    return (uint64_t)((int64_t)std::min(std::max(k, lo), hi) + (1 << 19)) & 0xFFFFF;
+  };
+  auto mark = [&](double cu, double cv, int64_t lay) {
+    centres.insert(((uint64_t)(lay + (1 << 23)) & 0xFFFFFF) << 40 | lattice_cell(cu) << 20 | lattice_cell(cv));
+  };
   auto take = [&](int64_t lay) {
     out->jmin = any ? std::min(out->jmin, lay) : lay;
     out->jmax = any ? std::max(out->jmax, lay) : lay;
@@ -353,7 +367,19 @@ void estimate_shape(const Geometry& g, int nbl, int nt, int nc, const double* uv
           drift = std::max({drift, std::fabs(x.cell(bl, t, cm, 0) - x.cell(bl, ta, cm, 0)),
                             std::fabs(x.cell(bl, t, cm, 1) - x.cell(bl, ta, cm, 1))});
         }
-        out->n_subgrids += (runs + layers) * (1 + (int64_t)std::floor(drift / (0.25 * (g.L - g.K))));
+        const int64_t segs = 1 + (int64_t)std::floor(drift / (0.25 * (g.L - g.K)));
+        out->n_subgrids += (runs + layers) * segs;
+        // the runs' midpoints on the first row of each time segment
+        for (int64_t sgm = 0; sgm < segs; ++sgm) {
+          const int t = ta + (int)(sgm * (te - ta) / segs);
+          const double u0 = x.cell(bl, t, 0, 0), u1 = x.cell(bl, t, nc - 1, 0);
+          const double v0 = x.cell(bl, t, 0, 1), v1 = x.cell(bl, t, nc - 1, 1);
+          const int64_t j0 = x.layer(bl, t, 0), j1 = x.layer(bl, t, nc - 1);
+          for (int64_t i = 0; i < runs; ++i) {
+            const double f = (i + 0.5) / runs;
+            mark(u0 + f * (u1 - u0), v0 + f * (v1 - v0), std::llround(j0 + f * (double)(j1 - j0)));
+          }
+        }
         placed += (int64_t)(te - ta) * nc;
         continue;
       }
@@ -375,10 +401,16 @@ void estimate_shape(const Geometry& g, int nbl, int nt, int nc, const double* uv
         take(lay);
         ++placed;
       }
-      if (pieces) out->n_subgrids += pieces + (int64_t)std::floor(std::max(b.uhi - b.ulo, b.vhi - b.vlo) / comfy);
+      if (pieces) {
+        out->n_subgrids += pieces + (int64_t)std::floor(std::max(b.uhi - b.ulo, b.vhi - b.vlo) / comfy);
+        mark(0.5 * (b.ulo + b.uhi), 0.5 * (b.vlo + b.vhi), prev_layer);
+      }
       }
     }
   out->n_subgrids += (placed + g.max_sg_vis - 1) / g.max_sg_vis;
+  // a quarter more for the groups the size cap splits (at most one in eight) and the
+  // centres the midpoint sample misses
+  out->n_groups = std::min<int64_t>(((int64_t)centres.size() * 5 + 3) / 4, out->n_subgrids);
 }
 
 aidg_status partition(const Geometry& g, int n_st, int nbl, int nt, int nc, const int32_t* baselines,

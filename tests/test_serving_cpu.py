@@ -265,6 +265,33 @@ def test_footprint_follows_geometry_variants():
     assert inv["plan_bytes"] > base["plan_bytes"] + base["aterm_bytes"]
 
 
+def distinct_centres(table):
+    """Same-centre groups of a partition before the size cap splits any: its distinct
+    (layer, U0, V0)."""
+    return len(set(zip(table["wlayer"].tolist(), table["U0"].tolist(), table["V0"].tolist())))
+
+
+@pytest.mark.parametrize("kind", ["tiny_fold_inverse", "diff_stokes"])
+def test_footprint_group_estimate_on_small_observations(kind):
+    """The estimate's same-centre group count (with its quarter margin), which caps the
+    batch workspace in plan_bytes, against the library partition's distinct centres (a
+    plan's workspace holds
+    one image per group, so an estimate bounded by the subgrid count alone overstates a
+    plan whose subgrids share few centres)."""
+    import paper_2502_17789_amd as aidg
+    if kind == "tiny_fold_inverse":
+        wl, kw = synth.config_tiny(71, ha0_deg=-60.0, beam_fwhm_deg=15.0), dict(w_step=12.0, w_fold=1, aterm_mode=1)
+    else:
+        wl, kw = synth.config_diff(seed=4), dict(stokes_i=1)
+    g = Geometry(wl.grid_size, wl.subgrid_size, wl.kernel_support, wl.pixel_scale,
+                 aterm_interval=wl.aterm_interval, **kw)
+    f = aidg.footprint(g, wl.n_stations, wl.baselines, wl.uvw, wl.freqs)
+    table, _ = aidg.partition(g, wl.n_stations, wl.baselines, wl.uvw, wl.freqs)
+    centres = distinct_centres(table)
+    print(kind, f["n_groups"], centres, f["n_subgrids"], table.shape[0])
+    assert 0.9 <= f["n_groups"] / centres <= 1.6, (f["n_groups"], centres)
+
+
 @pytest.mark.parametrize("L,K", [(32, 8), (64, 16), (96, 24)])
 def test_footprint_layers_and_subgrids_on_the_mwa_observation(L, K):
     """At the MWA-like size the estimate's layer count is the partition's (at transit and
@@ -282,5 +309,7 @@ def test_footprint_layers_and_subgrids_on_the_mwa_observation(L, K):
         t2 = time.perf_counter()
         assert f["n_wlayers"] == int(table["wlayer"].max()) + 1
         assert 0.5 <= f["n_subgrids"] / table.shape[0] <= 2.0, (f["n_subgrids"], table.shape[0])
+        centres = distinct_centres(table)
+        assert 0.9 <= f["n_groups"] / centres <= 1.6, (f["n_groups"], centres)
         assert f["n_excluded"] == 0
         assert t1 - t0 < 0.2 * (t2 - t1)
