@@ -17,6 +17,7 @@ Usage: python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--no-cpu-baseline]
 from __future__ import annotations
 
 import argparse
+import copy
 import json
 import os
 import sys
@@ -77,6 +78,61 @@ def measured_traffic(kernel: str):
     return None if k is None else round(k["bytes_per_launch"])
 
 
+def summarize_traffic(copy_fetch: str, copy_write: str, run_fetch: str, run_write: str, trace: str, out: str):
+    """HBM bytes per launch of every kernel of a counter run, from rocprofv3 CSV output
+    directories (FETCH_SIZE and WRITE_SIZE passes of the copy probe and of the run, and
+    a --kernel-trace --stats run of the same command for the launch times), scaled by
+    what the counters read for the 1 GiB device-to-device copy.  Writes the JSON that
+    measured_traffic() reads, keyed by the library's source hash."""
+    import csv
+    import glob
+
+    def counters(d):
+        tot, n = {}, {}
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for row in csv.DictReader(open(f)):
+                k = row["Kernel_Name"]
+                tot[k] = tot.get(k, 0.0) + float(row["Counter_Value"])
+                n[k] = n.get(k, 0) + 1
+        return tot, n
+
+    def short(name):
+        for k in ("grid_dft", "fft_add", "split_ifft", "degrid_dft", "copyBuffer"):
+            if k in name:
+                return k
+        return None
+
+    cf, cn = counters(copy_fetch)
+    cw, _ = counters(copy_write)
+    copy_bytes = 1 << 30
+    ck = [k for k in cf if "copyBuffer" in k]
+    fetch_scale = copy_bytes / 1024 / (cf[ck[0]] / cn[ck[0]]) if ck else 1.0
+    ck = [k for k in cw if "copyBuffer" in k]
+    write_scale = copy_bytes / 1024 / (cw[ck[0]] / cn[ck[0]]) if ck else 1.0
+    rf, rn = counters(run_fetch)
+    rw, _ = counters(run_write)
+    ms = {}
+    for f in glob.glob(os.path.join(trace, "**", "*kernel_stats.csv"), recursive=True):
+        for row in csv.DictReader(open(f)):
+            k = short(row["Name"])
+            if k:
+                ms[k] = float(row["AverageNs"]) / 1e6
+    rec = {"library_sha256": library_source_hash(), "copy_probe_bytes": copy_bytes,
+           "fetch_scale": fetch_scale, "write_scale": write_scale, "kernels": {}}
+    for name, v in rf.items():
+        k = short(name)
+        if k is None or k == "copyBuffer":
+            continue
+        launches = rn[name]
+        fk, wk = v / launches, rw.get(name, 0.0) / launches
+        rec["kernels"][k] = {"launches": launches, "fetch_kib_raw": fk, "write_kib_raw": wk,
+                             "read_bytes": fk * 1024 * fetch_scale, "write_bytes": wk * 1024 * write_scale,
+                             "bytes_per_launch": (fk * fetch_scale + wk * write_scale) * 1024,
+                             "launch_ms": ms.get(k)}
+    json.dump(rec, open(out, "w"), indent=1)
+    print(json.dumps(rec), flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,6 +161,16 @@ def parse():
     ap.add_argument("--lattice-cases", type=lambda t: tuple(int(x) for x in t.split(":")), nargs="*",
                     default=[], help="extra FP32 kernel-sweep cases L:lattice (centre lattice step)")
     ap.add_argument("--lattice-only", action="store_true", help="kernel sweep: only the --lattice-cases")
+    ap.add_argument("--degrid-forms", type=int, nargs="+", default=[0],
+                    help="kernel sweep: degridder forms to run (0 automatic, 1 recurrence, 2 per visibility, "
+                         "3 direct)")
+    ap.add_argument("--occupancy-sweep", action="store_true",
+                    help="degridder forms against subgrid occupancy: the MWA-like observation with every "
+                         "k-th channel kept (k from --occupancy-decimation), FP32 (JSON line per case)")
+    ap.add_argument("--occupancy-decimation", type=int, nargs="+", default=[1, 4, 12, 32, 96])
+    ap.add_argument("--occupancy-L", type=int, nargs="+", default=[32, 96])
+    ap.add_argument("--occupancy-forms", type=int, nargs="+", default=[1, 3, 2, 0],
+                    help="occupancy sweep: degridder forms (1 recurrence, 3 direct, 2 per visibility, 0 auto)")
     ap.add_argument("--image", action="store_true",
                     help="image-level w-stacking (invert and predict) at the MWA-like size, FP32, at "
                          "max |w| of --image-wmax wavelengths (JSON line per case)")
@@ -117,6 +183,9 @@ def parse():
                     help="Stokes-I grids: one complex value per cell instead of four")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device-to-device 3 times (calibrates HBM byte counters)")
+    ap.add_argument("--summarize-traffic", nargs=6, metavar=("COPY_FETCH", "COPY_WRITE", "FETCH", "WRITE",
+                                                            "TRACE", "OUT"),
+                    help="no GPU: write the per-kernel HBM traffic JSON from rocprofv3 CSV directories")
     return ap.parse_args()
 
 
@@ -398,10 +467,62 @@ def precision_study(args):
             torch.cuda.empty_cache()
 
 
+def _kernel_case(aidg, wl, prec, L, lattice=0, form=0, reps=2):
+    """Kernel times of one plan of the observation `wl` at subgrid size L (K = L/4):
+    HIP events around every launch, mean of `reps` grid + degrid calls after a
+    warm-up.  Returns the JSON record of the case."""
+    import torch
+
+    import synth
+
+    cdt = torch.complex64 if prec == aidg.FP32 else torch.complex128
+    A = synth.device_phase_screen_aterms(wl.n_stations, L, 2.0, seed=7)
+    n_int = (wl.n_times + wl.aterm_interval - 1) // wl.aterm_interval
+    A = A.expand(n_int, -1, -1, -1, -1).contiguous().to(cdt)
+    geo = aidg.Geometry(wl.grid_size, L, L // 4, wl.pixel_scale, aterm_interval=wl.aterm_interval,
+                        precision=prec, center_lattice=lattice, degrid_form=form)
+    gen = torch.Generator(device="cuda")
+    with aidg.Plan(geo, wl.n_stations, wl.baselines, wl.uvw, wl.freqs, A) as plan:
+        del A
+        gen.manual_seed(2)
+        V = torch.randn(plan.vis_shape(), dtype=cdt, device="cuda", generator=gen)
+        G = torch.zeros(plan.grid_shape(), dtype=cdt, device="cuda")
+        Vo = torch.empty_like(V)
+        plan.grid(V, G)
+        plan.degrid(G, Vo)
+        torch.cuda.synchronize()
+        plan.set_profiling(True)
+        for _ in range(reps):
+            plan.grid(V, G)
+            plan.degrid(G, Vo)
+        torch.cuda.synchronize()
+        kt = plan.kernel_times()
+        info = plan.info
+        del V, G, Vo
+    torch.cuda.empty_cache()
+    ms = {k: v["ms"] / reps for k, v in kt.items()}
+    n = wl.n_vis
+    t_grid = ms["grid_dft"] + ms["fft_add"]
+    t_degrid = ms["split_ifft"] + ms["degrid_dft"]
+    return {
+        "subgrid_size": L, "kernel_support": L // 4, "center_lattice": lattice or "auto",
+        "precision": "fp32" if prec == aidg.FP32 else "fp64",
+        "degrid_form": ("auto", "recurrence", "per_vis", "direct")[form],
+        "n_vis": n, "n_chans": int(wl.n_chans), "n_subgrids": info["n_subgrids"], "n_groups": info["n_groups"],
+        "n_subgrids_pervis": info["n_subgrids_pervis"], "n_subgrids_direct": info["n_subgrids_direct"],
+        "mean_vis_per_subgrid": round(n / max(info["n_subgrids"], 1), 1),
+        "grid_mvis_s": round(n / (t_grid * 1e-3) / 1e6, 1),
+        "degrid_mvis_s": round(n / (t_degrid * 1e-3) / 1e6, 1),
+        "ms": {k: round(v, 3) for k, v in ms.items() if v > 0},
+        "dft_tflops": {k: round(kt[k]["vis_pixels"] * FLOP_PER_VP_EXECUTED[k] / (ms[k] * reps * 1e-3) / 1e12, 2)
+                       for k in ("grid_dft", "degrid_dft")}}
+
+
 def kernel_sweep(args):
     """Throughput against subgrid size, kernels only (HIP events around every launch):
     the MWA-like observation partitioned at L = 32, 64, 96 with K = L/4, in FP32
-    and FP64.  grid = grid_dft + fft_add, degrid = split_ifft + degrid_dft."""
+    and FP64, for each degridder form of --degrid-forms.  grid = grid_dft + fft_add,
+    degrid = split_ifft + degrid_dft."""
     import torch
 
     import paper_2502_17789_amd as aidg
@@ -409,50 +530,35 @@ def kernel_sweep(args):
 
     torch.cuda.set_device(0)
     wl = synth.config_mwa(seed=2)
-    gen = torch.Generator(device="cuda")
     cases = [] if args.lattice_only else [(prec, L, 0) for prec in (aidg.FP32, aidg.FP64) for L in (32, 64, 96)]
     cases += [(aidg.FP32, L, lat) for L, lat in args.lattice_cases]
     for prec, L, lattice in cases:
-        cdt = torch.complex64 if prec == aidg.FP32 else torch.complex128
-        if True:
-            A = synth.device_phase_screen_aterms(wl.n_stations, L, 2.0, seed=7)
-            n_int = (wl.n_times + wl.aterm_interval - 1) // wl.aterm_interval
-            A = A.expand(n_int, -1, -1, -1, -1).contiguous().to(cdt)
-            geo = aidg.Geometry(wl.grid_size, L, L // 4, wl.pixel_scale, aterm_interval=wl.aterm_interval,
-                                precision=prec, center_lattice=lattice)
-            with aidg.Plan(geo, wl.n_stations, wl.baselines, wl.uvw, wl.freqs, A) as plan:
-                del A
-                gen.manual_seed(2)
-                V = torch.randn(plan.vis_shape(), dtype=cdt, device="cuda", generator=gen)
-                G = torch.zeros(plan.grid_shape(), dtype=cdt, device="cuda")
-                Vo = torch.empty_like(V)
-                plan.grid(V, G)
-                plan.degrid(G, Vo)
-                torch.cuda.synchronize()
-                plan.set_profiling(True)
-                reps = 2
-                for _ in range(reps):
-                    plan.grid(V, G)
-                    plan.degrid(G, Vo)
-                torch.cuda.synchronize()
-                kt = plan.kernel_times()
-                info = plan.info
-                del V, G, Vo
-            ms = {k: v["ms"] / reps for k, v in kt.items()}
-            n = wl.n_vis
-            t_grid = ms["grid_dft"] + ms["fft_add"]
-            t_degrid = ms["split_ifft"] + ms["degrid_dft"]
-            print(json.dumps({
-                "kernel_sweep": {"subgrid_size": L, "kernel_support": L // 4, "center_lattice": lattice or "auto",
-                                 "precision": "fp32" if prec == aidg.FP32 else "fp64",
-                                 "n_vis": n, "n_subgrids": info["n_subgrids"], "n_groups": info["n_groups"],
-                                 "mean_vis_per_subgrid": round(n / max(info["n_subgrids"], 1), 1)},
-                "grid_mvis_s": round(n / (t_grid * 1e-3) / 1e6, 1),
-                "degrid_mvis_s": round(n / (t_degrid * 1e-3) / 1e6, 1),
-                "ms": {k: round(v, 3) for k, v in ms.items() if v > 0},
-                "dft_tflops": {k: round(kt[k]["vis_pixels"] * FLOP_PER_VP / (ms[k] * reps * 1e-3) / 1e12, 2)
-                               for k in ("grid_dft", "degrid_dft")}}), flush=True)
-            torch.cuda.empty_cache()
+        for form in args.degrid_forms:
+            rec = _kernel_case(aidg, wl, prec, L, lattice, form)
+            print(json.dumps({"kernel_sweep": rec}), flush=True)
+
+
+def occupancy_sweep(args):
+    """Degridder throughput against subgrid occupancy (Sec. 4.2, subgrid occupancy): the
+    MWA-like observation with every k-th channel kept (rows of about 1/k the channels,
+    subgrids of about 1/k the visibilities), degridded in each form of
+    --occupancy-forms: the channel recurrence, direct phasors, per visibility (where a
+    sub-table fits the workgroup) and the automatic choice per subgrid."""
+    import torch
+
+    import paper_2502_17789_amd as aidg
+    import synth
+
+    torch.cuda.set_device(0)
+    base = synth.config_mwa(seed=2)
+    for L in args.occupancy_L:
+        for k in args.occupancy_decimation:
+            wl = copy.copy(base)
+            wl.freqs = np.ascontiguousarray(base.freqs[::k])
+            for form in args.occupancy_forms:
+                rec = _kernel_case(aidg, wl, aidg.FP32, L, 0, form)
+                rec["channel_decimation"] = k
+                print(json.dumps({"occupancy_sweep": rec}), flush=True)
 
 
 def image_bench(args):
@@ -584,8 +690,14 @@ def main():
     if args.kernel_sweep:
         kernel_sweep(args)
         return
+    if args.occupancy_sweep:
+        occupancy_sweep(args)
+        return
     if args.image:
         image_bench(args)
+        return
+    if args.summarize_traffic:
+        summarize_traffic(*args.summarize_traffic)
         return
     if args.copy_probe:
         import torch

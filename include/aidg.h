@@ -63,7 +63,7 @@
 extern "C" {
 #endif
 
-#define AIDG_ABI_VERSION 7
+#define AIDG_ABI_VERSION 8
 
 typedef enum {
   AIDG_OK = 0,
@@ -131,9 +131,27 @@ typedef struct {
                               [W][1][N][N] and images [1][N][N].  Gridding is then the
                               adjoint of degridding up to a factor 2:
                               <grid(V), G> = <V, degrid(G)> / 2.  0: four planes (default) */
+  int32_t degrid_form;     /* degridder design per subgrid (Sec. 3.2, Degridder: a kernel
+                              design chosen by subgrid occupancy); the forms agree to
+                              rounding.  AIDG_DEGRID_AUTO (0): per subgrid, the form of
+                              least modelled cost (the direct form for rows of a few
+                              channels, the recurrence for longer ones).
+                              AIDG_DEGRID_RECURRENCE (1): lanes own subgrid pixels, the
+                              phasors step along each row's channels (FP64-seeded every
+                              reseed_channels) and each visibility is a cross-lane
+                              reduction; sub-tables without a common channel spacing take
+                              the direct form.  AIDG_DEGRID_PER_VIS (2): lanes own
+                              visibilities, every (visibility, pixel) phase is formed in
+                              FP64, for sub-tables of at most 256 visibilities (128 at
+                              L = 32 in FP32), the recurrence for larger ones (the paper's
+                              "natural" thread-per-visibility design).
+                              AIDG_DEGRID_DIRECT (3): lanes own subgrid pixels and every
+                              visibility's phasor is seeded from FP64 (no recurrence) */
+  int32_t reserved;        /* 0 */
   int64_t workspace_bytes; /* device budget for the group images of one batch
                               (4 L^2 complex each); 0 = 2 GiB */
 } aidg_geometry;
+enum { AIDG_DEGRID_AUTO = 0, AIDG_DEGRID_RECURRENCE = 1, AIDG_DEGRID_PER_VIS = 2, AIDG_DEGRID_DIRECT = 3 };
 
 /* One subgrid: the rectangular sub-table [t0, t0+nt) x [c0, c0+nc) of one
  * baseline's visibility table (Sec. 3.1), its integer centre cell, its w-layer
@@ -167,6 +185,9 @@ typedef struct {
   int64_t n_groups;        /* runs of subgrids with one w-layer and centre that share one
                               subgrid FFT; a centre holding more than 8x the mean
                               visibilities per centre is split into several */
+  int64_t n_subgrids_pervis; /* subgrids the degridder takes in its per-visibility form
+                              (geometry degrid_form) */
+  int64_t n_subgrids_direct; /* subgrids the degridder takes in its direct form */
 } aidg_plan_info;
 
 typedef struct aidg_plan aidg_plan;

@@ -21,6 +21,7 @@ AIDG_OK, AIDG_E_INVALID, AIDG_E_NOMEM, AIDG_E_DEVICE, AIDG_E_UNSUPPORTED, AIDG_E
 STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "NOMEM", 3: "DEVICE", 4: "UNSUPPORTED", 5: "RANGE", 6: "BUSY"}
 FP32, FP64 = 0, 1
 ATERM_ADJOINT, ATERM_INVERSE = 0, 1  # A-term of gridding: A^H (adjoint of degridding) or normalised A^-1
+DEGRID_AUTO, DEGRID_RECURRENCE, DEGRID_PER_VIS, DEGRID_DIRECT = 0, 1, 2, 3  # degridder form per subgrid
 
 # aidg_subgrid (64 bytes), see include/aidg.h
 SUBGRID_DTYPE = np.dtype([
@@ -43,7 +44,8 @@ class _Geometry(ctypes.Structure):
                 ("reseed_channels", ctypes.c_int32), ("strict_range", ctypes.c_int32),
                 ("max_subgrid_vis", ctypes.c_int32), ("center_lattice", ctypes.c_int32),
                 ("w_fold", ctypes.c_int32), ("aterm_mode", ctypes.c_int32),
-                ("stokes_i", ctypes.c_int32), ("workspace_bytes", ctypes.c_int64)]
+                ("stokes_i", ctypes.c_int32), ("degrid_form", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("workspace_bytes", ctypes.c_int64)]
 
 
 class _PlanInfo(ctypes.Structure):
@@ -53,14 +55,16 @@ class _PlanInfo(ctypes.Structure):
                 ("device_bytes", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
                 ("grid_bytes", ctypes.c_int64), ("vis_bytes", ctypes.c_int64),
                 ("n_batches", ctypes.c_int64), ("max_subgrid_vis", ctypes.c_int64),
-                ("n_groups", ctypes.c_int64)]
+                ("n_groups", ctypes.c_int64), ("n_subgrids_pervis", ctypes.c_int64),
+                ("n_subgrids_direct", ctypes.c_int64)]
 
 
 class _Footprint(ctypes.Structure):
     _fields_ = [("n_wlayers", ctypes.c_int32), ("n_pol", ctypes.c_int32), ("w_step", ctypes.c_double),
                 ("n_subgrids", ctypes.c_int64), ("n_excluded", ctypes.c_int64), ("grid_bytes", ctypes.c_int64),
                 ("vis_bytes", ctypes.c_int64), ("aterm_bytes", ctypes.c_int64), ("plan_bytes", ctypes.c_int64),
-                ("n_groups", ctypes.c_int64)]
+                ("n_groups", ctypes.c_int64), ("n_subgrids_pervis", ctypes.c_int64),
+                ("n_subgrids_direct", ctypes.c_int64)]
 
 
 KERNEL_CLASSES = ("grid_dft", "fft_add", "split_ifft", "degrid_dft", "zero_vis", "image_fft",
@@ -99,6 +103,7 @@ class Geometry:
     w_fold: int = 0
     aterm_mode: int = ATERM_ADJOINT
     stokes_i: int = 0
+    degrid_form: int = 0  # DEGRID_AUTO, DEGRID_RECURRENCE, DEGRID_PER_VIS or DEGRID_DIRECT
 
     @property
     def n_pol(self) -> int:
@@ -110,11 +115,11 @@ class Geometry:
                          self.pixel_scale, self.w_step, self.taper_beta, self.precision,
                          self.reseed_channels, self.strict_range, self.max_subgrid_vis,
                          self.center_lattice, self.w_fold, self.aterm_mode, self.stokes_i,
-                         self.workspace_bytes)
+                         self.degrid_form, 0, self.workspace_bytes)
 
 
 _lib = None
-ABI_VERSION = 7  # the structure layouts above follow include/aidg.h at this version
+ABI_VERSION = 8  # the structure layouts above follow include/aidg.h at this version
 
 
 def library() -> ctypes.CDLL:

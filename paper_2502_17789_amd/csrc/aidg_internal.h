@@ -35,13 +35,19 @@ struct alignas(16) SubgridDev {
   double dfc;                  // channel spacing / c (s/m * Hz ... i.e. 1/m) for the recurrence
   double w0;                   // layer w, wavelengths
   int32_t fold;                // 1: visibilities enter and leave conjugate-transposed
-  int32_t pad1, pad2, pad3;
+  int32_t kind;                // degridder form: kDegridRecur, kDegridDirect or kDegridPerVis
+  int32_t pad2, pad3;
 };
+// Degridder forms, chosen per subgrid by the plan (degrid_form).
+constexpr int32_t kDegridRecur = 0;   // lanes own pixels; phasors step along each row's channels
+constexpr int32_t kDegridDirect = 1;  // lanes own pixels; every visibility's phasor seeded directly
+constexpr int32_t kDegridPerVis = 2;  // lanes own visibilities
 static_assert(sizeof(SubgridDev) == 96, "SubgridDev layout");
 
 // Geometry after validation, with derived quantities.
 struct Geometry {
   int N, L, K, aterm_interval, precision, R, strict, max_sg_vis, lattice, fold, amode;
+  int degrid_form;  // AIDG_DEGRID_AUTO, AIDG_DEGRID_COOPERATIVE or AIDG_DEGRID_PER_VIS
   int npol;  // grid planes: 4, or 1 for Stokes-I grids
   double dl, fov, du, beta, w_step;
   int64_t workspace;
@@ -125,6 +131,13 @@ enum KernelClass {
   kImageFft = 5,      // image-level row FFTs (invert / predict)
   kImageWstack = 6    // image-level transposes and w-stacking passes
 };
+
+// Degridder form of a sub-table of nt rows and nc channels (kernels.hip), `uniform`
+// when its channels have a common spacing: the geometry's choice, or (automatic) the
+// form of least modelled cost.  The recurrence needs a common spacing (else the
+// direct form), and only sub-tables of at most the workgroup's lane count can take the
+// per-visibility form (else the recurrence).
+int32_t degrid_form(const Geometry& g, int nt, int nc, bool uniform);
 
 // Launch one kernel class over a group (kernels.hip).  max_nv: the largest
 // sub-table of the group (degridder LDS).  Returns a hipError_t as int.

@@ -56,6 +56,7 @@ hipStream_t release_stream(int device) {
 struct aidg_plan {
   Geometry g{};
   int n_st = 0, nbl = 0, nt = 0, nc = 0, n_int = 0, W = 1, max_nv = 1, device = 0;
+  int64_t n_pervis = 0, n_direct = 0;  // subgrids the degridder takes in these forms
   std::vector<aidg_subgrid> table;
   std::vector<double> w0;
   int64_t n_excluded = 0;
@@ -631,6 +632,9 @@ aidg_status aidg_plan_create(const aidg_geometry* geo, int32_t n_stations, int32
         if (std::fabs((freqs_hz[c] - freqs_hz[c - 1]) - df) > 1e-9 * std::fabs(df)) uniform = false;
       d.dfc = df * inv_c;
       d.R = uniform ? g.R : 1;
+      d.kind = degrid_form(g, s.nt, s.nc, uniform);
+      plan->n_pervis += d.kind == kDegridPerVis;
+      plan->n_direct += d.kind == kDegridDirect;
     }
     // inverse A-term mode: distinct (A_p plane, A_q plane) pairs with their visibility
     // counts, for the normalisation map
@@ -804,6 +808,8 @@ aidg_status aidg_plan_info_get(const aidg_plan* plan, aidg_plan_info* info) {
   info->n_batches = plan->batch_begin.empty() ? 0 : (int64_t)plan->batch_begin.size() - 1;
   info->n_groups = plan->grp_begin.empty() ? 0 : (int64_t)plan->grp_begin.size() - 1;
   info->max_subgrid_vis = plan->max_nv;
+  info->n_subgrids_pervis = plan->n_pervis;
+  info->n_subgrids_direct = plan->n_direct;
   return AIDG_OK;
 }
 
@@ -905,7 +911,9 @@ aidg_status aidg_footprint_estimate(const aidg_geometry* geo, int32_t n_stations
     if (N <= kMaxImageN) b += al(N * elem) + al(N * 8);
     if (g.amode) {
       const int64_t pairs = std::min<int64_t>(n_sg, (int64_t)n_int * n_baselines);
-      b += al(pairs * 8) + al(pairs * 8) + al(64 * L * L * 8) + al(L * L * 8);
+      // the normalisation map's partial sums: one chunk per about 64 pairs, at most 64
+      const int64_t chunks = std::max<int64_t>(1, std::min<int64_t>(64, (pairs + 63) / 64));
+      b += al(pairs * 8) + al(pairs * 8) + al(chunks * L * L * 8) + al(L * L * 8);
     }
     out->plan_bytes = b;
     return AIDG_OK;

@@ -52,42 +52,19 @@ __device__ __forceinline__ float2 phasor(double theta, float) {
   return phasor_quarter(t, (int)q);  // |theta| is bounded by the grid size in turns
 }
 
-// exp(2 pi i theta) for a phase given in quarter turns, theta4 = 4 theta, FP32 result:
-// the reduction theta4 = q + tau, |tau| <= 1/2 happens in FP64 and tau is rounded once
-// to FP32; sin and cos of (pi/2) tau are Taylor polynomials to degree 9 and 10
-// (truncation below 2e-9 for |tau| <= 1/2), evaluated in FP32 by Horner's rule, and the
-// result is rotated by q quarter turns.  Callers fold the factor 4 into their phase
-// coefficients, which saves the FP64 multiply of phasor().
-__device__ __forceinline__ float2 phasor4(double theta4) {
-  const double q = rint(theta4);
-  const float u = (float)(theta4 - q);
-  const int qi = (int)q;
-  const float u2 = u * u;
-  float s = fmaf(u2, 1.6044118478735975e-4f, -4.681754135318687e-3f);
-  s = fmaf(u2, s, 7.969262624616703e-2f);
-  s = fmaf(u2, s, -6.459640975062462e-1f);
-  s = fmaf(u2, s, 1.5707963267948966f);
-  s = s * u;
-  float c = fmaf(u2, -2.5202042373060596e-5f, 9.192602748394263e-4f);
-  c = fmaf(u2, c, -2.0863480763352957e-2f);
-  c = fmaf(u2, c, 2.53669507901048e-1f);
-  c = fmaf(u2, c, -1.2337005501361697f);
-  c = fmaf(u2, c, 1.0f);
-  const bool odd = qi & 1;
-  const float cc = odd ? s : c, ss = odd ? c : s;
-  const unsigned sign_c = ((unsigned)(qi + 1) << 30) & 0x80000000u, sign_s = ((unsigned)qi << 30) & 0x80000000u;
-  return {__uint_as_float(__float_as_uint(cc) ^ sign_c), __uint_as_float(__float_as_uint(ss) ^ sign_s)};
+// exp(2 pi i theta) for a phase theta in turns, FP32 result: theta = q + t with q the
+// nearest integer and |t| <= 1/2, exact in FP64; t is rounded once to FP32 and the sine
+// and cosine of 2 pi t come from the transcendental unit (v_sin_f32 / v_cos_f32 take
+// their argument in turns).  On gfx950 their absolute error over |t| <= 1/2 is at most
+// 1.3e-7 (rms 3.5e-8), the size of FP32 rounding of a unit value, and the pair costs
+// about as much as two FMA where a Taylor form (phasor_quarter) takes about 16 VALU
+// operations.
+__device__ __forceinline__ float2 phasor_turns(double theta) {
+  const float t = (float)(theta - rint(theta));
+  return {__builtin_amdgcn_cosf(t), __builtin_amdgcn_sinf(t)};
 }
 
-// FP64 variant of phasor4: the plain FP64 phasor of theta4 / 4.
-__device__ __forceinline__ double2 phasor4_f64(double theta4) {
-  const double r = 0.25 * theta4 - rint(0.25 * theta4);
-  double s, c;
-  sincospi(2.0 * r, &s, &c);
-  return {c, s};
-}
-
-// FP64 variant: reduction to [-1/2, 1/2] and the device library's sincospi.
+// FP64 phasor of a phase in turns: reduction to [-1/2, 1/2] and the device library's sincospi.
 __device__ __forceinline__ double2 phasor(double theta, double) {
   const double r = theta - rint(theta);
   double s, c;

@@ -190,10 +190,9 @@ __device__ __forceinline__ Slot resolve(const Group& g, int64_t slot) {
 
 // ------------------------------------------------------------------ gridder
 
-// Phasors of the gridder: exp(+2 pi i theta) with the phase given in quarter turns,
-// 4 theta.
-__device__ __forceinline__ float2 gphasor(double theta4, float) { return phasor4(theta4); }
-__device__ __forceinline__ double2 gphasor(double theta4, double) { return phasor4_f64(theta4); }
+// Phasors of the (de)gridder: exp(2 pi i theta) with the phase theta in turns.
+__device__ __forceinline__ float2 tphasor(double theta, float) { return phasor_turns(theta); }
+__device__ __forceinline__ double2 tphasor(double theta, double) { return phasor(theta, 0.0); }
 
 template <int L, typename R>
 __global__ __launch_bounds__(kThreads) void grid_dft(const Group g) {
@@ -260,11 +259,10 @@ __global__ __launch_bounds__(kThreads) void grid_dft(const Group g) {
       const double um = uvw[0], vm = uvw[1], wm = uvw[2];
       const V4* vrow = vlds + 2 * t * s.nc;
       V2 st[kPix];  // per-channel step exp(2 pi i dfc (um l + vm m + wm n1))
-      // the phasors' phases in quarter turns: 4 (cu l + cv m + cw n1)
+      // the phasors' phases in turns: cu l + cv m + cw n1
       auto seed = [&](V2 (&ph)[kPix], double cu, double cv, double cw) {
-        const double ku = 4.0 * cu, kv = 4.0 * cv, kw = 4.0 * cw;
 #pragma unroll
-        for (int p = 0; p < kPix; ++p) ph[p] = gphasor(fma(ku, px[p].l, fma(kv, px[p].m, kw * px[p].n1)), R());
+        for (int p = 0; p < kPix; ++p) ph[p] = tphasor(fma(cu, px[p].l, fma(cv, px[p].m, cw * px[p].n1)), R());
       };
       seed(st, um * s.dfc, vm * s.dfc, wm * s.dfc);
       for (int j0 = 0; j0 < s.nc; j0 += s.R) {
@@ -616,10 +614,165 @@ __device__ __forceinline__ R reduce16(R (&a)[16], int ln, R* area) {
   return v + dpp<kDppXor2>(v);
 }
 
-// Phasors of the degridder: exp(-2 pi i theta) with theta given through quarter-turn
-// coefficients (the caller passes -4 theta).
-__device__ __forceinline__ float2 dphasor(double theta4, float) { return phasor4(theta4); }
-__device__ __forceinline__ double2 dphasor(double theta4, double) { return phasor4_f64(theta4); }
+
+// The degridder's prologue at one subgrid pixel: S' = T (-1)^(x+y) A_p S A_q^H of the
+// group image S (Sec. 3.3, A-term application; the taper table carries the
+// checkerboard), and what a phase needs of the pixel (its offsets from the centre and
+// n - 1).
+template <int L, typename R>
+__device__ __forceinline__ void corrected_pixel(const KernelArgs& a, const SubgridDev& s,
+                                                const typename C2<R>::T* img, int pix,
+                                                typename C2<R>::T (&sp)[4], SeedPixel& px) {
+  using V2 = typename C2<R>::T;
+  const int x = pix % L, y = pix / L;
+  const double l = (x - L / 2) * a.lstep, m = (y - L / 2) * a.lstep;
+  const double r2 = l * l + m * m;
+  px = {-r2 / (1.0 + sqrt(1.0 - r2)), (float)(x - L / 2), (float)(y - L / 2)};
+  const V2* At = reinterpret_cast<const V2*>(a.aterms);
+  const V2* Ap = At + ((int64_t)s.ap * L * L + pix) * 4;
+  const V2* Aq = At + ((int64_t)s.aq * L * L + pix) * 4;
+  const V2 a0 = Ap[0], a1 = Ap[1], a2 = Ap[2], a3 = Ap[3];
+  V2 b0 = Aq[0], b1 = Aq[1], b2 = Aq[2], b3 = Aq[3];
+  b0.y = -b0.y; b1.y = -b1.y; b2.y = -b2.y; b3.y = -b3.y;  // conj
+  const V2 s0 = img[0 * L * L + pix], s1 = img[1 * L * L + pix];
+  const V2 s2 = img[2 * L * L + pix], s3 = img[3 * L * L + pix];
+  const V2 t0 = cmul<R>(a0, s0) + cmul<R>(a1, s2);
+  const V2 t1 = cmul<R>(a0, s1) + cmul<R>(a1, s3);
+  const V2 t2 = cmul<R>(a2, s0) + cmul<R>(a3, s2);
+  const V2 t3 = cmul<R>(a2, s1) + cmul<R>(a3, s3);
+  const R w = reinterpret_cast<const R*>(a.taper)[pix];
+  // A_q^H = [[conj b0, conj b2], [conj b1, conj b3]]
+  sp[0] = (cmul<R>(t0, b0) + cmul<R>(t1, b1)) * w;
+  sp[1] = (cmul<R>(t0, b2) + cmul<R>(t1, b3)) * w;
+  sp[2] = (cmul<R>(t2, b0) + cmul<R>(t3, b1)) * w;
+  sp[3] = (cmul<R>(t2, b2) + cmul<R>(t3, b3)) * w;
+}
+
+// Output element i (= 8 x channel offset + component) of a degridded row: a folded
+// sub-table returns the conjugate transpose of its prediction at -uvw.
+template <typename R>
+__device__ __forceinline__ void store_vis(R* vrow, int i, R v, bool fold, bool add) {
+  int d = i;
+  if (fold) {
+    const int comp = i & 7, pol = comp >> 1;
+    d = i - comp + (pol == 1 ? 2 : pol == 2 ? 1 : pol) * 2 + (comp & 1);
+    if (comp & 1) v = -v;
+  }
+  vrow[d] = add ? vrow[d] + v : v;
+}
+
+// Pixels per LDS chunk of the per-visibility form: the corrected image (4 values) and
+// the pixel record of each, within the LDS the cooperative form takes, a multiple of
+// the workgroup size.
+template <int L, typename R>
+constexpr int pervis_chunk() {
+  using D = DegridTune<L, R>;
+  constexpr int per_pixel = (int)(4 * sizeof(typename C2<R>::T) + sizeof(SeedPixel));
+  constexpr int n = (int)(degrid_lds_bytes<L, R>() / per_pixel) / D::NT * D::NT;
+  return n < L * L ? n : L * L;
+}
+
+// Per-visibility form of the degridder, for sparse subgrids (Sec. 3.2, Degridder: the
+// kernel design chosen per subgrid by its occupancy).  The cooperative form below puts
+// pixels on lanes, so each row of a sub-table costs two FP64-seeded phasors per pixel
+// and each visibility a cross-lane reduction; with a few channels per row those fixed
+// costs dominate.  Here lanes own visibilities: the nv = nt nc visibilities of the
+// subgrid (nv <= NT, which the plan guarantees for the subgrids it marks) take
+// G = floor(NT / nv) lanes each, lane (k, g) summing over the pixels g, g + G, ... of
+// every LDS chunk of the corrected image.  Each (visibility, pixel) phase is formed in
+// FP64 from the pixel's offsets and n - 1, reduced to a turn and turned into a phasor
+// by the transcendental unit (no recurrence, so no seeds).  The G partial sums of a
+// visibility meet in LDS and are added in slice order, so the result does not depend
+// on timing.
+template <int L, typename R>
+__device__ __forceinline__ void degrid_pervis(const KernelArgs& a, const SubgridDev& s,
+                                              const typename C2<R>::T* img, R* vis,
+                                              unsigned char* smem) {
+  using V2 = typename C2<R>::T;
+  constexpr int NT = DegridTune<L, R>::NT, CHV = pervis_chunk<L, R>();
+  static_assert(CHV >= NT && CHV % NT == 0 && (L * L) % NT == 0, "per-visibility chunks");
+  static_assert(NT * 8 * sizeof(R) <= degrid_lds_bytes<L, R>(), "partial sums fit the LDS");
+  V2* simg = reinterpret_cast<V2*>(smem);                              // [CHV][4]
+  SeedPixel* spx = reinterpret_cast<SeedPixel*>(smem + CHV * 4 * sizeof(V2));  // [CHV]
+  R* part = reinterpret_cast<R*>(smem);                                // [NT][8], after the chunks
+  const int nv = s.nt * s.nc;
+  const int G = NT / nv;
+  const int k = threadIdx.x / G, gi = threadIdx.x - k * G;
+  const bool active = k < nv;
+  const int t = active ? k / s.nc : 0, j = active ? k - t * s.nc : 0;
+  // phase of exp(-2 pi i phi) in turns: -(c_u dx lstep + c_v dy lstep + c_w n1)
+  double ku = 0, kv = 0, kw = 0;
+  if (active) {
+    const_view<double> uvw = as_const(a.uvw + 3 * (s.uvw0 + t));
+    const double fc = as_const(a.fc)[s.c0 + j];
+    const double u0 = (s.U0 - a.N / 2) * a.du, v0 = (s.V0 - a.N / 2) * a.du;
+    ku = -(uvw[0] * fc - u0) * a.lstep;
+    kv = -(uvw[1] * fc - v0) * a.lstep;
+    kw = -(uvw[2] * fc - s.w0);
+  }
+  R acc[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) acc[i] = 0;
+  for (int c0 = 0; c0 < L * L; c0 += CHV) {
+    const int n = min(CHV, L * L - c0);  // a multiple of NT (L^2 and CHV are)
+    __syncthreads();  // the previous chunk is no longer read
+    // all of a lane's pixels of the chunk at once, so that their loads overlap
+#pragma unroll
+    for (int r = 0; r < CHV / NT; ++r) {
+      const int i = r * NT + threadIdx.x;
+      if (r * NT < n) {
+        V2 sp[4];
+        corrected_pixel<L, R>(a, s, img, c0 + i, sp, spx[i]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) simg[4 * i + q] = sp[q];
+      }
+    }
+    __syncthreads();
+    if (active) {
+      // U pixels per step with independent phase chains; pixels past the chunk take
+      // the chunk's last pixel with a zero phasor
+      constexpr int U = 4;
+      for (int i = gi; i < n; i += U * G) {
+        SeedPixel px[U];
+        V2 sv[U][4];
+        R keep[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int ii = min(i + u * G, n - 1);
+          keep[u] = i + u * G < n ? R(1) : R(0);
+          px[u] = spx[ii];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) sv[u][q] = simg[4 * ii + q];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          V2 ph = tphasor(fma(ku, (double)px[u].dx, fma(kv, (double)px[u].dy, kw * px[u].n1)), R());
+          ph.x *= keep[u];
+          ph.y *= keep[u];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const V2 v = sv[u][q];
+            acc[2 * q] = fma(v.x, ph.x, acc[2 * q]);
+            acc[2 * q] = fma(-v.y, ph.y, acc[2 * q]);
+            acc[2 * q + 1] = fma(v.x, ph.y, acc[2 * q + 1]);
+            acc[2 * q + 1] = fma(v.y, ph.x, acc[2 * q + 1]);
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();  // the last chunk is no longer read: its LDS takes the partial sums
+#pragma unroll
+  for (int i = 0; i < 8; ++i) part[threadIdx.x * 8 + i] = acc[i];
+  __syncthreads();
+  for (int o = threadIdx.x; o < nv * 8; o += NT) {
+    const int kk = o >> 3, comp = o & 7;
+    R v = part[kk * G * 8 + comp];
+    for (int q = 1; q < G; ++q) v = v + part[(kk * G + q) * 8 + comp];
+    const int tt = kk / s.nc, jj = kk - tt * s.nc;
+    store_vis(vis + (s.vis0 + (int64_t)tt * a.nc_total + jj) * 8, comp, v, s.fold != 0, false);
+  }
+}
 
 template <int L, typename R>
 __global__ __launch_bounds__((DegridTune<L, R>::NT))
@@ -639,13 +792,15 @@ __attribute__((amdgpu_waves_per_eu(DegridTune<L, R>::W))) void degrid_dft(const 
   const SubgridDev& s = sl.s;
   const R* __restrict__ scratch = reinterpret_cast<const R*>(g.scratch);
   R* __restrict__ vis = reinterpret_cast<R*>(sl.out);
-  const V2* At = reinterpret_cast<const V2*>(a.aterms);
-  const R* taper = reinterpret_cast<const R*>(a.taper);
   const V2* img = reinterpret_cast<const V2*>(scratch) + sl.img_slot * 4 * L * L;
+  if (s.kind == kDegridPerVis) {
+    degrid_pervis<L, R>(a, s, img, vis, smem_raw);
+    return;
+  }
   const double u0 = (s.U0 - a.N / 2) * a.du, v0 = (s.V0 - a.N / 2) * a.du;
-  // channels per FP32 recurrence run: even (runs start at even channel offsets); 1 means
-  // every channel is seeded (irregular channel spacing)
-  const int Rs = s.R <= 1 ? 1 : (s.R & ~1);
+  // channels per FP32 recurrence run: even (runs start at even channel offsets; a
+  // sub-table without a common channel spacing takes the direct form)
+  const int Rs = s.R & ~1;
   // the value this lane owns after reduce16: channel offset (0 or 1) and component
   const int vidx = 4 * (ln >> 4) + ((ln & 15) >> 2);
   const bool owner = (ln & 3) == 0;
@@ -657,32 +812,11 @@ __attribute__((amdgpu_waves_per_eu(DegridTune<L, R>::W))) void degrid_dft(const 
 #pragma unroll
     for (int p = 0; p < P; ++p) {
       const int pix = chunk * CH + p * NT + threadIdx.x;
-      const int x = pix % L, y = pix / L;
-      const double l = (x - L / 2) * a.lstep, m = (y - L / 2) * a.lstep;
-      const double r2 = l * l + m * m;
-      pxt[p * NT + threadIdx.x] = {-r2 / (1.0 + sqrt(1.0 - r2)), (float)(x - L / 2), (float)(y - L / 2)};
-      // prologue: S' = T (-1)^(x+y) A_p S A_q^H
-      const V2* Ap = At + ((int64_t)s.ap * L * L + pix) * 4;
-      const V2* Aq = At + ((int64_t)s.aq * L * L + pix) * 4;
-      const V2 a0 = Ap[0], a1 = Ap[1], a2 = Ap[2], a3 = Ap[3];
-      V2 b0 = Aq[0], b1 = Aq[1], b2 = Aq[2], b3 = Aq[3];
-      b0.y = -b0.y; b1.y = -b1.y; b2.y = -b2.y; b3.y = -b3.y;  // conj
-      const V2 s0 = img[0 * L * L + pix], s1 = img[1 * L * L + pix];
-      const V2 s2 = img[2 * L * L + pix], s3 = img[3 * L * L + pix];
-      const V2 t0 = cmul<R>(a0, s0) + cmul<R>(a1, s2);
-      const V2 t1 = cmul<R>(a0, s1) + cmul<R>(a1, s3);
-      const V2 t2 = cmul<R>(a2, s0) + cmul<R>(a3, s2);
-      const V2 t3 = cmul<R>(a2, s1) + cmul<R>(a3, s3);
-      const R w = taper[pix];
-      // A_q^H = [[conj b0, conj b2], [conj b1, conj b3]]
-      sp[p][0] = (cmul<R>(t0, b0) + cmul<R>(t1, b1)) * w;
-      sp[p][1] = (cmul<R>(t0, b2) + cmul<R>(t1, b3)) * w;
-      sp[p][2] = (cmul<R>(t2, b0) + cmul<R>(t3, b1)) * w;
-      sp[p][3] = (cmul<R>(t2, b2) + cmul<R>(t3, b3)) * w;
+      corrected_pixel<L, R>(a, s, img, pix, sp[p], pxt[p * NT + threadIdx.x]);
     }
-    // -4 (c_u dx lstep + c_v dy lstep + c_w n1): the phase of exp(-2 pi i phi) in quarter turns
+    // -(c_u dx lstep + c_v dy lstep + c_w n1): the phase of exp(-2 pi i phi) in turns
     auto seed = [&](V2 (&ph)[P], double cu, double cv, double cw) {
-      const double ku = -4.0 * cu * a.lstep, kv = -4.0 * cv * a.lstep, kw = -4.0 * cw;
+      const double ku = -cu * a.lstep, kv = -cv * a.lstep, kw = -cw;
 #pragma unroll
       for (int p = 0; p < P; ++p) {
         // an opaque index keeps the compiler from hoisting the load and conversions out
@@ -690,98 +824,111 @@ __attribute__((amdgpu_waves_per_eu(DegridTune<L, R>::W))) void degrid_dft(const 
         int e = p * NT + threadIdx.x;
         asm volatile("" : "+v"(e));
         const SeedPixel q = pxt[e];
-        ph[p] = dphasor(fma(ku, (double)q.dx, fma(kv, (double)q.dy, kw * q.n1)), R());
+        ph[p] = tphasor(fma(ku, (double)q.dx, fma(kv, (double)q.dy, kw * q.n1)), R());
       }
     };
+    // Partial sums of two visibilities over the lane's pixels, S'_q ph0 and S'_q ph1
+    // (16 values), reduced across the wave: the lane's share of the pair (see reduce16).
+    auto pair_value = [&](const V2 (&ph0)[P], const V2 (&ph1)[P]) -> R {
+      R part[16];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        part[2 * q] = sp[0][q].x * ph0[0].x - sp[0][q].y * ph0[0].y;
+        part[2 * q + 1] = sp[0][q].x * ph0[0].y + sp[0][q].y * ph0[0].x;
+        part[8 + 2 * q] = sp[0][q].x * ph1[0].x - sp[0][q].y * ph1[0].y;
+        part[8 + 2 * q + 1] = sp[0][q].x * ph1[0].y + sp[0][q].y * ph1[0].x;
+      }
+#pragma unroll
+      for (int p = 1; p < P; ++p) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          part[2 * q] = fma(sp[p][q].x, ph0[p].x, part[2 * q]);
+          part[2 * q] = fma(-sp[p][q].y, ph0[p].y, part[2 * q]);
+          part[2 * q + 1] = fma(sp[p][q].x, ph0[p].y, part[2 * q + 1]);
+          part[2 * q + 1] = fma(sp[p][q].y, ph0[p].x, part[2 * q + 1]);
+          part[8 + 2 * q] = fma(sp[p][q].x, ph1[p].x, part[8 + 2 * q]);
+          part[8 + 2 * q] = fma(-sp[p][q].y, ph1[p].y, part[8 + 2 * q]);
+          part[8 + 2 * q + 1] = fma(sp[p][q].x, ph1[p].y, part[8 + 2 * q + 1]);
+          part[8 + 2 * q + 1] = fma(sp[p][q].y, ph1[p].x, part[8 + 2 * q + 1]);
+        }
+      }
+      return reduce16<R>(part, ln, area);
+    };
+    // The waves' values of a block of up to kChanBlock visibilities (staged in `stage`),
+    // summed in wave order and added to the output (assigned by the first pixel chunk);
+    // each output element has one owner thread, the same in every chunk.  out(k) is the
+    // output row of the block's visibility k.
+    auto flush_block = [&](int n_in_block, auto out) {
+      __syncthreads();
+      const R* sb = stage + buf * NW * kChanBlock * 8;
+      for (int i = threadIdx.x; i < n_in_block * 8; i += NT) {
+        R v = sb[i];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) v = v + sb[w * kChanBlock * 8 + i];
+        store_vis(out(i >> 3), i & 7, v, s.fold != 0, chunk != 0);
+      }
+      buf ^= 1;
+    };
+    if (s.kind == kDegridDirect) {
+      // Direct form (short rows, or channels without a common spacing): the nv = nt nc
+      // visibilities in row-major order, two per step, each with its own FP64-seeded
+      // phasor: no per-row step seed and no padding of odd rows
+      const int nv = s.nt * s.nc;
+      auto direct = [&](V2 (&ph)[P], int k) {
+        const int t = k / s.nc, j = k - t * s.nc;
+        const_view<double> uvw = as_const(a.uvw + 3 * (s.uvw0 + t));
+        const double fc = as_const(a.fc)[s.c0 + j];
+        seed(ph, uvw[0] * fc - u0, uvw[1] * fc - v0, uvw[2] * fc - s.w0);
+      };
+      for (int kb0 = 0; kb0 < nv; kb0 += kChanBlock) {
+        const int kbn = min(kChanBlock, nv - kb0);
+        R* stg = stage + (buf * NW + wave) * kChanBlock * 8;
+        for (int k = kb0; k < kb0 + kbn; k += 2) {
+          V2 ph0[P], ph1[P];
+          direct(ph0, k);
+          direct(ph1, min(k + 1, nv - 1));  // an odd last visibility repeats, dropped
+          const R val = pair_value(ph0, ph1);
+          const int kc = k - kb0 + (vidx >> 3);
+          if (owner && k + (vidx >> 3) < nv) stg[kc * 8 + (vidx & 7)] = val;
+        }
+        flush_block(kbn, [&](int kc) {
+          const int k = kb0 + kc, t = k / s.nc, j = k - t * s.nc;
+          return vis + (s.vis0 + (int64_t)t * a.nc_total + j) * 8;
+        });
+      }
+      continue;
+    }
+    // Recurrence form: per row, the phasor steps along the channels by
+    // exp(-2 pi i dfc (um l + vm m + wm n1)) and is re-seeded from FP64 every Rs
+    // channels; two channels per step (a row of odd length ends on a second channel
+    // whose result is dropped)
     for (int t = 0; t < s.nt; ++t) {
       const_view<double> uvw = as_const(a.uvw + 3 * (s.uvw0 + t));
       const double um = uvw[0], vm = uvw[1], wm = uvw[2];
-      // per-channel step exp(-2 pi i dfc (um l + vm m + wm n1)) and the running phasor
       V2 st[P], cur[P];
       seed(st, um * s.dfc, vm * s.dfc, wm * s.dfc);
-      auto origin = [&](V2 (&ph)[P], int j) {
-        const double fc = as_const(a.fc)[s.c0 + j];
-        seed(ph, um * fc - u0, vm * fc - v0, wm * fc - s.w0);
-      };
-      // The row's channels in blocks of kChanBlock, two per step (a row of odd length
-      // ends on a second channel whose result is dropped).  IRREGULAR: every channel is
-      // seeded from FP64 (irregular channel spacing); otherwise the phasor steps along
-      // the channels and is re-seeded every Rs of them.  One loop per case keeps the
-      // phasor registers in place (no copies between the two ways of forming them).
-      auto channels = [&](auto irregular, int cb0, int cbn, int& since, R* stg) {
-        for (int j = cb0; j < cb0 + cbn; j += 2) {
-          V2 nxt[P];
-          if constexpr (decltype(irregular)::value) {
-            origin(cur, j);
-            origin(nxt, min(j + 1, s.nc - 1));
-          } else {
-            if (since >= Rs) {
-              origin(cur, j);
-              since = 0;
-            }
-            since += 2;
-#pragma unroll
-            for (int p = 0; p < P; ++p) nxt[p] = cmul<R>(cur[p], st[p]);
-          }
-          R part[16];
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            part[2 * q] = sp[0][q].x * cur[0].x - sp[0][q].y * cur[0].y;
-            part[2 * q + 1] = sp[0][q].x * cur[0].y + sp[0][q].y * cur[0].x;
-            part[8 + 2 * q] = sp[0][q].x * nxt[0].x - sp[0][q].y * nxt[0].y;
-            part[8 + 2 * q + 1] = sp[0][q].x * nxt[0].y + sp[0][q].y * nxt[0].x;
-          }
-#pragma unroll
-          for (int p = 1; p < P; ++p) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              part[2 * q] = fma(sp[p][q].x, cur[p].x, part[2 * q]);
-              part[2 * q] = fma(-sp[p][q].y, cur[p].y, part[2 * q]);
-              part[2 * q + 1] = fma(sp[p][q].x, cur[p].y, part[2 * q + 1]);
-              part[2 * q + 1] = fma(sp[p][q].y, cur[p].x, part[2 * q + 1]);
-              part[8 + 2 * q] = fma(sp[p][q].x, nxt[p].x, part[8 + 2 * q]);
-              part[8 + 2 * q] = fma(-sp[p][q].y, nxt[p].y, part[8 + 2 * q]);
-              part[8 + 2 * q + 1] = fma(sp[p][q].x, nxt[p].y, part[8 + 2 * q + 1]);
-              part[8 + 2 * q + 1] = fma(sp[p][q].y, nxt[p].x, part[8 + 2 * q + 1]);
-            }
-          }
-          if constexpr (!decltype(irregular)::value) {
-#pragma unroll
-            for (int p = 0; p < P; ++p) cur[p] = cmul<R>(nxt[p], st[p]);
-          }
-          const R val = reduce16<R>(part, ln, area);
-          const int jc = j - cb0 + (vidx >> 3);
-          if (owner && j + (vidx >> 3) < s.nc) stg[jc * 8 + (vidx & 7)] = val;
-        }
-      };
       int since = Rs;  // channels since the last FP64 seed: seed at the row's first channel
       for (int cb0 = 0; cb0 < s.nc; cb0 += kChanBlock) {
         const int cbn = min(kChanBlock, s.nc - cb0);
         R* stg = stage + (buf * NW + wave) * kChanBlock * 8;
-        if (Rs == 1)
-          channels(std::true_type(), cb0, cbn, since, stg);
-        else
-          channels(std::false_type(), cb0, cbn, since, stg);
-        __syncthreads();
-        // the waves' values of the block, summed in wave order and added to the output
-        // (assigned by the first pixel chunk); each output element has one owner thread,
-        // the same in every chunk
-        const R* sb = stage + buf * NW * kChanBlock * 8;
-        R* vrow = vis + (s.vis0 + (int64_t)t * a.nc_total + cb0) * 8;
-        for (int i = threadIdx.x; i < cbn * 8; i += NT) {
-          R v = sb[i];
-#pragma unroll
-          for (int w = 1; w < NW; ++w) v = v + sb[w * kChanBlock * 8 + i];
-          int d = i;
-          if (s.fold) {
-            // folded sub-table: the conjugate transpose of the prediction at -uvw
-            const int comp = i & 7, pol = comp >> 1;
-            d = i - comp + (pol == 1 ? 2 : pol == 2 ? 1 : pol) * 2 + (comp & 1);
-            if (comp & 1) v = -v;
+        for (int j = cb0; j < cb0 + cbn; j += 2) {
+          if (since >= Rs) {
+            const double fc = as_const(a.fc)[s.c0 + j];
+            seed(cur, um * fc - u0, vm * fc - v0, wm * fc - s.w0);
+            since = 0;
           }
-          vrow[d] = chunk == 0 ? v : vrow[d] + v;
+          since += 2;
+          V2 nxt[P];
+#pragma unroll
+          for (int p = 0; p < P; ++p) nxt[p] = cmul<R>(cur[p], st[p]);
+          const R val = pair_value(cur, nxt);
+#pragma unroll
+          for (int p = 0; p < P; ++p) cur[p] = cmul<R>(nxt[p], st[p]);
+          const int jc = j - cb0 + (vidx >> 3);
+          if (owner && j + (vidx >> 3) < s.nc) stg[jc * 8 + (vidx & 7)] = val;
         }
-        buf ^= 1;
+        R* vrow = vis + (s.vis0 + (int64_t)t * a.nc_total + cb0) * 8;
+        flush_block(cbn, [&](int jc) { return vrow + jc * 8; });
       }
     }
   }
@@ -820,6 +967,41 @@ int launch_one(KernelClass k, const Group& g, hipStream_t st, int max_nv) {
 }
 
 }  // namespace
+
+namespace {
+template <typename R>
+int degrid_lanes(int L) {
+  return L == 32 ? DegridTune<32, R>::NT : L == 64 ? DegridTune<64, R>::NT : DegridTune<96, R>::NT;
+}
+}  // namespace
+
+int32_t degrid_form(const Geometry& g, int nt, int nc, bool uniform) {
+  const int nv = nt * nc;
+  const int lanes = g.precision == AIDG_FP32 ? degrid_lanes<float>(g.L) : degrid_lanes<double>(g.L);
+  const bool pv_ok = nv >= 1 && nv <= lanes;
+  if (!uniform && g.degrid_form != AIDG_DEGRID_PER_VIS) return kDegridDirect;
+  switch (g.degrid_form) {
+    case AIDG_DEGRID_RECURRENCE: return kDegridRecur;
+    case AIDG_DEGRID_DIRECT: return kDegridDirect;
+    case AIDG_DEGRID_PER_VIS: return pv_ok ? kDegridPerVis : uniform ? kDegridRecur : kDegridDirect;
+    default: break;
+  }
+  // Automatic: the recurrence or the direct form, whichever has the smaller modelled
+  // cost per subgrid pixel, in units of one visibility of the recurrence (16 FMA, the
+  // phasor step and a share of the reduction).  The recurrence pays per row two seeded
+  // phasors and the block bookkeeping (kRow) and pads odd rows to even; the direct form
+  // pays one seeded phasor per visibility (kDirect) and pads an odd sub-table.  Both
+  // constants are fits to the degridder's times on the MWA-like observation with every
+  // k-th channel kept (k = 1 ... 96, L = 32, 64, 96): a row costs about two
+  // visibilities, a directly seeded visibility 1.9 to 2.0.  So rows of one channel take
+  // the direct form at about half the cost, rows of two or three channels break even
+  // and longer rows keep the recurrence.  The per-visibility form measured slower than
+  // the direct form at every occupancy and is never chosen automatically.
+  constexpr double kRow = 2.0, kDirect = 1.95;
+  const double recur = (double)nt * ((nc + (nc & 1)) + kRow);
+  const double direct = kDirect * (nv + (nv & 1));
+  return direct < recur ? kDegridDirect : kDegridRecur;
+}
 
 int launch_group(KernelClass k, int L, int precision, const Group& g, void* stream, int max_nv) {
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);

@@ -88,6 +88,11 @@ aidg_status validate_geometry(const aidg_geometry* g, Geometry* o, std::string* 
     return AIDG_E_INVALID;
   }
   o->npol = g->stokes_i ? 1 : 4;
+  if (g->degrid_form < AIDG_DEGRID_AUTO || g->degrid_form > AIDG_DEGRID_DIRECT || g->reserved != 0) {
+    *err = "degrid_form must be 0 (automatic), 1 (recurrence), 2 (per visibility) or 3 (direct), reserved 0";
+    return AIDG_E_INVALID;
+  }
+  o->degrid_form = g->degrid_form;
   if (g->center_lattice > 0) {
     o->lattice = g->center_lattice;
   } else {
