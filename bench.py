@@ -81,7 +81,8 @@ def measured_traffic(kernel: str):
 def summarize_traffic(copy_fetch: str, copy_write: str, run_fetch: str, run_write: str, trace: str, out: str):
     """HBM bytes per launch of every kernel of a counter run, from rocprofv3 CSV output
     directories (FETCH_SIZE and WRITE_SIZE passes of the copy probe and of the run, and
-    a --kernel-trace --stats run of the same command for the launch times), scaled by
+    a --kernel-trace --stats run of the same command for the launch times, as CSV or as
+    its SQLite database), scaled by
     what the counters read for the 1 GiB device-to-device copy.  Writes the JSON that
     measured_traffic() reads, keyed by the library's source hash."""
     import csv
@@ -97,7 +98,7 @@ def summarize_traffic(copy_fetch: str, copy_write: str, run_fetch: str, run_writ
         return tot, n
 
     def short(name):
-        for k in ("grid_dft", "fft_add", "split_ifft", "degrid_dft", "copyBuffer"):
+        for k in ("degrid_dft", "grid_dft", "fft_add", "split_ifft", "copyBuffer"):
             if k in name:
                 return k
         return None
@@ -117,6 +118,12 @@ def summarize_traffic(copy_fetch: str, copy_write: str, run_fetch: str, run_writ
             k = short(row["Name"])
             if k:
                 ms[k] = float(row["AverageNs"]) / 1e6
+    for f in glob.glob(os.path.join(trace, "**", "*.db"), recursive=True):
+        import sqlite3   # rocprofv3's default output: its top_kernels view holds microseconds
+        for name, avg_us in sqlite3.connect(f).execute("select name, average from top_kernels"):
+            k = short(name)
+            if k:
+                ms[k] = float(avg_us) / 1e3
     rec = {"library_sha256": library_source_hash(), "copy_probe_bytes": copy_bytes,
            "fetch_scale": fetch_scale, "write_scale": write_scale, "kernels": {}}
     for name, v in rf.items():

@@ -20,6 +20,16 @@ __device__ __forceinline__ typename C2<R>::T cmul(typename C2<R>::T a, typename 
   return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
 }
 
+// (c, s) = (cos, sin) of an angle, rotated by qi quarter turns: swap for odd qi, then
+// flip the sign bits (cos is negative for qi = 1, 2 mod 4 and sin for qi = 2, 3: bit 1
+// of qi + 1 and of qi).
+__device__ __forceinline__ float2 rotate_quarter(float c, float s, int qi) {
+  const bool odd = qi & 1;
+  const float cc = odd ? s : c, ss = odd ? c : s;
+  const unsigned sign_c = ((unsigned)(qi + 1) << 30) & 0x80000000u, sign_s = ((unsigned)qi << 30) & 0x80000000u;
+  return {__uint_as_float(__float_as_uint(cc) ^ sign_c), __uint_as_float(__float_as_uint(ss) ^ sign_s)};
+}
+
 // exp(2 pi i (t + qi / 4)) for |t| <= 1/8 turn, FP32: sin/cos(2 pi t) from their
 // Taylor series to degree 9 and 10 (truncation < 2e-9 for |2 pi t| <= pi/4),
 // evaluated by Horner in FP32, then a rotation by qi quarter turns.
@@ -35,12 +45,7 @@ __device__ __forceinline__ float2 phasor_quarter(float t, int qi) {
   c = fmaf(t2, c, 64.93939402266828f);
   c = fmaf(t2, c, -19.739208802178716f);
   c = fmaf(t2, c, 1.0f);
-  // rotate by qi quarter turns: swap for odd qi, then flip the sign bits (cos is
-  // negative for qi = 1, 2 mod 4 and sin for qi = 2, 3: bit 1 of qi + 1 and of qi)
-  const bool odd = qi & 1;
-  const float cc = odd ? s : c, ss = odd ? c : s;
-  const unsigned sign_c = ((unsigned)(qi + 1) << 30) & 0x80000000u, sign_s = ((unsigned)qi << 30) & 0x80000000u;
-  return {__uint_as_float(__float_as_uint(cc) ^ sign_c), __uint_as_float(__float_as_uint(ss) ^ sign_s)};
+  return rotate_quarter(c, s, qi);
 }
 
 // exp(2 pi i theta) for a phase theta in turns, FP32 result.  The quarter-turn
@@ -52,17 +57,31 @@ __device__ __forceinline__ float2 phasor(double theta, float) {
   return phasor_quarter(t, (int)q);  // |theta| is bounded by the grid size in turns
 }
 
-// exp(2 pi i theta) for a phase theta in turns, FP32 result: theta = q + t with q the
-// nearest integer and |t| <= 1/2, exact in FP64; t is rounded once to FP32 and the sine
-// and cosine of 2 pi t come from the transcendental unit (v_sin_f32 / v_cos_f32 take
-// their argument in turns).  On gfx950 their absolute error over |t| <= 1/2 is at most
-// 1.3e-7 (rms 3.5e-8), the size of FP32 rounding of a unit value, and the pair costs
-// about as much as two FMA where a Taylor form (phasor_quarter) takes about 16 VALU
-// operations.
+// exp(2 pi i theta) for a phase theta in turns, FP32 result: theta = q/4 + t with q the
+// nearest integer to 4 theta and |t| <= 1/8, exact in FP64; t is rounded once to FP32
+// (2^-28 turn at most, 2.3e-8 rad: the reduction to a quarter rather than a whole turn
+// keeps this rounding 8x below that of a [-1/2, 1/2] argument), the transcendental unit's
+// v_cos_f32 / v_sin_f32 (which take their argument in turns) give cos and sin of 2 pi t,
+// and the result is rotated by q quarter turns.  On gfx950 the unit's absolute error is
+// at most 1.3e-7 (rms 3.5e-8, phase rms 2.3e-8 rad), the size of FP32 rounding of a unit
+// value; the whole phasor costs about 11 VALU operations where the Taylor form
+// (phasor_quarter) takes about 20.
 __device__ __forceinline__ float2 phasor_turns(double theta) {
-  const float t = (float)(theta - rint(theta));
-  return {__builtin_amdgcn_cosf(t), __builtin_amdgcn_sinf(t)};
+  const double q = rint(4.0 * theta);
+  const float t = (float)fma(q, -0.25, theta);
+  return rotate_quarter(__builtin_amdgcn_cosf(t), __builtin_amdgcn_sinf(t), (int)q);
 }
+
+// A phasor that is raised to powers (a recurrence step) scaled back to unit magnitude:
+// z (3 - |z|^2) / 2, the first Newton step of 1 / sqrt(|z|^2), exact to second order in
+// |z|^2 - 1 (about 1e-7 here).  The transcendental unit's sine and cosine leave
+// |z|^2 - 1 at -6.5e-8 on average (rms 8.6e-8), a bias that k steps of a recurrence
+// would multiply by k; after the correction the magnitude error is FP32 rounding only.
+__device__ __forceinline__ float2 unit_step(float2 z) {
+  const float f = fmaf(-0.5f, fmaf(z.x, z.x, z.y * z.y), 1.5f);
+  return {z.x * f, z.y * f};
+}
+__device__ __forceinline__ double2 unit_step(double2 z) { return z; }  // FP64: exact enough
 
 // FP64 phasor of a phase in turns: reduction to [-1/2, 1/2] and the device library's sincospi.
 __device__ __forceinline__ double2 phasor(double theta, double) {
