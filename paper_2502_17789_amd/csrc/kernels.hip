@@ -919,7 +919,12 @@ __attribute__((amdgpu_waves_per_eu(DegridTune<L, R>::W))) void degrid_dft(const 
       const double um = uvw[0], vm = uvw[1], wm = uvw[2];
       V2 st[P], cur[P];
       seed(st, um * s.dfc, vm * s.dfc, wm * s.dfc, std::true_type());
-      int since = Rs;  // channels since the last FP64 seed: seed at the row's first channel
+      // the row's first origin before its loop, so that no phasor value reaches the loop
+      // from an earlier row or chunk (the compiler would otherwise keep cur live, and
+      // spilled, across the whole chunk loop)
+      seed(cur, um * as_const(a.fc)[s.c0] - u0, vm * as_const(a.fc)[s.c0] - v0,
+           wm * as_const(a.fc)[s.c0] - s.w0, std::false_type());
+      int since = 0;  // channels since the last FP64 seed
       for (int cb0 = 0; cb0 < s.nc; cb0 += kChanBlock) {
         const int cbn = min(kChanBlock, s.nc - cb0);
         R* stg = stage + (buf * NW + wave) * kChanBlock * 8;
