@@ -21,15 +21,18 @@
 //   split_ifft one workgroup per (polarisation, group): copy the window times
 //              (-1)^(a+b) into LDS (splitter), inverse FFT, store the group image.
 //   degrid_dft one workgroup per subgrid; lanes own P pixels each and apply
-//              T (-1)^(x+y) A_p S A_q^H to the group image once per pixel chunk;
-//              phasors follow ph <- ph * step along the channels (re-seeded from
-//              FP64 every R), and for each group of 4 channels every lane forms its
-//              pixels' partial sums (32 floats); a wave-wide transpose-reduction
-//              (permlane32/permlane16 swaps, then in FP32 a per-wave LDS area, in
-//              FP64 DPP) leaves each lane pair with one reduced value, and waves
-//              combine through LDS atomics; the finished visibilities are written
-//              once (Eq. degridder).
-//
+//              T (-1)^(x+y) A_p S A_q^H to the group image once per pixel chunk.
+//              The plan picks one of three forms per subgrid (Sec. 3.2, Degridder:
+//              the design chosen by subgrid occupancy).  Recurrence: per row the
+//              phasor steps along the channels (re-seeded from FP64 every R);
+//              direct: every visibility's phasor seeded from FP64 (short rows);
+//              in both, for each pair of visibilities every lane forms its pixels'
+//              partial sums (16 floats) and a wave-wide transpose-reduction
+//              (permlane32/permlane16 swaps, a per-wave LDS area, DPP) leaves each lane
+//              with one finished value; the waves' values are staged in LDS and added
+//              to the output in wave order (deterministic, no atomics).  Per
+//              visibility: lanes own visibilities and walk the corrected image in LDS
+//              (Eq. degridder).
 // A Stokes-I plan (npol = 1) keeps one grid plane: grid_dft adds (XX + YY) / 2 of the
 // corrected image and fft_add transforms that plane only; split_ifft stores the group
 // image as I [[1, 0], [0, 1]], which degrid_dft reads like any other.
