@@ -76,36 +76,32 @@ __device__ __forceinline__ void grid_work(int64_t b, int64_t* slot, int* chunk) 
 __device__ __forceinline__ int64_t degrid_slot(int64_t b, int64_t n) {
   return b < (n & ~int64_t(63)) ? ((b & ~int64_t(63)) | ((b & 7) << 3) | ((b >> 3) & 7)) : b;
 }
-#ifndef GRID_PIX
-#define GRID_PIX 4  // compile-time tile parameter; 4 measured best (2 within noise)
-#endif
-constexpr int kPix = GRID_PIX;              // pixels per lane in the gridder
-constexpr int kChunk = kThreads * kPix;     // pixels per workgroup pass
+// Gridder tiling: pixels per lane (PIX; a workgroup pass covers kThreads PIX pixels) and
+// the waves per SIMD the register allocation aims at (W).
+template <typename R> struct GridTune;
+template <> struct GridTune<float> { static constexpr int PIX = 4, W = 3; };
+template <> struct GridTune<double> { static constexpr int PIX = 2, W = 2; };
 // Degridder tiling: NT threads per workgroup (one subgrid), P pixels per lane (NT P
 // divides L^2; more pixels amortise the cross-lane reduction per visibility over more
 // work) and the waves per SIMD the register allocation aims at (W).
 template <int L, typename R> struct DegridTune;
-template <> struct DegridTune<32, float> { static constexpr int NT = 128, P = 8, W = 3; };
-template <> struct DegridTune<64, float> { static constexpr int NT = 256, P = 8, W = 3; };
-template <> struct DegridTune<96, float> { static constexpr int NT = 256, P = 9, W = 3; };
+template <> struct DegridTune<32, float> { static constexpr int NT = 256, P = 4, W = 4; };
+template <> struct DegridTune<64, float> { static constexpr int NT = 256, P = 8, W = 2; };
+template <> struct DegridTune<96, float> { static constexpr int NT = 256, P = 6, W = 3; };
 template <int L> struct DegridTune<L, double> { static constexpr int NT = 256, P = 4, W = 2; };
 
-struct Pixel {
-  int pix, x, y;
-  double l, m, n1;
+// What a phasor seed needs of a subgrid pixel: its offsets from the centre and n - 1.
+struct alignas(16) SeedPixel {
+  double n1;     // n - 1
+  float dx, dy;  // x - L/2, y - L/2
 };
 
 template <int L>
-__device__ __forceinline__ Pixel pixel_at(int pix, double lstep) {
-  Pixel p;
-  p.pix = pix;
-  p.x = pix % L;
-  p.y = pix / L;
-  p.l = (p.x - L / 2) * lstep;
-  p.m = (p.y - L / 2) * lstep;
-  const double r2 = p.l * p.l + p.m * p.m;
-  p.n1 = -r2 / (1.0 + sqrt(1.0 - r2));
-  return p;
+__device__ __forceinline__ SeedPixel pixel_at(int pix, double lstep) {
+  const int x = pix % L, y = pix / L;
+  const double l = (x - L / 2) * lstep, m = (y - L / 2) * lstep;
+  const double r2 = l * l + m * m;
+  return {-r2 / (1.0 + sqrt(1.0 - r2)), (float)(x - L / 2), (float)(y - L / 2)};
 }
 
 // Values every lane of a wave holds identically, moved to scalar registers word
@@ -193,6 +189,20 @@ __device__ __forceinline__ Slot resolve(const Group& g, int64_t slot) {
 
 // ------------------------------------------------------------------ gridder
 
+// Channel runs of the phasor recurrence in a row of nc channels with re-seeding interval
+// R.  R = 1 (also what a sub-table without a common channel spacing carries): runs of
+// one channel.  Otherwise nr = ceil(nc / R') runs, R' = R rounded down to even, of M
+// channels each, M the smallest even length with nr M >= nc (so M <= R'); the last run
+// covers the rest.  A run [j0, je) with H = ceil((je - j0) / 2) pairs up its channels
+// symmetrically about its centre j0 + H - 1/2: channels j0 + H - 1 - k and j0 + H + k,
+// at -(k + 1/2) and +(k + 1/2) channel steps from it; a run of odd length ends on a
+// padding channel (j0 + 2 H - 1 = je), which takes no part.
+__device__ __forceinline__ int run_length(int nc, int R) {
+  if (R <= 1) return 1;
+  const int Rs = R & ~1, nr = (nc + Rs - 1) / Rs;
+  return 2 * ((nc + 2 * nr - 1) / (2 * nr));
+}
+
 // Phasors of the (de)gridder: exp(2 pi i theta) with the phase theta in turns.  A phase
 // origin (used once per block of channels) comes from the transcendental unit; a
 // recurrence step, which the channel recurrence raises to powers up to R, from the
@@ -206,9 +216,11 @@ __device__ __forceinline__ float2 sphasor(double theta, float) { return unit_ste
 __device__ __forceinline__ double2 sphasor(double theta, double) { return phasor(theta, 0.0); }
 
 template <int L, typename R>
-__global__ __launch_bounds__(kThreads) void grid_dft(const Group g) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(GridTune<R>::W)))
+void grid_dft(const Group g) {
   using V2 = typename C2<R>::T;
   using V4 = typename C4<R>::T;
+  constexpr int kPix = GridTune<R>::PIX, kChunk = kThreads * kPix;
   extern __shared__ unsigned char smem_raw[];
   V4* vlds = reinterpret_cast<V4*>(smem_raw);  // one subgrid's visibilities, 8 values each
   int64_t local;
@@ -238,23 +250,40 @@ __global__ __launch_bounds__(kThreads) void grid_dft(const Group g) {
     // across the subgrid loop, which would cost occupancy.
     int lane = threadIdx.x;
     asm volatile("" : "+v"(lane));
-    Pixel px[kPix];
+    SeedPixel px[kPix];
 #pragma unroll
     for (int p = 0; p < kPix; ++p) px[p] = pixel_at<L>(chunk * kChunk + p * kThreads + lane, a.lstep);
 
     // Stage the sub-table (rows of nc visibilities, coalesced) in LDS; every lane then
-    // reads each visibility by a broadcast LDS load into vector registers, so the
-    // accumulation FMAs take only VGPR operands and can dual-issue.
+    // reads each staged value by a broadcast LDS load into vector registers, so the
+    // accumulation FMAs take only VGPR operands and can dual-issue.  Channels pair up
+    // within the recurrence runs (run_length): a pair's low channel holds
+    // P = V_hi + V_lo and its high channel Q = i (V_hi - V_lo); the low channel of a run
+    // of odd length that has no partner keeps V_lo.
     const int nv = s.nt * s.nc;
+    const int M = run_length(s.nc, s.R);
     for (int i = threadIdx.x; i < 2 * nv; i += kThreads) {
       const int k = i >> 1, row = k / s.nc, c = k - row * s.nc;
-      const V4* src = reinterpret_cast<const V4*>(vis) + (s.vis0 + (int64_t)row * a.nc_total + c) * 2;
-      if (s.fold) {
-        // folded sub-table: stage V^H = [[conj XX, conj YX], [conj XY, conj YY]]
-        const V4 h0 = src[0], h1 = src[1];
-        vlds[i] = (i & 1) ? V4{h0.z, -h0.w, h1.z, -h1.w} : V4{h0.x, -h0.y, h1.x, -h1.y};
+      // half i & 1 of visibility (row, j): polarisations 2 (i & 1) and 2 (i & 1) + 1
+      auto fetch = [&](int j) -> V4 {
+        const V4* src = reinterpret_cast<const V4*>(vis) + (s.vis0 + (int64_t)row * a.nc_total + j) * 2;
+        if (s.fold) {
+          // folded sub-table: stage V^H = [[conj XX, conj YX], [conj XY, conj YY]]
+          const V4 h0 = src[0], h1 = src[1];
+          return (i & 1) ? V4{h0.z, -h0.w, h1.z, -h1.w} : V4{h0.x, -h0.y, h1.x, -h1.y};
+        }
+        return src[i & 1];
+      };
+      const int j0 = c / M * M, je = min(s.nc, j0 + M), Hr = (je - j0 + 1) / 2;
+      const int partner = j0 + 2 * Hr - 1 - (c - j0);
+      const V4 mine = fetch(c);
+      if (partner < je) {
+        const V4 other = fetch(partner);
+        const bool hi = c - j0 >= Hr;
+        const V4 vh = hi ? mine : other, vl = hi ? other : mine;
+        vlds[i] = hi ? V4{vl.y - vh.y, vh.x - vl.x, vl.w - vh.w, vh.z - vl.z} : vh + vl;
       } else {
-        vlds[i] = src[i & 1];
+        vlds[i] = mine;
       }
     }
     R acc[kPix][8];
@@ -264,84 +293,113 @@ __global__ __launch_bounds__(kThreads) void grid_dft(const Group g) {
       for (int i = 0; i < 8; ++i) acc[p][i] = 0;
     __syncthreads();
 
+    // Per row and run, with E(x) = exp(2 pi i x), d the per-channel phase step and
+    // e_k = E((k + 1/2) d): the run's channels H + k and H - 1 - k add
+    // V_hi e_k + V_lo conj(e_k) = P Re e_k + Q Im e_k (real multipliers: 16 FMA per
+    // pixel for two visibilities) to H_run, and e_k steps by E(d) outward from the
+    // centre (the phasor recurrence of Sec. 3.2, Gridder, in both directions at once).
+    // H_run times E(theta_c), the phasor at the run's centre frequency seeded from FP64,
+    // goes into the accumulator.
     const double u0 = (s.U0 - a.N / 2) * a.du, v0 = (s.V0 - a.N / 2) * a.du;
     for (int t = 0; t < s.nt; ++t) {
       const_view<double> uvw = as_const(a.uvw + 3 * (s.uvw0 + t));
       const double um = uvw[0], vm = uvw[1], wm = uvw[2];
       const V4* vrow = vlds + 2 * t * s.nc;
-      V2 st[kPix];  // per-channel step exp(2 pi i dfc (um l + vm m + wm n1))
       // the phasors' phases in turns: cu l + cv m + cw n1
       auto seed = [&](V2 (&ph)[kPix], double cu, double cv, double cw, auto step) {
+        const double ku = cu * a.lstep, kv = cv * a.lstep;
 #pragma unroll
         for (int p = 0; p < kPix; ++p) {
-          const double th = fma(cu, px[p].l, fma(cv, px[p].m, cw * px[p].n1));
+          const double th = fma(ku, (double)px[p].dx, fma(kv, (double)px[p].dy, cw * px[p].n1));
           ph[p] = decltype(step)::value ? sphasor(th, R()) : tphasor(th, R());
         }
       };
-      seed(st, um * s.dfc, vm * s.dfc, wm * s.dfc, std::true_type());
-      for (int j0 = 0; j0 < s.nc; j0 += s.R) {
-        const int jn = min(s.nc, j0 + s.R);
-        // Channels j0..jn-1 of the row contribute ph_{j0} * H with
-        // H = sum_k V_{j0+k} st^k, evaluated by Horner's rule from the last channel
-        // back (h <- h st + V_j: 4 FMA per polarisation, no phasor update), two
-        // channels per step; ph_{j0} is the FP64-seeded phasor of the block.  An even
-        // block starts with h = V_{jn-1} st + V_{jn-2} straight from the staged values,
-        // an odd one with h = V_{jn-1} (the only copies into per-pixel registers).
+      auto load = [&](int j, R (&vv)[8]) {
+        const V4 va = vrow[2 * j], vb = vrow[2 * j + 1];
+        vv[0] = va.x; vv[1] = va.y; vv[2] = va.z; vv[3] = va.w;
+        vv[4] = vb.x; vv[5] = vb.y; vv[6] = vb.z; vv[7] = vb.w;
+      };
+      V2 hs[kPix], st[kPix];  // E(d / 2) and E(d)
+      seed(hs, 0.5 * um * s.dfc, 0.5 * vm * s.dfc, 0.5 * wm * s.dfc, std::true_type());
+#pragma unroll
+      for (int p = 0; p < kPix; ++p) st[p] = unit_step(cmul<R>(hs[p], hs[p]));
+      for (int j0 = 0; j0 < s.nc; j0 += M) {
+        // a run of n channels: centre j0 + H - 1/2, n / 2 full pairs and, for odd n, the
+        // low channel j0 alone at the last step
+        const int n = min(s.nc, j0 + M) - j0, H = (n + 1) / 2, Hf = n / 2;
         V2 h[kPix][4];
-        auto load = [&](int j, R (&vv)[8]) {
-          const V4 va = vrow[2 * j], vb = vrow[2 * j + 1];
-          vv[0] = va.x; vv[1] = va.y; vv[2] = va.z; vv[3] = va.w;
-          vv[4] = vb.x; vv[5] = vb.y; vv[6] = vb.z; vv[7] = vb.w;
-        };
-        auto step = [&](int j) {
-          R vv[8];
-          load(j, vv);
+        // pair (j0 + H - 1 - k, j0 + H + k) with phasor e_k; `first` starts H_run
+        auto pair = [&](auto first, int k, const V2 (&e)[kPix]) {
+          R pv[8], qv[8];
+          load(j0 + H - 1 - k, pv);
+          load(j0 + H + k, qv);
 #pragma unroll
           for (int p = 0; p < kPix; ++p) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-              R re = fma(h[p][q].x, st[p].x, vv[2 * q]);
-              re = fma(-h[p][q].y, st[p].y, re);
-              R im = fma(h[p][q].x, st[p].y, vv[2 * q + 1]);
-              im = fma(h[p][q].y, st[p].x, im);
-              h[p][q] = V2{re, im};
+              if constexpr (decltype(first)::value) {
+                h[p][q].x = pv[2 * q] * e[p].x;
+                h[p][q].y = pv[2 * q + 1] * e[p].x;
+              } else {
+                h[p][q].x = fma(pv[2 * q], e[p].x, h[p][q].x);
+                h[p][q].y = fma(pv[2 * q + 1], e[p].x, h[p][q].y);
+              }
+              h[p][q].x = fma(qv[2 * q], e[p].y, h[p][q].x);
+              h[p][q].y = fma(qv[2 * q + 1], e[p].y, h[p][q].y);
             }
           }
         };
-        int j;
-        {
-          R vt[8];
-          load(jn - 1, vt);
-          if ((jn - j0) & 1) {
+        // the low channel j0 of a run of odd length alone: V_lo conj(e_k)
+        auto single = [&](auto first, const V2 (&e)[kPix]) {
+          R pv[8];
+          load(j0, pv);
 #pragma unroll
-            for (int p = 0; p < kPix; ++p)
+          for (int p = 0; p < kPix; ++p) {
 #pragma unroll
-              for (int q = 0; q < 4; ++q) h[p][q] = V2{vt[2 * q], vt[2 * q + 1]};
-            j = jn - 2;
-          } else {
-            R vv[8];
-            load(jn - 2, vv);
-#pragma unroll
-            for (int p = 0; p < kPix; ++p) {
-#pragma unroll
-              for (int q = 0; q < 4; ++q) {
-                R re = fma(vt[2 * q], st[p].x, vv[2 * q]);
-                re = fma(-vt[2 * q + 1], st[p].y, re);
-                R im = fma(vt[2 * q], st[p].y, vv[2 * q + 1]);
-                im = fma(vt[2 * q + 1], st[p].x, im);
-                h[p][q] = V2{re, im};
+            for (int q = 0; q < 4; ++q) {
+              if constexpr (decltype(first)::value) {
+                h[p][q].x = pv[2 * q] * e[p].x;
+                h[p][q].y = pv[2 * q + 1] * e[p].x;
+              } else {
+                h[p][q].x = fma(pv[2 * q], e[p].x, h[p][q].x);
+                h[p][q].y = fma(pv[2 * q + 1], e[p].x, h[p][q].y);
               }
+              h[p][q].x = fma(pv[2 * q + 1], e[p].y, h[p][q].x);
+              h[p][q].y = fma(-pv[2 * q], e[p].y, h[p][q].y);
             }
-            j = jn - 3;
+          }
+        };
+        if (Hf == 0) {
+          single(std::true_type(), hs);
+        } else {
+          pair(std::true_type(), 0, hs);
+          // e_k = e_{k-1} E(d), two steps per iteration (alternating registers)
+          V2 e[kPix], f[kPix];
+#pragma unroll
+          for (int p = 0; p < kPix; ++p) e[p] = cmul<R>(hs[p], st[p]);
+          int k = 1;
+          for (; k + 1 < Hf; k += 2) {
+            pair(std::false_type(), k, e);
+#pragma unroll
+            for (int p = 0; p < kPix; ++p) f[p] = cmul<R>(e[p], st[p]);
+            pair(std::false_type(), k + 1, f);
+#pragma unroll
+            for (int p = 0; p < kPix; ++p) e[p] = cmul<R>(f[p], st[p]);
+          }
+          if (k < Hf) {
+            pair(std::false_type(), k, e);
+            if (n & 1) {
+#pragma unroll
+              for (int p = 0; p < kPix; ++p) f[p] = cmul<R>(e[p], st[p]);
+              single(std::false_type(), f);
+            }
+          } else if (n & 1) {
+            single(std::false_type(), e);
           }
         }
-        for (; j > j0; j -= 2) {
-          step(j);
-          step(j - 1);
-        }
-        const double fc = as_const(a.fc)[s.c0 + j0];
+        const double fcc = as_const(a.fc)[s.c0 + j0] + (H - 0.5) * s.dfc;
         V2 ph[kPix];
-        seed(ph, um * fc - u0, vm * fc - v0, wm * fc - s.w0, std::false_type());
+        seed(ph, um * fcc - u0, vm * fcc - v0, wm * fcc - s.w0, std::false_type());
 #pragma unroll
         for (int p = 0; p < kPix; ++p) {
 #pragma unroll
@@ -359,7 +417,7 @@ __global__ __launch_bounds__(kThreads) void grid_dft(const Group g) {
     // tapered and added to the group's image
 #pragma unroll
     for (int p = 0; p < kPix; ++p) {
-      const int pix = px[p].pix;
+      const int pix = chunk * kChunk + p * kThreads + lane;
       const V2* Ap = At + ((int64_t)s.ap * L * L + pix) * 4;
       const V2* Aq = At + ((int64_t)s.aq * L * L + pix) * 4;
       V2 a0 = Ap[0], a1 = Ap[1], a2 = Ap[2], a3 = Ap[3];
@@ -581,19 +639,14 @@ constexpr int kChanBlock = 32;
 // different banks for both the 16-byte stores and the strided loads.
 constexpr int kRedPitch = 68;
 
-// What a phasor seed needs of a subgrid pixel, kept in LDS (one entry per pixel of the
-// chunk, each read only by the lane that owns the pixel) rather than in registers.
-struct alignas(16) SeedPixel {
-  double n1;     // n - 1
-  float dx, dy;  // x - L/2, y - L/2
-};
 
 template <int L, typename R>
 constexpr size_t degrid_lds_bytes() {
   using D = DegridTune<L, R>;
   return (size_t)D::NT * D::P * sizeof(SeedPixel)               // the lanes' pixels
          + (size_t)(D::NT / 64) * 4 * kRedPitch * sizeof(R)     // per-wave reduction areas
-         + (size_t)2 * (D::NT / 64) * kChanBlock * 8 * sizeof(R);  // double-buffered stage
+         + (size_t)2 * (D::NT / 64) * kChanBlock * 8 * sizeof(R)  // double-buffered stage
+         + (size_t)D::NT * D::P * sizeof(typename C2<R>::T);     // the pixels' half steps
 }
 
 // Sum 16 per-lane values over the 64 lanes of a wave.  Two permlane swap levels in
@@ -638,10 +691,7 @@ __device__ __forceinline__ void corrected_pixel(const KernelArgs& a, const Subgr
                                                 const typename C2<R>::T* img, int pix,
                                                 typename C2<R>::T (&sp)[4], SeedPixel& px) {
   using V2 = typename C2<R>::T;
-  const int x = pix % L, y = pix / L;
-  const double l = (x - L / 2) * a.lstep, m = (y - L / 2) * a.lstep;
-  const double r2 = l * l + m * m;
-  px = {-r2 / (1.0 + sqrt(1.0 - r2)), (float)(x - L / 2), (float)(y - L / 2)};
+  px = pixel_at<L>(pix, a.lstep);
   const V2* At = reinterpret_cast<const V2*>(a.aterms);
   const V2* Ap = At + ((int64_t)s.ap * L * L + pix) * 4;
   const V2* Aq = At + ((int64_t)s.aq * L * L + pix) * 4;
@@ -798,6 +848,7 @@ __attribute__((amdgpu_waves_per_eu(DegridTune<L, R>::W))) void degrid_dft(const 
   SeedPixel* pxt = reinterpret_cast<SeedPixel*>(smem_raw);           // [CH]
   R* red = reinterpret_cast<R*>(smem_raw + CH * sizeof(SeedPixel));  // [NW][4][kRedPitch]
   R* stage = red + NW * 4 * kRedPitch;                               // [2][NW][kChanBlock][8]
+  V2* hst = reinterpret_cast<V2*>(stage + 2 * NW * kChanBlock * 8);  // [P][NT]
   const int wave = threadIdx.x >> 6, ln = threadIdx.x & 63;
   R* area = red + wave * 4 * kRedPitch;
   const int64_t local = degrid_slot(blockIdx.x, g.total_sg);
@@ -812,10 +863,10 @@ __attribute__((amdgpu_waves_per_eu(DegridTune<L, R>::W))) void degrid_dft(const 
     return;
   }
   const double u0 = (s.U0 - a.N / 2) * a.du, v0 = (s.V0 - a.N / 2) * a.du;
-  // channels per FP32 recurrence run: even (runs start at even channel offsets; a
-  // sub-table without a common channel spacing takes the direct form)
-  const int Rs = s.R & ~1;
-  // the value this lane owns after reduce16: channel offset (0 or 1) and component
+  // recurrence runs of the rows (a sub-table without a common channel spacing takes the
+  // direct form); the result of a run's padding channel is dropped
+  const int M = run_length(s.nc, s.R);
+  // the value this lane owns after reduce16, and whether it stores it
   const int vidx = 4 * (ln >> 4) + ((ln & 15) >> 2);
   const bool owner = (ln & 3) == 0;
   int buf = 0;
@@ -913,42 +964,113 @@ __attribute__((amdgpu_waves_per_eu(DegridTune<L, R>::W))) void degrid_dft(const 
       }
       continue;
     }
-    // Recurrence form: per row, the phasor steps along the channels by
-    // exp(-2 pi i dfc (um l + vm m + wm n1)) and is re-seeded from FP64 every Rs
-    // channels; two channels per step (a row of odd length ends on a second channel
-    // whose result is dropped)
+    // Recurrence form, channels paired about the run centre: with E(x) = exp(2 pi i x),
+    // theta_c the phase at the run's centre frequency and d the per-channel phase step,
+    // channel H + k of the run sees X E((k + 1/2) d) and channel H - 1 - k sees
+    // X E(-(k + 1/2) d), where X = S' E(theta_c).  So with e_k = E((k + 1/2) d), the
+    // sums A = sum X Re e_k and B = sum X Im e_k (real multipliers: 16 FMA per pixel for
+    // two visibilities) give both, A + iB and A - iB, and e_k steps by E(d) (the phasor
+    // recurrence of Sec. 3.2, Degridder, taken outward from the centre in both
+    // directions at once).  E(theta_c) is seeded from FP64 per run, E(d / 2) per row.
     for (int t = 0; t < s.nt; ++t) {
       const_view<double> uvw = as_const(a.uvw + 3 * (s.uvw0 + t));
       const double um = uvw[0], vm = uvw[1], wm = uvw[2];
-      V2 st[P], cur[P];
-      seed(st, um * s.dfc, vm * s.dfc, wm * s.dfc, std::true_type());
-      // the row's first origin before its loop, so that no phasor value reaches the loop
-      // from an earlier row or chunk (the compiler would otherwise keep cur live, and
-      // spilled, across the whole chunk loop)
-      seed(cur, um * as_const(a.fc)[s.c0] - u0, vm * as_const(a.fc)[s.c0] - v0,
-           wm * as_const(a.fc)[s.c0] - s.w0, std::false_type());
-      int since = 0;  // channels since the last FP64 seed
-      for (int cb0 = 0; cb0 < s.nc; cb0 += kChanBlock) {
-        const int cbn = min(kChanBlock, s.nc - cb0);
-        R* stg = stage + (buf * NW + wave) * kChanBlock * 8;
-        for (int j = cb0; j < cb0 + cbn; j += 2) {
-          if (since >= Rs) {
-            const double fc = as_const(a.fc)[s.c0 + j];
-            seed(cur, um * fc - u0, vm * fc - v0, wm * fc - s.w0, std::false_type());
-            since = 0;
-          }
-          since += 2;
-          V2 nxt[P];
+      V2 st[P];  // E(d)
+      {
+        V2 hs[P];  // E(d / 2), the first e_k of every run, kept in the lane's LDS entries
+        seed(hs, 0.5 * um * s.dfc, 0.5 * vm * s.dfc, 0.5 * wm * s.dfc, std::true_type());
 #pragma unroll
-          for (int p = 0; p < P; ++p) nxt[p] = cmul<R>(cur[p], st[p]);
-          const R val = pair_value(cur, nxt);
-#pragma unroll
-          for (int p = 0; p < P; ++p) cur[p] = cmul<R>(nxt[p], st[p]);
-          const int jc = j - cb0 + (vidx >> 3);
-          if (owner && j + (vidx >> 3) < s.nc) stg[jc * 8 + (vidx & 7)] = val;
+        for (int p = 0; p < P; ++p) {
+          hst[p * NT + threadIdx.x] = hs[p];
+          st[p] = unit_step(cmul<R>(hs[p], hs[p]));
         }
-        R* vrow = vis + (s.vis0 + (int64_t)t * a.nc_total + cb0) * 8;
-        flush_block(cbn, [&](int jc) { return vrow + jc * 8; });
+      }
+      R* vrow = vis + (s.vis0 + (int64_t)t * a.nc_total) * 8;
+      for (int j0 = 0; j0 < s.nc; j0 += M) {
+        const int je = min(s.nc, j0 + M), H = (je - j0 + 1) / 2;
+        const double fcc = as_const(a.fc)[s.c0 + j0] + (H - 0.5) * s.dfc;
+        V2 X[P][4];
+        {
+          V2 ec[P];
+          seed(ec, um * fcc - u0, vm * fcc - v0, wm * fcc - s.w0, std::false_type());
+#pragma unroll
+          for (int p = 0; p < P; ++p)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) X[p][q] = cmul<R>(sp[p][q], ec[p]);
+        }
+        V2 e[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+          int ix = p * NT + threadIdx.x;
+          asm volatile("" : "+v"(ix));
+          e[p] = hst[ix];
+        }
+        for (int k0 = 0; k0 < H; k0 += kChanBlock / 2) {
+          const int kn = min(kChanBlock / 2, H - k0);
+          R* stg = stage + (buf * NW + wave) * kChanBlock * 8;
+          // A (values 0-7) and B (8-15) of the lane's pixels for phasors e, reduced
+          auto pair_sym = [&](const V2 (&e)[P]) -> R {
+            R part[16];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              part[2 * q] = X[0][q].x * e[0].x;
+              part[2 * q + 1] = X[0][q].y * e[0].x;
+              part[8 + 2 * q] = X[0][q].x * e[0].y;
+              part[8 + 2 * q + 1] = X[0][q].y * e[0].y;
+            }
+#pragma unroll
+            for (int p = 1; p < P; ++p) {
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                part[2 * q] = fma(X[p][q].x, e[p].x, part[2 * q]);
+                part[2 * q + 1] = fma(X[p][q].y, e[p].x, part[2 * q + 1]);
+                part[8 + 2 * q] = fma(X[p][q].x, e[p].y, part[8 + 2 * q]);
+                part[8 + 2 * q + 1] = fma(X[p][q].y, e[p].y, part[8 + 2 * q + 1]);
+              }
+            }
+            return reduce16<R>(part, ln, area);
+          };
+          // two pairs per iteration, the phasor steps alternating between e and f
+          int k = 0;
+          for (; k + 1 < kn; k += 2) {
+            V2 f[P];
+            const R v0 = pair_sym(e);
+#pragma unroll
+            for (int p = 0; p < P; ++p) f[p] = cmul<R>(e[p], st[p]);
+            const R v1 = pair_sym(f);
+#pragma unroll
+            for (int p = 0; p < P; ++p) e[p] = cmul<R>(f[p], st[p]);
+            if (owner) {
+              stg[k * 16 + vidx] = v0;
+              stg[(k + 1) * 16 + vidx] = v1;
+            }
+          }
+          if (k < kn) {
+            const R v0 = pair_sym(e);
+#pragma unroll
+            for (int p = 0; p < P; ++p) e[p] = cmul<R>(e[p], st[p]);
+            if (owner) stg[k * 16 + vidx] = v0;
+          }
+          // the waves' A and B of the block's pairs, summed in wave order, combined
+          // into the two channels of each pair and added to the output
+          __syncthreads();
+          const R* sb = stage + buf * NW * kChanBlock * 8;
+          for (int i = threadIdx.x; i < kn * 16; i += NT) {
+            const int slot = i >> 4, hi = (i >> 3) & 1, comp = i & 7, im = comp & 1;
+            const int jj = j0 + (hi ? H + k0 + slot : H - 1 - k0 - slot);
+            if (jj >= je) continue;  // padding channel of a run of odd length
+            const int ia = slot * 16 + comp, ib = slot * 16 + 8 + (comp ^ 1);
+            R va = sb[ia], vb = sb[ib];
+#pragma unroll
+            for (int w = 1; w < NW; ++w) {
+              va = va + sb[w * kChanBlock * 8 + ia];
+              vb = vb + sb[w * kChanBlock * 8 + ib];
+            }
+            // channel H + k: A + iB; channel H - 1 - k: A - iB
+            store_vis(vrow + jj * 8, comp, hi == im ? va + vb : va - vb, s.fold != 0, chunk != 0);
+          }
+          buf ^= 1;
+        }
       }
     }
   }
@@ -965,7 +1087,7 @@ int launch_one(KernelClass k, const Group& g, hipStream_t st, int max_nv) {
   const unsigned n = (unsigned)(k == kDegridDft ? g.total_sg : g.total_grp);
   switch (k) {
     case kGridDft:
-      hipLaunchKernelGGL((grid_dft<L, R>), dim3((n + kXcds - 1) / kXcds * kXcds * ((L * L) / kChunk)),
+      hipLaunchKernelGGL((grid_dft<L, R>), dim3((n + kXcds - 1) / kXcds * kXcds * ((L * L) / (kThreads * GridTune<R>::PIX))),
                          dim3(kThreads), (size_t)max_nv * 8 * sizeof(R), st, g);
       break;
     case kFftAdd:
