@@ -1129,16 +1129,17 @@ int32_t degrid_form(const Geometry& g, int nt, int nc, bool uniform) {
     default: break;
   }
   // Automatic: the recurrence or the direct form, whichever has the smaller modelled
-  // cost per subgrid pixel, in units of one visibility of the recurrence (16 FMA, the
-  // phasor step and a share of the reduction).  The recurrence pays per row two seeded
-  // phasors and the block bookkeeping (kRow) and pads odd rows to even; the direct form
-  // pays one seeded phasor per visibility (kDirect) and pads an odd sub-table.  Both
-  // constants are fits to the degridder's times on the MWA-like observation with every
-  // k-th channel kept (k = 1 ... 96, L = 32, 64, 96): a row costs about two
-  // visibilities, a directly seeded visibility 1.9 to 2.0.  So rows of one channel take
-  // the direct form at about half the cost, rows of two or three channels break even
-  // and longer rows keep the recurrence.  The per-visibility form measured slower than
-  // the direct form at every occupancy and is never chosen automatically.
+  // cost per subgrid pixel: the recurrence pays per visibility of its rows (odd rows
+  // padded to even) and a fixed cost per row (kRow visibilities: the row's seeded
+  // phasors and block bookkeeping), the direct form kDirect per visibility (one seeded
+  // phasor each; an odd sub-table padded).  On the MWA-like observation with every k-th
+  // channel kept (k = 1 ... 96, L = 32, 64, 96), fits of the degridder's times put a
+  // directly seeded visibility at 3.5 to 4.6 visibilities of the paired recurrence and a
+  // run at 4 to 13.  By those fits the constants below choose within 2 % of the best
+  // pair on a grid over both, and the automatic choice measured within 1 % of the faster
+  // single form, or faster, at every k.  Rows of one to three channels take the direct
+  // form.  The per-visibility form measured slower than the direct form at every
+  // occupancy and is never chosen automatically.
   constexpr double kRow = 2.0, kDirect = 1.95;
   const double recur = (double)nt * ((nc + (nc & 1)) + kRow);
   const double direct = kDirect * (nv + (nv & 1));
