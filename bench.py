@@ -29,14 +29,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Algorithmic work per (visibility, subgrid pixel): the 2x2 complex multiply-
-# accumulate is 16 FP32 FMAs, the phasor step ph <- ph * step is 4 FP32 ops
-# (2 mul + 2 FMA); each occupies one FMA issue slot, counted as 2 FLOP.  The
-# degridder executes exactly this form.  The gridder evaluates each row's channel
-# sum by Horner's rule (h <- h step + V_j: 16 FMA per pair, no separate phasor step),
-# so it executes 32 FLOP per pair; its rate is reported at both counts.
+# Algorithmic work per (visibility, subgrid pixel) in the method's form: the 2x2
+# complex multiply-accumulate is 16 FP32 FMAs, the phasor step ph <- ph * step is 4
+# FP32 ops (2 mul + 2 FMA); each occupies one FMA issue slot, counted as 2 FLOP: 40.
+# Both kernels pair a recurrence run's channels symmetrically about its centre, so
+# two visibilities take 16 FMA per pixel with real multipliers and one complex phasor
+# step (6 FLOP): 19 FLOP per (visibility, pixel) executed.  Rates are reported at both
+# counts.
 FLOP_PER_VP = 40
-FLOP_PER_VP_EXECUTED = {"grid_dft": 32, "degrid_dft": 40}
+FLOP_PER_VP_EXECUTED = {"grid_dft": 19, "degrid_dft": 19}
 # FP32 vector peak of MI355X: 256 CUs x 4 SIMDs x 2.4 GHz, each SIMD issuing up to
 # two wave64 VALU instructions per 4 cycles (gfx950 VALU dual issue, counted by
 # SQ_ACTIVE_INST_VALU2) = 128 FMA per clock per CU = 157.3 TFLOP/s at 2 FLOP/FMA.
@@ -645,15 +646,15 @@ def dataclasses_replace(obj, **kw):
 
 
 def path_roofline(kt, wall_s):
-    """Sustained rate of the whole timed step: both DFT kernels' executed FLOP (32 per
-    vp for the Horner gridder, 40 for the degridder) over the wall time, which also
-    covers the FFTs, the adder, the splitter and the zeroing kernels."""
+    """Sustained rate of the whole timed step: both DFT kernels' executed FLOP (19 per
+    vp in the paired-channel form) over the wall time, which also covers the FFTs, the
+    adder, the splitter and the zeroing kernels."""
     flop = sum(kt[k]["vis_pixels"] * FLOP_PER_VP_EXECUTED[k] for k in ("grid_dft", "degrid_dft"))
     achieved = flop / wall_s / 1e12
     return {"achieved": round(achieved, 3), "peak": round(PEAK_FP32_TFLOPS, 1), "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-            "scope": "grid_dft (32 FLOP per vp) + degrid_dft (40) executed FLOP over the wall time of the "
-                     "timed steps"}
+            "scope": "grid_dft + degrid_dft executed FLOP (19 per vp each, paired-channel form) over the "
+                     "wall time of the timed steps"}
 
 
 # Rates of the survey's roofline definition: FP32 FMA at the dual-issue peak, FP64 FMA at
@@ -778,6 +779,8 @@ def main():
                 "peak": round(PEAK_FP32_TFLOPS, 1), "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": measured_traffic(dom),
                 "frac_of_single_issue": round(achieved / PEAK_FP32_SINGLE_ISSUE_TFLOPS, 4),
+                "frac_executed": round(k["vis_pixels"] * FLOP_PER_VP_EXECUTED[dom] / (k["ms"] * 1e-3) / 1e12
+                                       / PEAK_FP32_TFLOPS, 4),
                 "avg_launch_ms": round(k["ms"] / max(k["launches"], 1), 4),
                 "launches": k["launches"]}
     else:

@@ -5,15 +5,16 @@
 // with one scratch image slot per group.
 //
 // Gridding of a batch (Sec. 2.5 imaging, steps 2a-2c):
-//   grid_dft   one workgroup per (1024-pixel chunk, group); each lane owns 4
-//              subgrid pixels.  For every subgrid of the group the visibilities
-//              are staged in LDS and read by wave broadcast; per row and block of
-//              R channels, H = sum_k V_{j0+k} step^k is evaluated by Horner's rule
-//              (4 FMA per polarisation per visibility and pixel) and multiplied by
-//              the block's phasor, seeded from an FP64 phase origin reduced to a
-//              quarter turn and an FP32 polynomial sin/cos (Eq. withw).  The
-//              subgrid's T (-1)^(x+y) A_p^H S A_q (Sec. 3.3) is added into the
-//              group's image slot.
+//   grid_dft   one workgroup per (pixel chunk, group); each lane owns 4 subgrid
+//              pixels (2 in FP64) of the chunk.  For every subgrid of the group the
+//              visibilities are staged in LDS, paired within each row's recurrence
+//              runs of at most R channels (sums and differences of the two channels
+//              symmetric about the run's centre), and read by wave broadcast; per run
+//              the pairs are weighted by the real and imaginary parts of the phasor
+//              steps outward from the centre (4 FMA per polarisation per pair and
+//              pixel) and the sum multiplied by the phasor at the centre, seeded from
+//              an FP64 phase reduced to a quarter turn (Eq. withw).  The subgrid's
+//              T (-1)^(x+y) A_p^H S A_q (Sec. 3.3) is added into the group's image slot.
 //   fft_add    one workgroup per (polarisation, group): Stockham FFT of the L x L
 //              plane in LDS (radix 4/2/3), then (-1)^(a+b) and an atomic add onto
 //              the group's window of its w-layer (Eq. shiftback).
@@ -23,16 +24,18 @@
 //   degrid_dft one workgroup per subgrid; lanes own P pixels each and apply
 //              T (-1)^(x+y) A_p S A_q^H to the group image once per pixel chunk.
 //              The plan picks one of three forms per subgrid (Sec. 3.2, Degridder:
-//              the design chosen by subgrid occupancy).  Recurrence: per row the
-//              phasor steps along the channels (re-seeded from FP64 every R);
-//              direct: every visibility's phasor seeded from FP64 (short rows);
-//              in both, for each pair of visibilities every lane forms its pixels'
-//              partial sums (16 floats) and a wave-wide transpose-reduction
-//              (permlane32/permlane16 swaps, a per-wave LDS area, DPP) leaves each lane
-//              with one finished value; the waves' values are staged in LDS and added
-//              to the output in wave order (deterministic, no atomics).  Per
-//              visibility: lanes own visibilities and walk the corrected image in LDS
-//              (Eq. degridder).
+//              the design chosen by subgrid occupancy).  Recurrence: per row and
+//              run of at most R channels, the image times the run's centre phasor
+//              (seeded from FP64) is weighted by the real and imaginary parts of the
+//              phasor steps outward from the centre, which gives the two channels
+//              symmetric about it at once; direct: every visibility's phasor seeded
+//              from FP64 (short rows); in both, for each pair of visibilities every
+//              lane forms its pixels' partial sums (16 floats) and a wave-wide
+//              transpose-reduction (permlane32/permlane16 swaps, a per-wave LDS area,
+//              DPP) leaves each lane with one finished value; the waves' values are
+//              staged in LDS and added to the output in wave order (deterministic, no
+//              atomics).  Per visibility: lanes own visibilities and walk the
+//              corrected image in LDS (Eq. degridder).
 // A Stokes-I plan (npol = 1) keeps one grid plane: grid_dft adds (XX + YY) / 2 of the
 // corrected image and fft_add transforms that plane only; split_ifft stores the group
 // image as I [[1, 0], [0, 1]], which degrid_dft reads like any other.
@@ -203,13 +206,14 @@ __device__ __forceinline__ int run_length(int nc, int R) {
   return 2 * ((nc + 2 * nr - 1) / (2 * nr));
 }
 
-// Phasors of the (de)gridder: exp(2 pi i theta) with the phase theta in turns.  A phase
-// origin (used once per block of channels) comes from the transcendental unit; a
-// recurrence step, which the channel recurrence raises to powers up to R, from the
-// Taylor form, scaled to unit magnitude: the unit's error varies smoothly with the
+// Phasors of the (de)gridder: exp(2 pi i theta) with the phase theta in turns.  A run's
+// centre phasor (used once per run of channels) comes from the transcendental unit;
+// the half step, which the channel recurrence raises to odd powers up to R - 1, from
+// the Taylor form, scaled to unit magnitude: the unit's error varies smoothly with the
 // angle, so pixels with nearby step angles share it and k steps add it up coherently
-// (measured on the MWA-like workload at R = 32: 7.9e-7 normwise against 3.0e-7 with
-// Taylor steps), where the Taylor form's FP32 rounding is uncorrelated between pixels.
+// (measured on the MWA-like workload at R = 32 with the earlier one-sided recurrence:
+// 7.9e-7 normwise against 3.0e-7 with Taylor steps), where the Taylor form's FP32
+// rounding is uncorrelated between pixels.
 __device__ __forceinline__ float2 tphasor(double theta, float) { return phasor_turns(theta); }
 __device__ __forceinline__ double2 tphasor(double theta, double) { return phasor(theta, 0.0); }
 __device__ __forceinline__ float2 sphasor(double theta, float) { return unit_step(phasor(theta, 0.0f)); }
