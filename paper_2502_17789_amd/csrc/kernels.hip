@@ -301,7 +301,8 @@ void grid_dft(const Group g) {
     // e_k = E((k + 1/2) d): the run's channels H + k and H - 1 - k add
     // V_hi e_k + V_lo conj(e_k) = P Re e_k + Q Im e_k (real multipliers: 16 FMA per
     // pixel for two visibilities) to H_run, and e_k steps by E(d) outward from the
-    // centre (the phasor recurrence of Sec. 3.2, Gridder, in both directions at once).
+    // centre in both directions at once (a recurrence along the channels in place of the
+    // per-visibility sine and cosine of Sec. 3.2).
     // H_run times E(theta_c), the phasor at the run's centre frequency seeded from FP64,
     // goes into the accumulator.
     const double u0 = (s.U0 - a.N / 2) * a.du, v0 = (s.V0 - a.N / 2) * a.du;
@@ -973,9 +974,10 @@ __attribute__((amdgpu_waves_per_eu(DegridTune<L, R>::W))) void degrid_dft(const 
     // channel H + k of the run sees X E((k + 1/2) d) and channel H - 1 - k sees
     // X E(-(k + 1/2) d), where X = S' E(theta_c).  So with e_k = E((k + 1/2) d), the
     // sums A = sum X Re e_k and B = sum X Im e_k (real multipliers: 16 FMA per pixel for
-    // two visibilities) give both, A + iB and A - iB, and e_k steps by E(d) (the phasor
-    // recurrence of Sec. 3.2, Degridder, taken outward from the centre in both
-    // directions at once).  E(theta_c) is seeded from FP64 per run, E(d / 2) per row.
+    // two visibilities) give both, A + iB and A - iB, and e_k steps by E(d) outward from
+    // the centre in both directions at once (a recurrence along the channels in place of
+    // the per-visibility sine and cosine of Sec. 3.2).  E(theta_c) is seeded from FP64
+    // per run, E(d / 2) per row.
     for (int t = 0; t < s.nt; ++t) {
       const_view<double> uvw = as_const(a.uvw + 3 * (s.uvw0 + t));
       const double um = uvw[0], vm = uvw[1], wm = uvw[2];
