@@ -32,7 +32,7 @@ import time
 
 import numpy as np
 
-from . import DIR_DEGRID, DIR_GRID, FP32, Executor, Geometry, Plan, footprint
+from . import AIDG_E_NOMEM, DIR_DEGRID, DIR_GRID, FP32, AidgError, Executor, Geometry, Plan, footprint
 
 
 @dataclasses.dataclass
@@ -125,20 +125,35 @@ class GpuBackend:
             x = x() if callable(x) else x
             return x if isinstance(x, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(x)).to(cdt).cuda()
 
+        def retried(fn):
+            # The library allocates its plans outside torch's caching allocator, so free
+            # blocks that torch keeps (outputs of retired jobs) can hold memory that
+            # admission counted as free, and freed plan memory returns to the device at
+            # the next synchronisation.  On an out-of-memory error both are given back
+            # and the allocation is tried once more.
+            try:
+                return fn()
+            except (AidgError, torch.OutOfMemoryError) as e:
+                if isinstance(e, AidgError) and e.status != AIDG_E_NOMEM:
+                    raise
+                torch.cuda.synchronize()
+                torch.cuda.empty_cache()
+                return fn()
+
         with torch.cuda.stream(self.upload):
-            A = device(job.aterms)
-            plan = Plan(g, job.n_stations, job.baselines, job.uvw, job.freqs, A.contiguous(),
-                        table=job.table, stream=self.upload)
+            A = retried(lambda: device(job.aterms))
+            plan = retried(lambda: Plan(g, job.n_stations, job.baselines, job.uvw, job.freqs,
+                                        A.contiguous(), table=job.table, stream=self.upload))
             del A   # the plan holds its own copy
             if callable(job.data):   # a factory gets the shape the plan expects
-                x = job.data(plan.grid_shape() if job.direction == "degrid" else plan.vis_shape())
-                data = device(x)
+                shape = plan.grid_shape() if job.direction == "degrid" else plan.vis_shape()
+                data = retried(lambda: device(job.data(shape)))
             else:
-                data = device(job.data)
+                data = retried(lambda: device(job.data))
             if job.direction == "grid":
-                out = torch.zeros(plan.grid_shape(), dtype=cdt, device="cuda")
+                out = retried(lambda: torch.zeros(plan.grid_shape(), dtype=cdt, device="cuda"))
             else:
-                out = torch.empty(plan.vis_shape(), dtype=cdt, device="cuda")
+                out = retried(lambda: torch.empty(plan.vis_shape(), dtype=cdt, device="cuda"))
             ready = torch.cuda.Event()
             ready.record(self.upload)
         self.compute.wait_event(ready)
