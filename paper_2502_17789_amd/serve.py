@@ -91,6 +91,22 @@ def plan_geometry(job: Job) -> Geometry:
     return g
 
 
+def retry_out_of_memory(fn, torch):
+    """fn(), tried once more after an out-of-memory error from the library (status
+    NOMEM) or from torch.  The library allocates its plans outside torch's caching
+    allocator, so free blocks that torch keeps (outputs of retired jobs) can hold memory
+    that admission counted as free, and freed plan memory returns to the device at the
+    next synchronisation: both are given back before the second try."""
+    try:
+        return fn()
+    except (AidgError, torch.OutOfMemoryError) as e:
+        if isinstance(e, AidgError) and e.status != AIDG_E_NOMEM:
+            raise
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        return fn()
+
+
 def job_footprint_estimate(job: Job) -> int:
     """Device bytes a job holds while admitted: its plan (the library's host estimate,
     aidg_footprint_estimate: A-terms, tables, subgrid records, workspace), its grid and
@@ -126,19 +142,7 @@ class GpuBackend:
             return x if isinstance(x, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(x)).to(cdt).cuda()
 
         def retried(fn):
-            # The library allocates its plans outside torch's caching allocator, so free
-            # blocks that torch keeps (outputs of retired jobs) can hold memory that
-            # admission counted as free, and freed plan memory returns to the device at
-            # the next synchronisation.  On an out-of-memory error both are given back
-            # and the allocation is tried once more.
-            try:
-                return fn()
-            except (AidgError, torch.OutOfMemoryError) as e:
-                if isinstance(e, AidgError) and e.status != AIDG_E_NOMEM:
-                    raise
-                torch.cuda.synchronize()
-                torch.cuda.empty_cache()
-                return fn()
+            return retry_out_of_memory(fn, torch)
 
         with torch.cuda.stream(self.upload):
             A = retried(lambda: device(job.aterms))

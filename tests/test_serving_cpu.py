@@ -313,3 +313,54 @@ def test_footprint_layers_and_subgrids_on_the_mwa_observation(L, K):
         assert 0.9 <= f["n_groups"] / centres <= 1.6, (f["n_groups"], centres)
         assert f["n_excluded"] == 0
         assert t1 - t0 < 0.2 * (t2 - t1)
+
+
+class _FakeCuda:
+    def __init__(self):
+        self.calls = []
+
+    def synchronize(self):
+        self.calls.append("synchronize")
+
+    def empty_cache(self):
+        self.calls.append("empty_cache")
+
+
+class _FakeTorch:
+    class OutOfMemoryError(RuntimeError):
+        pass
+
+    def __init__(self):
+        self.cuda = _FakeCuda()
+
+
+def test_out_of_memory_retried_once():
+    """An allocation that fails for memory is tried once more after the caches are given
+    back; other library errors and a second failure propagate."""
+    from paper_2502_17789_amd import AIDG_E_INVALID, AIDG_E_NOMEM, AidgError
+    from paper_2502_17789_amd.serve import retry_out_of_memory
+
+    for err in (AidgError(AIDG_E_NOMEM, "device allocation failed"), _FakeTorch.OutOfMemoryError("oom")):
+        t = _FakeTorch()
+        tries = []
+
+        def fn():
+            tries.append(1)
+            if len(tries) == 1:
+                raise err
+            return "plan"
+
+        assert retry_out_of_memory(fn, t) == "plan"
+        assert len(tries) == 2 and t.cuda.calls == ["synchronize", "empty_cache"]
+
+    t = _FakeTorch()
+    with pytest.raises(AidgError):
+        retry_out_of_memory(lambda: (_ for _ in ()).throw(AidgError(AIDG_E_INVALID, "bad")), t)
+    assert t.cuda.calls == []
+
+    def always():
+        raise AidgError(AIDG_E_NOMEM, "still no memory")
+    t = _FakeTorch()
+    with pytest.raises(AidgError):
+        retry_out_of_memory(always, t)
+    assert t.cuda.calls == ["synchronize", "empty_cache"]
