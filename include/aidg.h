@@ -90,7 +90,10 @@ typedef struct {
                               < 0 a single layer at w0 = 0 */
   double taper_beta;       /* Kaiser-Bessel beta; 0 selects pi K / 4 */
   int32_t precision;       /* AIDG_FP32 (FP32 phasors/accumulation, FP64 phase origins) or AIDG_FP64 */
-  int32_t reseed_channels; /* FP32 phasor recurrence re-seeded from FP64 every R channels; 0 = 32 */
+  int32_t reseed_channels; /* R: each row's channels form runs of at most R (rounded down to
+                              even; R = 1: every channel alone) whose phasors are seeded
+                              from FP64 at the run's centre and stepped outward in FP32;
+                              0 = 32 */
   int32_t strict_range;    /* 0: unplaceable visibilities are excluded (grid ignores them,
                               degrid writes 0); 1: plan creation fails with AIDG_E_RANGE */
   int32_t max_subgrid_vis; /* cap on visibilities per subgrid, 0 = 1024, at most 2048
@@ -137,14 +140,14 @@ typedef struct {
                               least modelled cost (the direct form for rows of a few
                               channels, the recurrence for longer ones).
                               AIDG_DEGRID_RECURRENCE (1): lanes own subgrid pixels, the
-                              phasors step along each row's channels (FP64-seeded every
-                              reseed_channels) and each visibility is a cross-lane
-                              reduction; sub-tables without a common channel spacing take
-                              the direct form.  AIDG_DEGRID_PER_VIS (2): lanes own
-                              visibilities, every (visibility, pixel) phase is formed in
-                              FP64, for sub-tables of at most 256 visibilities (128 at
-                              L = 32 in FP32), the recurrence for larger ones (the paper's
-                              "natural" thread-per-visibility design).
+                              phasors step outward from the centre of each run of
+                              reseed_channels (FP64-seeded there) and each pair of
+                              visibilities is a cross-lane reduction; sub-tables without a
+                              common channel spacing take the direct form.
+                              AIDG_DEGRID_PER_VIS (2): lanes own visibilities, every
+                              (visibility, pixel) phase is formed in FP64, for sub-tables
+                              of at most 256 visibilities, the recurrence for larger ones
+                              (the paper's "natural" thread-per-visibility design).
                               AIDG_DEGRID_DIRECT (3): lanes own subgrid pixels and every
                               visibility's phasor is seeded from FP64 (no recurrence) */
   int32_t reserved;        /* 0 */
