@@ -2,12 +2,12 @@
 // Sec. 2.5 imaging step 3) and its adjoint for prediction (Eq. wunstack, prediction
 // step 2).  A centred N x N transform is two passes of one-dimensional FFTs along
 // rows with a tiled transpose between them:
-//   image_fft_rows  one workgroup per row: the row is read into LDS times (-1)^x,
-//                   transformed by mixed-radix Stockham passes (radix 4/2/3/5;
-//                   FP32 twiddles computed, FP64 ones from a table), and written
-//                   back times (-1)^k.  The
-//                   prediction variant first multiplies each image value by
-//                   exp(-2 pi i w0 n1) / (L^2 T).
+//   image_fft_rows  one workgroup per row: the row times (-1)^x is transformed by
+//                   mixed-radix Stockham passes through LDS (radix 4/2/3/5; FP32
+//                   twiddles computed, FP64 ones from a table; the last pass writes
+//                   global memory) and written back times
+//                   (-1)^k.  The prediction variant first multiplies each image
+//                   value by exp(-2 pi i w0 n1) / (L^2 T).
 //   image_transpose 32 x 32 tiles through LDS.
 //   image_wstack    a transposing tile pass that adds one layer's transform times
 //                   exp(+2 pi i w0 n1) / (L^2 T) into the image (or stores it, for
@@ -44,10 +44,15 @@ __device__ __forceinline__ float2 root_of_unity(int a, int M, float inv_m) {
 // earlier radices): butterfly j < N/R reads buf[j + i N/R], multiplies input i by
 // exp(DIR 2 pi i k i / (Ls R)) with k = j mod Ls, and writes its outputs to
 // buf[(j / Ls) Ls R + k + i Ls].  In place: every read, a barrier, every write.
+// The last pass hands its outputs to store(k) instead (coalesced: the last pass has
+// j / Ls = 0), which saves the row's separate store pass through LDS and its barrier.
+// (Reading the first pass's inputs from global memory as well raised the kernel's
+// registers from 53 to over 100, with spills in the prediction variant.)
 // FP32 twiddles are computed (root_of_unity for the first, products for its powers);
 // FP64 ones come from the table.
-template <int R, int DIR, typename V2>
-__device__ __forceinline__ void row_pass(V2* buf, int N, int Ls, const V2* __restrict__ tw) {
+template <int R, int DIR, bool LAST, typename V2, typename Store>
+__device__ __forceinline__ void row_pass(V2* buf, int N, int Ls, const V2* __restrict__ tw,
+                                         const Store& store) {
   using Rt = decltype(V2{}.x);
   constexpr int MAXB = (kMaxImageN / R + kFftThreads - 1) / kFftThreads;
   const int m = N / R, tstep = N / (Ls * R), M = Ls * R;
@@ -89,28 +94,42 @@ __device__ __forceinline__ void row_pass(V2* buf, int N, int Ls, const V2* __res
       butterfly<V2, R, DIR>(y[b]);
     }
   }
-  __syncthreads();
+  // LDS reads before LDS writes (the last pass writes global memory only)
+  if constexpr (!LAST) __syncthreads();
 #pragma unroll
   for (int b = 0; b < MAXB; ++b) {
     const int j = threadIdx.x + b * kFftThreads;
     if (j < m) {
       const int k = kk[b], base = gg[b] * Ls * R + k;
 #pragma unroll
-      for (int i = 0; i < R; ++i) buf[base + i * Ls] = y[b][i];
+      for (int i = 0; i < R; ++i) {
+        if constexpr (LAST) store(base + i * Ls, y[b][i]);
+        else buf[base + i * Ls] = y[b][i];
+      }
     }
   }
-  __syncthreads();
+  if constexpr (!LAST) __syncthreads();
 }
 
-template <int DIR, typename V2>
-__device__ __forceinline__ void row_fft(V2* buf, const ImageRadices& fr, int N, const V2* tw) {
+template <int R, int DIR, typename V2, typename Store>
+__device__ __forceinline__ void row_pass_at(bool last, V2* buf, int N, int Ls, const V2* tw,
+                                            const Store& store) {
+  if (last) row_pass<R, DIR, true>(buf, N, Ls, tw, store);
+  else row_pass<R, DIR, false>(buf, N, Ls, tw, store);
+}
+
+// The transform of the row held in LDS; store(k, v) takes output k.
+template <int DIR, typename V2, typename Store>
+__device__ __forceinline__ void row_fft(V2* buf, const ImageRadices& fr, int N, const V2* tw,
+                                        const Store& store) {
   int Ls = 1;
   for (int p = 0; p < fr.n; ++p) {
     const int r = fr.r[p];
-    if (r == 4) row_pass<4, DIR>(buf, N, Ls, tw);
-    else if (r == 2) row_pass<2, DIR>(buf, N, Ls, tw);
-    else if (r == 3) row_pass<3, DIR>(buf, N, Ls, tw);
-    else row_pass<5, DIR>(buf, N, Ls, tw);
+    const bool last = p == fr.n - 1;
+    if (r == 4) row_pass_at<4, DIR>(last, buf, N, Ls, tw, store);
+    else if (r == 2) row_pass_at<2, DIR>(last, buf, N, Ls, tw, store);
+    else if (r == 3) row_pass_at<3, DIR>(last, buf, N, Ls, tw, store);
+    else row_pass_at<5, DIR>(last, buf, N, Ls, tw, store);
     Ls *= r;
   }
 }
@@ -155,20 +174,15 @@ __global__ __launch_bounds__(kFftThreads) void image_fft_rows(const typename C2<
   V2* buf = reinterpret_cast<V2*>(smem_raw);
   const int row = blockIdx.x;
   const V2* s = src + (size_t)row * N;
+  V2* d = dst + (size_t)row * N;
   for (int x = threadIdx.x; x < N; x += kFftThreads) {
     V2 v = s[x];
     if constexpr (PREDICT) v = cmul<R>(v, wterm<R>(x, row, N, dl, w0, itaper, inv_l2, -1.0));
-    if (x & 1) v = V2{-v.x, -v.y};
-    buf[x] = v;
+    buf[x] = (x & 1) ? V2{-v.x, -v.y} : v;
   }
   __syncthreads();
-  row_fft<DIR>(buf, fr, N, tw);
-  V2* d = dst + (size_t)row * N;
-  for (int k = threadIdx.x; k < N; k += kFftThreads) {
-    V2 v = buf[k];
-    if (k & 1) v = V2{-v.x, -v.y};
-    d[k] = v;
-  }
+  auto store = [&](int k, V2 v) { d[k] = (k & 1) ? V2{-v.x, -v.y} : v; };
+  row_fft<DIR>(buf, fr, N, tw, store);
 }
 
 // dst[x][y] = src[y][x] over 32 x 32 tiles (grid ceil(N/32) x ceil(N/32), 256 threads).
