@@ -169,6 +169,8 @@ def parse():
     ap.add_argument("--lattice-cases", type=lambda t: tuple(int(x) for x in t.split(":")), nargs="*",
                     default=[], help="extra FP32 kernel-sweep cases L:lattice (centre lattice step)")
     ap.add_argument("--lattice-only", action="store_true", help="kernel sweep: only the --lattice-cases")
+    ap.add_argument("--sweep-reseed", type=int, nargs="*", default=[],
+                    help="kernel sweep: extra FP32 L = 96 cases at these re-seed intervals R")
     ap.add_argument("--degrid-forms", type=int, nargs="+", default=[0],
                     help="kernel sweep: degridder forms to run (0 automatic, 1 recurrence, 2 per visibility, "
                          "3 direct)")
@@ -475,7 +477,7 @@ def precision_study(args):
             torch.cuda.empty_cache()
 
 
-def _kernel_case(aidg, wl, prec, L, lattice=0, form=0, reps=2):
+def _kernel_case(aidg, wl, prec, L, lattice=0, form=0, reps=2, reseed=0):
     """Kernel times of one plan of the observation `wl` at subgrid size L (K = L/4):
     HIP events around every launch, mean of `reps` grid + degrid calls after a
     warm-up.  Returns the JSON record of the case."""
@@ -488,7 +490,7 @@ def _kernel_case(aidg, wl, prec, L, lattice=0, form=0, reps=2):
     n_int = (wl.n_times + wl.aterm_interval - 1) // wl.aterm_interval
     A = A.expand(n_int, -1, -1, -1, -1).contiguous().to(cdt)
     geo = aidg.Geometry(wl.grid_size, L, L // 4, wl.pixel_scale, aterm_interval=wl.aterm_interval,
-                        precision=prec, center_lattice=lattice, degrid_form=form)
+                        precision=prec, center_lattice=lattice, degrid_form=form, reseed_channels=reseed)
     gen = torch.Generator(device="cuda")
     with aidg.Plan(geo, wl.n_stations, wl.baselines, wl.uvw, wl.freqs, A) as plan:
         del A
@@ -516,6 +518,7 @@ def _kernel_case(aidg, wl, prec, L, lattice=0, form=0, reps=2):
         "subgrid_size": L, "kernel_support": L // 4, "center_lattice": lattice or "auto",
         "precision": "fp32" if prec == aidg.FP32 else "fp64",
         "degrid_form": ("auto", "recurrence", "per_vis", "direct")[form],
+        "reseed_channels": reseed or 32,
         "n_vis": n, "n_chans": int(wl.n_chans), "n_subgrids": info["n_subgrids"], "n_groups": info["n_groups"],
         "n_subgrids_pervis": info["n_subgrids_pervis"], "n_subgrids_direct": info["n_subgrids_direct"],
         "mean_vis_per_subgrid": round(n / max(info["n_subgrids"], 1), 1),
@@ -544,6 +547,10 @@ def kernel_sweep(args):
         for form in args.degrid_forms:
             rec = _kernel_case(aidg, wl, prec, L, lattice, form)
             print(json.dumps({"kernel_sweep": rec}), flush=True)
+    # the speed side of the re-seed interval (the precision side is --precision)
+    for R in args.sweep_reseed:
+        rec = _kernel_case(aidg, wl, aidg.FP32, 96, 0, 0, reseed=R)
+        print(json.dumps({"kernel_sweep": rec}), flush=True)
 
 
 def occupancy_sweep(args):
