@@ -192,21 +192,24 @@ def test_edge_cases(aidg, orc, name):
     assert np.abs(Vg[mask == 0]).max(initial=0.0) == 0.0
 
 
+@pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("R", [1, 2, 3, 5, 8, 32])
-def test_reseed_intervals(aidg, orc, R):
+def test_reseed_intervals(aidg, orc, R, precision):
     """Recurrence runs for re-seeding intervals from one channel up: rows of 23 channels
     split into runs of one channel (R = 1), of two, or of balanced even lengths with a
-    ragged last run of odd length; grid and degrid against the oracle."""
+    ragged last run of odd length; grid and degrid against the oracle, FP32 and FP64."""
     wl = synth.config_tiny(206, n_st=4, n_t=5, n_c=23)
     table = orc.partition(wl, 0.0)
     rng = np.random.default_rng(13)
     V = synth.random_vis((wl.n_baselines, wl.n_times, wl.n_chans), rng)
     G = synth.random_grid(orc.n_layers(table), wl.grid_size, rng)
-    with plan_for(aidg, wl, table, reseed_channels=R, degrid_form=aidg.DEGRID_RECURRENCE) as p:
-        Gg = host(p.grid(dev(V, 0)))
-        Vg = host(p.degrid(dev(G, 0)))
-    check_grid(Gg, orc.grid(wl, V, table), 1e-5, f"R={R} grid")
-    check_vis(Vg, orc.degrid(wl, G, table), 1e-5, f"R={R} degrid")
+    tol = 1e-5 if precision == 0 else 1e-10
+    with plan_for(aidg, wl, table, precision=precision, reseed_channels=R,
+                  degrid_form=aidg.DEGRID_RECURRENCE) as p:
+        Gg = host(p.grid(dev(V, precision)))
+        Vg = host(p.degrid(dev(G, precision)))
+    check_grid(Gg, orc.grid(wl, V, table), tol, f"R={R} grid")
+    check_vis(Vg, orc.degrid(wl, G, table), tol, f"R={R} degrid")
 
 
 def test_nonuniform_channels_and_split_subgrids(aidg, orc):
